@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of batched SPHINCS+ signing on one MI355X.
+
+One step = one slh_sign_batch call over the whole batch (prelude, FORS,
+TREE and WOTS kernels), inputs and outputs resident in HBM.  Prints one
+JSON line.  Default workload: SPHINCS+-SHA2-128f, one key, 4096 random
+32-byte messages; --all also times the 192f (1 key) and 256f (64 keys)
+batch-4096 workloads, reported under "extra".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "c2_128f_4096": "SPHINCS+-SHA2-128f, 1 key, 4096 x 32-byte messages",
+    "c3_192f_4096": "SPHINCS+-SHA2-192f, 1 key, 4096 x 32-byte messages",
+    "c4_256f_4096x64": "SPHINCS+-SHA2-256f, 64 keys, 4096 x 32-byte messages",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(slh, workloads, name):
+    import numpy as np
+    import torch
+    cfg = workloads.CONFIGS[name]
+    param, batch = cfg["param"], cfg["batch"]
+    ctx = slh.Context(0)
+    slots = []
+    for i in range(cfg["keys"]):
+        pk, sk = slh.keygen(param, workloads.key_seed(param, i))
+        slots.append(ctx.add_keys(param, sk))
+    if cfg["keys"] > 1:
+        kidx = workloads.key_assignment(cfg["cfg"], batch, cfg["keys"])
+    else:
+        kidx = [0] * batch
+    msgs = workloads.messages(cfg["cfg"], batch, cfg["length"])
+    items, blob, total = slh.pack_batch([param] * batch, [slots[k] for k in kidx], msgs)
+    d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+    d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    return ctx, items, d_m, d_s, cfg, msgs, kidx
+
+
+def run(slh, workloads, name, steps, warmup):
+    import torch
+    ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.sign_batch(items, d_m, d_s, stream=stream)
+    torch.cuda.synchronize()
+    ctx.phase_times(reset=True)
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ctx.sign_batch(items, d_m, d_s, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile(False)
+    phases = ctx.phase_times(reset=True)
+    ctx.close()
+    elapsed = t1 - t0
+    return {
+        "elapsed": elapsed,
+        "ms_per_step": 1000.0 * elapsed / steps,
+        "sig_per_s": cfg["batch"] * steps / elapsed,
+        "phases": phases,
+        "cfg": cfg,
+    }
+
+
+def cpu_baseline(name, workloads, seconds=15.0):
+    """The oracle, as it stands, on the host cores: sign messages of the same
+    workload in a thread pool for about `seconds`."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    cfg = workloads.CONFIGS[name]
+    param = cfg["param"]
+    p = oracle.params(workloads.NAME_OF[param])
+    pk, sk = oracle.keygen(p, workloads.key_seed(param, 0))
+    msgs = workloads.messages(cfg["cfg"], cfg["batch"], cfg["length"])
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(16, cores))
+    done = 0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        while time.perf_counter() - t0 < seconds and done < len(msgs):
+            chunk = msgs[done:done + threads]
+            list(ex.map(lambda m: oracle.sign(p, m, sk), chunk))
+            done += len(chunk)
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "signatures/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d messages of the %s workload, key 0, %d host threads, %.1f s"
+                      % (done, name, threads, el)}
+
+
+def roofline(param, res):
+    from paper_2512_23969_amd import accounting as acc
+    ms, launches, msgs = res["phases"]["tree"]
+    if launches == 0:
+        return None
+    per_launch_msgs = msgs / launches
+    ops_per_launch = acc.ops_per_signature(param, "tree") * per_launch_msgs
+    avg_s = ms / launches / 1000.0
+    achieved = ops_per_launch / avg_s / 1e12
+    peak = acc.VALU_PEAK_OPS / 1e12
+    return {"bound": "alu", "kernel": "k_tree", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(ms / launches, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2_128f_4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--all", action="store_true", help="also time the 192f and 256f workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (calibrates HBM counters)")
+    args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        src = torch.ones(args.copy_calib, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calib, "launches": 3}), flush=True)
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: signing shards by message with no exchange, "
+              "and this build measures the single-GPU kernel (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    from paper_2512_23969_amd import accounting as acc
+    from paper_2512_23969_amd import slh, workloads
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("bench: workload", args.workload)
+    res = run(slh, workloads, args.workload, args.steps, args.warmup)
+    param = res["cfg"]["param"]
+    c256, c512 = acc.compressions_per_signature(param)
+    line = {
+        "metric": "signatures/s (SPHINCS+-SHA2-%s, batch %d)" % (workloads.NAME_OF[param], res["cfg"]["batch"]),
+        "value": round(res["sig_per_s"], 1),
+        "unit": "signatures/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded random keys and 32-byte messages)",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "batch": res["cfg"]["batch"], "keys": res["cfg"]["keys"], "msg_bytes": 32,
+                   "mode": "plain"},
+        "compressions_per_s": {"sha256": round(res["sig_per_s"] * c256, 0),
+                               "sha512": round(res["sig_per_s"] * c512, 0)},
+        "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param) / acc.VALU_PEAK_OPS, 4),
+        "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items()},
+        "roofline": roofline(param, res),
+    }
+    if args.all:
+        extra = {}
+        for name in ("c3_192f_4096", "c4_256f_4096x64"):
+            if name == args.workload:
+                continue
+            log("bench: workload", name)
+            steps_c = max(3, args.steps // 2)
+            r = run(slh, workloads, name, steps_c, args.warmup)
+            prm = r["cfg"]["param"]
+            extra[name] = {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
+                           "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
+                           "roofline": roofline(prm, r),
+                           "phase_ms_per_step": {k: round(v[0] / steps_c, 3)
+                                                 for k, v in r["phases"].items()}}
+        line["extra"] = extra
+    if not args.no_cpu:
+        log("bench: cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(args.workload, workloads, args.cpu_seconds)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,170 @@
+/*
+ * slh.h -- C ABI of the MI355X (gfx950) batched SPHINCS+ signing library.
+ *
+ * What the library computes.  SPHINCS+ signature generation as accelerated by
+ * the HERO-Sign paper (arXiv 2512.23969): its Section II-A describes the
+ * scheme (WOTS+, FORS, XMSS trees, hypertree), Table 1 the -f parameter sets
+ * and the Fig. 2 listing the signing flow.  The exact arithmetic is that of
+ * FIPS 205 (SLH-DSA) with the SHA2 "simple" tweakable hashes (FIPS 205
+ * Section 11.2): keygen is slh_keygen_internal (Algorithm 18), signing is
+ * slh_sign_internal (Algorithm 19) with opt_rand = PK.seed (deterministic
+ * signing, no context prefix: the raw message M is signed), verification is
+ * slh_verify_internal (Algorithm 20).
+ *
+ * Parameter sets (the paper's Table 1):
+ *   SLH_SHA2_128F  n=16 h=66 d=22 a=6 k=33 w=16   signature 17088 bytes
+ *   SLH_SHA2_192F  n=24 h=66 d=22 a=8 k=33 w=16   signature 35664 bytes
+ *   SLH_SHA2_256F  n=32 h=68 d=17 a=9 k=35 w=16   signature 49856 bytes
+ *
+ * Byte encodings are those of FIPS 205:
+ *   seed = SK.seed | SK.prf | PK.seed                 (3n bytes)
+ *   pk   = PK.seed | PK.root                          (2n bytes)
+ *   sk   = SK.seed | SK.prf | PK.seed | PK.root       (4n bytes)
+ *   sig  = R | SIG_FORS | SIG_HT                      (sizes above)
+ *
+ * Conventions.
+ *   - Return value: SLH_OK (0) or a negative error code.  Arguments are
+ *     validated on the host before anything is launched; on SLH_EINVAL
+ *     nothing has been written.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are device
+ *     memory of the context's GPU (for example torch tensors' data_ptr()).
+ *   - The caller owns every buffer it passes.  The library keeps no caller
+ *     pointer after a call's work has completed on its stream.
+ *   - Calls that take a stream enqueue their GPU work on it and return
+ *     without waiting; results are ready when the stream has reached the
+ *     point of the call.  Calls on one context are serialised by the
+ *     library across streams.
+ *   - A context is not thread safe: one host thread at a time per context.
+ */
+#ifndef SLH_H
+#define SLH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLH_SHA2_128F 1u
+#define SLH_SHA2_192F 2u
+#define SLH_SHA2_256F 3u
+
+#define SLH_OK 0
+#define SLH_EINVAL (-1)  /* bad parameter set, slot, size, offset or null pointer */
+#define SLH_ENOMEM (-2)  /* device memory could not be obtained within the budget */
+#define SLH_EDEVICE (-3) /* a HIP call failed; slh_last_error() has the text      */
+#define SLH_EBUSY (-4)   /* admission refused (serving queue full)               */
+
+/* Sizes of a parameter set. */
+typedef struct {
+    uint32_t n;          /* security parameter, bytes */
+    uint32_t h, d, hp;   /* hypertree height, layers, XMSS tree height h/d */
+    uint32_t a, k;       /* FORS tree height, number of FORS trees */
+    uint32_t len;        /* WOTS+ chains per key (len1 + len2) */
+    uint32_t m;          /* digest bytes taken from H_msg */
+    uint32_t seed_bytes; /* 3n */
+    uint32_t pk_bytes;   /* 2n */
+    uint32_t sk_bytes;   /* 4n */
+    uint32_t sig_bytes;  /* n (1 + k (a + 1) + h + d len) */
+} slh_sizes;
+
+/* One signing request of a batch (32 bytes, host memory).
+ *   param     parameter set of the request; must equal the key slot's set
+ *   key_slot  slot returned by slh_ctx_add_keys
+ *   msg_off   byte offset of the message in the batch's message buffer
+ *   msg_len   message length in bytes (any length, 0 allowed)
+ *   sig_off   byte offset of the signature in the batch's signature buffer;
+ *             must be a multiple of 16 */
+typedef struct {
+    uint32_t param;
+    uint32_t key_slot;
+    uint64_t msg_off;
+    uint64_t msg_len;
+    uint64_t sig_off;
+} slh_item;
+
+typedef struct slh_ctx slh_ctx;
+
+/* Execution modes of slh_sign_batch.  Every mode produces the same bytes. */
+#define SLH_MODE_PLAIN 0u  /* per-phase kernels launched one after another */
+
+/* Fill *out with the sizes of parameter set `param`.
+ * Errors: SLH_EINVAL for an unknown set or a null pointer. */
+int slh_params(uint32_t param, slh_sizes *out);
+
+/* Create a signing context on GPU `device`.  `hbm_budget` caps the bytes of
+ * working memory the context keeps on the device (0 = default of 8 GiB);
+ * larger batches are processed in chunks that fit.
+ * Errors: SLH_EINVAL (null out, bad device), SLH_EDEVICE. */
+int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx **out);
+
+/* Release a context and all its device memory.  Waits for its pending work.
+ * A null context is accepted and ignored. */
+int slh_ctx_destroy(slh_ctx *ctx);
+
+/* Text of the last error recorded on the context (never null; owned by the
+ * context, valid until its next call).  A null context gives the text of
+ * the last error of the context-free calls of the calling thread. */
+const char *slh_last_error(const slh_ctx *ctx);
+
+/* Key generation (Algorithm 18) on the current GPU.  Host pointers:
+ *   seed  3n bytes SK.seed | SK.prf | PK.seed   (input)
+ *   pk    2n bytes                               (output)
+ *   sk    4n bytes                               (output)
+ * Synchronous.  Errors: SLH_EINVAL, SLH_ENOMEM, SLH_EDEVICE. */
+int slh_keygen(uint32_t param, const uint8_t *seed, uint8_t *pk, uint8_t *sk);
+
+/* Copy `count` secret keys (host, count * 4n bytes, each SK.seed | SK.prf |
+ * PK.seed | PK.root) of parameter set `param` into the context's device key
+ * table and derive their per-key hash state.  Their slots are
+ * *first_slot ... *first_slot + count - 1.  Synchronous.
+ * Errors: SLH_EINVAL, SLH_ENOMEM, SLH_EDEVICE. */
+int slh_ctx_add_keys(slh_ctx *ctx, uint32_t param, const uint8_t *sks, uint32_t count,
+                     uint32_t *first_slot);
+
+/* Sign a batch (Algorithm 19 per request, deterministic).
+ *   items       host array of `count` requests (any mix of parameter sets)
+ *   msgs        device buffer holding the messages, msgs_bytes long
+ *   sigs        device buffer receiving the signatures, sigs_bytes long,
+ *               16-byte aligned
+ *   mode        SLH_MODE_*
+ *   stream      hipStream_t to enqueue on (null = the default stream)
+ * Every item must satisfy msg_off + msg_len <= msgs_bytes and
+ * sig_off + sig_bytes(param) <= sigs_bytes; signature ranges must not
+ * overlap.  count == 0 is a no-op.
+ * Errors: SLH_EINVAL, SLH_ENOMEM, SLH_EDEVICE. */
+int slh_sign_batch(slh_ctx *ctx, const slh_item *items, uint32_t count, const uint8_t *msgs,
+                   uint64_t msgs_bytes, uint8_t *sigs, uint64_t sigs_bytes, uint32_t mode,
+                   void *stream);
+
+/* Verify one signature (Algorithm 20) on the current GPU.  Host pointers.
+ * Returns 1 if valid, 0 if not (including a wrong sig_len), negative on
+ * error (SLH_EINVAL, SLH_ENOMEM, SLH_EDEVICE).  Synchronous. */
+int slh_verify(uint32_t param, const uint8_t *msg, size_t msg_len, const uint8_t *sig,
+               size_t sig_len, const uint8_t *pk);
+
+/* Kernel phases of the signing path, for per-phase timing. */
+#define SLH_PHASE_PRELUDE 0 /* PRF_msg, H_msg, index split           */
+#define SLH_PHASE_FORS 1    /* FORS trees, auth paths, FORS pk       */
+#define SLH_PHASE_TREE 2    /* WOTS+ chains, leaves, XMSS roots/auth */
+#define SLH_PHASE_WOTS 3    /* WOTS+ signatures of the signing leaves */
+#define SLH_NPHASES 4
+
+/* Turn per-phase timing on or off for later slh_sign_batch calls.  When on,
+ * the library records a HIP event before and after every kernel it
+ * launches, on the caller's stream (the paper reports per-kernel throughput
+ * in its Table 8; this is the same measurement).  Errors: SLH_EINVAL. */
+int slh_ctx_profile(slh_ctx *ctx, int enable);
+
+/* Accumulated GPU time per phase since the last reset.  Host arrays of
+ * SLH_NPHASES entries: ms[i] milliseconds, launches[i] kernel launches,
+ * messages[i] messages processed.  Waits for the recorded events.  reset != 0
+ * clears the totals.  Errors: SLH_EINVAL, SLH_EDEVICE. */
+int slh_ctx_phase_times(slh_ctx *ctx, double *ms, uint64_t *launches, uint64_t *messages,
+                        int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,95 @@
+"""Work accounting of the signing path: hash compressions per signature and
+per kernel, and the algorithmic 32-bit VALU operations they stand for.
+
+Counts follow from the parameter sets (the paper's Table 1) and the SHA2
+instantiation of the tweakable hashes: after the per-key PK.seed block,
+F and PRF take one SHA-256 compression; H takes one SHA-256 (n = 16) or
+SHA-512 (n >= 24) compression; T_l takes ceil((22 + l n + pad) / block)
+compressions.  The paper gives the per-leaf figures 560 / 816 / 1072
+(Section III-C) and the leaf counts (Section III-B) these reproduce.
+
+Algorithmic VALU operations per compression (gfx950 instruction set, one
+instruction per primitive of FIPS 180-4, no precomputation):
+  SHA-256: round = Sigma1 (3 rotates + 1 xor3) + Ch + Sigma0 (3 + 1) + Maj
+           + 4 three-input adds = 14; schedule word = 2 x (2 rotates +
+           1 shift + 1 xor3) + 2 adds = 10; feed-forward 8.
+           64 * 14 + 48 * 10 + 8 = 1384.
+  SHA-512: on 32-bit lanes every 64-bit rotate, xor3, Ch, Maj is 2
+           instructions and every 64-bit add 2 (add + carry):
+           round = 8 + 8 + 2 + 2 + 7 adds * 2 = 34; schedule word = 8 + 8
+           + 3 adds * 2 = 22; feed-forward 16.
+           80 * 34 + 64 * 22 + 16 = 4144.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+OPS_SHA256 = 64 * 14 + 48 * 10 + 8
+OPS_SHA512 = 80 * 34 + 64 * 22 + 16
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock for 32-bit integer VALU
+# operations at the 2.4 GHz peak engine clock.
+CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
+VALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK_HZ   # 3.93e13 lane-ops/s
+
+
+@dataclass(frozen=True)
+class Params:
+    n: int
+    h: int
+    d: int
+    a: int
+    k: int
+
+    @property
+    def hp(self):
+        return self.h // self.d
+
+    @property
+    def len(self):
+        return 2 * self.n + 3
+
+    @property
+    def wide(self):
+        return self.n >= 24
+
+
+PARAMS = {1: Params(16, 66, 22, 6, 33), 2: Params(24, 66, 22, 8, 33), 3: Params(32, 68, 17, 9, 35)}
+
+
+def t_blocks(p: Params, l: int) -> int:
+    """Compressions of T_l after the PK.seed block."""
+    mb = 22 + l * p.n
+    if p.wide:
+        return (mb + 17 + 127) // 128
+    return (mb + 9 + 63) // 64
+
+
+def per_signature(param: int) -> dict:
+    """Compressions of one signature on the signing path, split by phase and
+    hash (no WOTS+ recomputation: the chain values are kept)."""
+    p = PARAMS[param]
+    leaves = p.d << p.hp
+    fors_leaves = p.k << p.a
+    c256 = {}
+    c512 = {}
+    c256["fors"] = 2 * fors_leaves + (0 if p.wide else (fors_leaves - p.k) + t_blocks(p, p.k))
+    c512["fors"] = ((fors_leaves - p.k) + t_blocks(p, p.k)) if p.wide else 0
+    chains = leaves * p.len * 16
+    tlen = leaves * t_blocks(p, p.len)
+    merkle = p.d * ((1 << p.hp) - 1)
+    c256["tree"] = chains + (0 if p.wide else tlen + merkle)
+    c512["tree"] = (tlen + merkle) if p.wide else 0
+    c256["wots"] = c512["wots"] = 0
+    return {"sha256": c256, "sha512": c512}
+
+
+def ops_per_signature(param: int, phase: str | None = None) -> int:
+    c = per_signature(param)
+    phases = [phase] if phase else list(c["sha256"])
+    return sum(c["sha256"][ph] * OPS_SHA256 + c["sha512"][ph] * OPS_SHA512 for ph in phases)
+
+
+def compressions_per_signature(param: int) -> tuple[int, int]:
+    c = per_signature(param)
+    return sum(c["sha256"].values()), sum(c["sha512"].values())

@@ -1,0 +1,499 @@
+// api.hip -- host side of the C ABI declared in include/slh.h.
+//
+// Validation, the device key table, the per-context working memory and the
+// launch sequence of one batch: prelude -> FORS and TREE -> WOTS, per
+// parameter set, in chunks that fit the context's memory budget.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/slh.h"
+#include "kernels.hpp"
+
+using namespace slh;
+
+namespace {
+
+thread_local std::string g_free_err;  // errors of the context-free calls
+
+struct Sizes {
+  uint32_t n, h, d, hp, a, k, len, m, sig;
+};
+bool sizes_of(uint32_t param, Sizes* s) {
+  switch (param) {
+    case SLH_SHA2_128F: *s = {16, 66, 22, 3, 6, 33, 35, 34, uint32_t(P<1>::sig_bytes)}; return true;
+    case SLH_SHA2_192F: *s = {24, 66, 22, 3, 8, 33, 51, 42, uint32_t(P<2>::sig_bytes)}; return true;
+    case SLH_SHA2_256F: *s = {32, 68, 17, 4, 9, 35, 67, 49, uint32_t(P<3>::sig_bytes)}; return true;
+    default: return false;
+  }
+}
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Working memory of one chunk of `c` messages of parameter set ID.
+template <int ID>
+struct Layout {
+  using Q = P<ID>;
+  static size_t tree_blocks(size_t c) {
+    const size_t trees = c * Q::d;
+    const size_t tpb = kLeavesPerBlock / Q::leaves;
+    return (trees + tpb - 1) / tpb;
+  }
+  static size_t recs(size_t c) { return up(c * sizeof(WorkRec)); }
+  static size_t items(size_t c) { return up(c * sizeof(DevItem)); }
+  static size_t stage(size_t c) { return up(tree_blocks(c) * Q::len * kLeavesPerBlock * Q::NW * 4); }
+  static size_t spill(size_t c) { return up(c * Q::d * Q::len * 16 * Q::NW * 4); }
+  static size_t total(size_t c) { return recs(c) + items(c) + stage(c) + spill(c); }
+};
+
+size_t per_message_bytes(uint32_t param) {
+  switch (param) {
+    case 1: return Layout<1>::total(1024) / 1024 + 1;
+    case 2: return Layout<2>::total(1024) / 1024 + 1;
+    default: return Layout<3>::total(1024) / 1024 + 1;
+  }
+}
+
+void be_words(const uint8_t* b, int nbytes, uint32_t* w) {
+  for (int i = 0; i < nbytes / 4; i++)
+    w[i] = (uint32_t(b[4 * i]) << 24) | (uint32_t(b[4 * i + 1]) << 16) | (uint32_t(b[4 * i + 2]) << 8) |
+           uint32_t(b[4 * i + 3]);
+}
+
+DevKey make_devkey(uint32_t param, uint32_t n, const uint8_t* sk_seed, const uint8_t* sk_prf,
+                   const uint8_t* pk_seed, const uint8_t* pk_root) {
+  DevKey K;
+  std::memset(&K, 0, sizeof K);
+  K.param = param;
+  K.n = n;
+  be_words(sk_seed, n, K.sk_seed);
+  be_words(sk_prf, n, K.sk_prf);
+  be_words(pk_seed, n, K.pk_seed);
+  if (pk_root) be_words(pk_root, n, K.pk_root);
+  return K;
+}
+
+}  // namespace
+
+struct slh_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  std::string err;
+  DevKey* keys = nullptr;
+  uint32_t nkeys = 0, cap = 0;
+  std::vector<uint32_t> key_param;
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  DevItem* staging = nullptr;  // pinned host copy of the items of a call
+  size_t staging_cap = 0;
+  hipEvent_t done = nullptr;   // end of the last call's GPU work
+  bool pending = false;
+  // optional per-phase timing: event pairs around every kernel launch
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Mark { int phase; size_t a, b; uint64_t units; };
+  std::vector<Mark> marks;
+  double phase_ms[SLH_NPHASES] = {0};
+  uint64_t phase_launches[SLH_NPHASES] = {0};
+  uint64_t phase_units[SLH_NPHASES] = {0};
+};
+
+namespace {
+
+int fail(slh_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_free_err = msg;
+  return code;
+}
+int hip_fail(slh_ctx* c, hipError_t e, const char* what) {
+  return fail(c, SLH_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHK(c, x)                                   \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #x); \
+  } while (0)
+
+// Timing of one launch: an event before and after it on the same stream.
+struct PhaseTimer {
+  slh_ctx* c;
+  hipStream_t s;
+  int phase;
+  uint64_t units;
+  size_t a = 0;
+  bool on;
+  PhaseTimer(slh_ctx* c_, hipStream_t s_, int phase_, uint64_t units_)
+      : c(c_), s(s_), phase(phase_), units(units_), on(c_->profile) {
+    if (on) a = take();
+  }
+  size_t take() {
+    if (c->ev_used == c->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return 0; }
+      c->ev_pool.push_back(e);
+    }
+    const size_t i = c->ev_used++;
+    (void)hipEventRecord(c->ev_pool[i], s);
+    return i;
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    const size_t b = take();
+    if (on) c->marks.push_back({phase, a, b, units});
+  }
+};
+
+// Make sure `bytes` of working memory are available (waits for pending work
+// before replacing the buffer).
+int ensure_ws(slh_ctx* c, size_t bytes) {
+  if (c->ws_bytes >= bytes) return SLH_OK;
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->ws) HIPCHK(c, hipFree(c->ws));
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  hipError_t e = hipMalloc(&c->ws, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SLH_ENOMEM, "hipMalloc of working memory failed");
+  }
+  c->ws_bytes = bytes;
+  return SLH_OK;
+}
+
+template <int ID>
+int launch_chunk(slh_ctx* c, const DevItem* h_items, size_t count, const uint8_t* msgs, uint8_t* sigs,
+                 hipStream_t s) {
+  using L = Layout<ID>;
+  using Q = P<ID>;
+  uint8_t* base = c->ws;
+  WorkRec* recs = reinterpret_cast<WorkRec*>(base);
+  DevItem* items = reinterpret_cast<DevItem*>(base + L::recs(count));
+  uint32_t* stage = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count));
+  uint32_t* spill = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count) + L::stage(count));
+  HIPCHK(c, hipMemcpyAsync(items, h_items, count * sizeof(DevItem), hipMemcpyHostToDevice, s));
+  const uint32_t n = uint32_t(count);
+  {
+    PhaseTimer t(c, s, SLH_PHASE_PRELUDE, n);
+    hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs,
+                       sigs, recs);
+  }
+  {
+    constexpr int S = ID == 1 ? 1 : (ID == 2 ? 2 : 3);
+    PhaseTimer t(c, s, SLH_PHASE_FORS, n);
+    hipLaunchKernelGGL((k_fors<ID, S>), dim3(n), dim3(kForsThreads), 0, s, c->keys, recs, n, sigs);
+  }
+  const uint32_t ntrees = n * Q::d;
+  {
+    PhaseTimer t(c, s, SLH_PHASE_TREE, n);
+    hipLaunchKernelGGL((k_tree<ID, false>), dim3(uint32_t(L::tree_blocks(count))), dim3(kTreeThreads), 0,
+                       s, c->keys, recs, ntrees, sigs, stage, spill, 0u, nullptr);
+  }
+  const uint32_t nw = n * Q::d * Q::len;
+  {
+    PhaseTimer t(c, s, SLH_PHASE_WOTS, n);
+    hipLaunchKernelGGL((k_wots<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, recs, n, sigs, spill);
+  }
+  HIPCHK(c, hipGetLastError());
+  return SLH_OK;
+}
+
+template <int ID>
+int sign_group(slh_ctx* c, const DevItem* h_items, size_t count, const uint8_t* msgs, uint8_t* sigs,
+               hipStream_t s) {
+  using L = Layout<ID>;
+  size_t chunk = c->budget / per_message_bytes(ID);
+  if (chunk < 1) chunk = 1;
+  chunk = std::min(chunk, count);
+  int rc = ensure_ws(c, L::total(chunk));
+  if (rc) return rc;
+  for (size_t off = 0; off < count; off += chunk) {
+    const size_t cnt = std::min(chunk, count - off);
+    rc = launch_chunk<ID>(c, h_items + off, cnt, msgs, sigs, s);
+    if (rc) return rc;
+  }
+  return SLH_OK;
+}
+
+}  // namespace
+
+namespace {
+template <int ID>
+int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
+  using Q = P<ID>;
+  const uint32_t n = Q::n;
+  DevKey hk = make_devkey(ID, n, seed, seed + n, seed + 2 * n, nullptr);
+  DevKey* dk = nullptr;
+  uint32_t* stage = nullptr;
+  uint32_t* root = nullptr;
+  const size_t stage_bytes = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
+  hipError_t e = hipMalloc(&dk, sizeof(DevKey));
+  if (e == hipSuccess) e = hipMalloc(&stage, stage_bytes);
+  if (e == hipSuccess) e = hipMalloc(&root, 32);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (dk) (void)hipFree(dk);
+    if (stage) (void)hipFree(stage);
+    return fail(nullptr, SLH_ENOMEM, "keygen device allocation failed");
+  }
+  uint32_t hroot[8] = {0};
+  e = hipMemcpy(dk, &hk, sizeof hk, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_key_midstates, dim3(1), dim3(64), 0, 0, dk, 0u, 1u);
+    hipLaunchKernelGGL((k_tree<ID, true>), dim3(1), dim3(kTreeThreads), 0, 0, dk, nullptr, 1u, nullptr,
+                       stage, nullptr, 0u, root);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(hroot, root, Q::n, hipMemcpyDeviceToHost);
+  (void)hipFree(dk);
+  (void)hipFree(stage);
+  (void)hipFree(root);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "keygen");
+  std::memcpy(sk, seed, 3 * n);
+  for (uint32_t i = 0; i < n / 4; i++) {
+    for (int b = 0; b < 4; b++) {
+      const uint8_t byte = uint8_t(hroot[i] >> (24 - 8 * b));
+      sk[3 * n + 4 * i + b] = byte;
+      pk[n + 4 * i + b] = byte;
+    }
+  }
+  std::memcpy(pk, seed + 2 * n, n);
+  return SLH_OK;
+}
+
+template <int ID>
+int verify_impl(const uint8_t* msg, size_t msg_len, const uint8_t* sig, const uint8_t* pk) {
+  using Q = P<ID>;
+  const size_t mbytes = std::max<size_t>(msg_len, 1);
+  const size_t total = up(sizeof(VerifyItem)) + up(mbytes) + up(Q::sig_bytes) + up(2 * Q::n) + up(sizeof(int));
+  uint8_t* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, total);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(nullptr, SLH_ENOMEM, "verify device allocation failed");
+  }
+  VerifyItem it{0, msg_len, 0, 0};
+  uint8_t* d_items = buf;
+  uint8_t* d_msg = d_items + up(sizeof(VerifyItem));
+  uint8_t* d_sig = d_msg + up(mbytes);
+  uint8_t* d_pk = d_sig + up(Q::sig_bytes);
+  int* d_res = reinterpret_cast<int*>(d_pk + up(2 * Q::n));
+  int res = -1;
+  e = hipMemcpy(d_items, &it, sizeof it, hipMemcpyHostToDevice);
+  if (e == hipSuccess && msg_len) e = hipMemcpy(d_msg, msg, msg_len, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_sig, sig, Q::sig_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_pk, pk, 2 * Q::n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((k_verify<ID>), dim3(1), dim3(kVerifyThreads), 0, 0,
+                       reinterpret_cast<const VerifyItem*>(d_items), 1u, d_msg, d_sig, d_pk, d_res);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(&res, d_res, sizeof res, hipMemcpyDeviceToHost);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "verify");
+  return res;
+}
+}  // namespace
+
+extern "C" {
+
+int slh_params(uint32_t param, slh_sizes* out) {
+  Sizes s;
+  if (!out || !sizes_of(param, &s)) return fail(nullptr, SLH_EINVAL, "unknown parameter set");
+  out->n = s.n; out->h = s.h; out->d = s.d; out->hp = s.hp; out->a = s.a; out->k = s.k;
+  out->len = s.len; out->m = s.m;
+  out->seed_bytes = 3 * s.n; out->pk_bytes = 2 * s.n; out->sk_bytes = 4 * s.n; out->sig_bytes = s.sig;
+  return SLH_OK;
+}
+
+int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
+  if (!out) return fail(nullptr, SLH_EINVAL, "null output pointer");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(nullptr, SLH_EINVAL, "no such device");
+  slh_ctx* c = new slh_ctx();
+  c->device = device;
+  c->budget = hbm_budget ? hbm_budget : (uint64_t(8) << 30);
+  e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "context set-up");
+  }
+  *out = c;
+  return SLH_OK;
+}
+
+int slh_ctx_destroy(slh_ctx* c) {
+  if (!c) return SLH_OK;
+  (void)hipSetDevice(c->device);
+  if (c->pending) (void)hipEventSynchronize(c->done);
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->keys) (void)hipFree(c->keys);
+  if (c->staging) (void)hipHostFree(c->staging);
+  if (c->done) (void)hipEventDestroy(c->done);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return SLH_OK;
+}
+
+const char* slh_last_error(const slh_ctx* c) { return c ? c->err.c_str() : g_free_err.c_str(); }
+
+int slh_ctx_profile(slh_ctx* c, int enable) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  c->profile = enable != 0;
+  return SLH_OK;
+}
+
+int slh_ctx_phase_times(slh_ctx* c, double* ms, uint64_t* launches, uint64_t* messages, int reset) {
+  if (!c || !ms || !launches || !messages) return fail(c, SLH_EINVAL, "null argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  for (const auto& m : c->marks) {
+    HIPCHK(c, hipEventSynchronize(c->ev_pool[m.b]));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev_pool[m.a], c->ev_pool[m.b]));
+    c->phase_ms[m.phase] += t;
+    c->phase_launches[m.phase] += 1;
+    c->phase_units[m.phase] += m.units;
+  }
+  c->marks.clear();
+  c->ev_used = 0;
+  for (int i = 0; i < SLH_NPHASES; i++) {
+    ms[i] = c->phase_ms[i];
+    launches[i] = c->phase_launches[i];
+    messages[i] = c->phase_units[i];
+    if (reset) { c->phase_ms[i] = 0; c->phase_launches[i] = 0; c->phase_units[i] = 0; }
+  }
+  return SLH_OK;
+}
+
+int slh_ctx_add_keys(slh_ctx* c, uint32_t param, const uint8_t* sks, uint32_t count, uint32_t* first_slot) {
+  Sizes s;
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (!sizes_of(param, &s)) return fail(c, SLH_EINVAL, "unknown parameter set");
+  if (!sks || !first_slot || count == 0) return fail(c, SLH_EINVAL, "null keys, null slot or zero count");
+  if (uint64_t(c->nkeys) + count > (1u << 24)) return fail(c, SLH_EINVAL, "too many keys");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->nkeys + count > c->cap) {
+    uint32_t ncap = std::max<uint32_t>(64, c->cap);
+    while (ncap < c->nkeys + count) ncap *= 2;
+    DevKey* nk = nullptr;
+    if (hipMalloc(&nk, size_t(ncap) * sizeof(DevKey)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "hipMalloc of the key table failed");
+    }
+    if (c->keys) {
+      HIPCHK(c, hipMemcpy(nk, c->keys, size_t(c->nkeys) * sizeof(DevKey), hipMemcpyDeviceToDevice));
+      HIPCHK(c, hipFree(c->keys));
+    }
+    c->keys = nk;
+    c->cap = ncap;
+  }
+  std::vector<DevKey> hk(count);
+  const uint32_t n = s.n;
+  for (uint32_t i = 0; i < count; i++) {
+    const uint8_t* k = sks + size_t(i) * 4 * n;
+    hk[i] = make_devkey(param, n, k, k + n, k + 2 * n, k + 3 * n);
+  }
+  HIPCHK(c, hipMemcpy(c->keys + c->nkeys, hk.data(), count * sizeof(DevKey), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_key_midstates, dim3((count + 63) / 64), dim3(64), 0, 0, c->keys, c->nkeys, count);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipDeviceSynchronize());
+  *first_slot = c->nkeys;
+  c->nkeys += count;
+  c->key_param.resize(c->nkeys, param);
+  return SLH_OK;
+}
+
+int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint8_t* msgs, uint64_t msgs_bytes,
+                   uint8_t* sigs, uint64_t sigs_bytes, uint32_t mode, void* stream) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (count == 0) return SLH_OK;
+  if (!items || !sigs) return fail(c, SLH_EINVAL, "null items or signature buffer");
+  if (mode != SLH_MODE_PLAIN) return fail(c, SLH_EINVAL, "unknown mode");
+  if (reinterpret_cast<uintptr_t>(sigs) % 16) return fail(c, SLH_EINVAL, "signature buffer not 16-byte aligned");
+  // validation, and grouping by parameter set
+  std::vector<std::pair<uint64_t, uint64_t>> ranges;
+  ranges.reserve(count);
+  size_t per[4] = {0, 0, 0, 0};
+  for (uint32_t i = 0; i < count; i++) {
+    const slh_item& it = items[i];
+    Sizes s;
+    if (!sizes_of(it.param, &s)) return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": unknown parameter set");
+    if (it.key_slot >= c->nkeys || c->key_param[it.key_slot] != it.param)
+      return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": key slot missing or of another parameter set");
+    if (it.msg_len > msgs_bytes || it.msg_off > msgs_bytes - it.msg_len)
+      return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": message outside the message buffer");
+    if (it.msg_len && !msgs) return fail(c, SLH_EINVAL, "null message buffer");
+    if (it.sig_off % 16) return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": signature offset not 16-byte aligned");
+    if (s.sig > sigs_bytes || it.sig_off > sigs_bytes - s.sig)
+      return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": signature outside the signature buffer");
+    ranges.emplace_back(it.sig_off, it.sig_off + s.sig);
+    per[it.param]++;
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); i++)
+    if (ranges[i].first < ranges[i - 1].second) return fail(c, SLH_EINVAL, "signature ranges overlap");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // the pinned staging copy of the items may still be read by the previous call
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->staging_cap < count) {
+    if (c->staging) HIPCHK(c, hipHostFree(c->staging));
+    c->staging = nullptr;
+    c->staging_cap = 0;
+    if (hipHostMalloc(&c->staging, size_t(count) * sizeof(DevItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "pinned staging allocation failed");
+    }
+    c->staging_cap = count;
+  }
+  size_t start[4] = {0, 0, per[1], per[1] + per[2]}, fill[4] = {0, 0, 0, 0};
+  for (uint32_t i = 0; i < count; i++) {
+    const slh_item& it = items[i];
+    DevItem& d = c->staging[start[it.param] + fill[it.param]++];
+    d.param = it.param; d.key_slot = it.key_slot; d.msg_off = it.msg_off; d.msg_len = it.msg_len;
+    d.sig_off = it.sig_off;
+  }
+  int rc = SLH_OK;
+  if (per[1] && !rc) rc = sign_group<1>(c, c->staging + start[1], per[1], msgs, sigs, s);
+  if (per[2] && !rc) rc = sign_group<2>(c, c->staging + start[2], per[2], msgs, sigs, s);
+  if (per[3] && !rc) rc = sign_group<3>(c, c->staging + start[3], per[3], msgs, sigs, s);
+  if (rc) return rc;
+  HIPCHK(c, hipEventRecord(c->done, s));
+  c->pending = true;
+  return SLH_OK;
+}
+
+
+int slh_keygen(uint32_t param, const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
+  if (!seed || !pk || !sk) return fail(nullptr, SLH_EINVAL, "null pointer");
+  switch (param) {
+    case SLH_SHA2_128F: return keygen_impl<1>(seed, pk, sk);
+    case SLH_SHA2_192F: return keygen_impl<2>(seed, pk, sk);
+    case SLH_SHA2_256F: return keygen_impl<3>(seed, pk, sk);
+    default: return fail(nullptr, SLH_EINVAL, "unknown parameter set");
+  }
+}
+
+int slh_verify(uint32_t param, const uint8_t* msg, size_t msg_len, const uint8_t* sig, size_t sig_len,
+               const uint8_t* pk) {
+  Sizes s;
+  if (!sizes_of(param, &s)) return fail(nullptr, SLH_EINVAL, "unknown parameter set");
+  if (!sig || !pk || (msg_len && !msg)) return fail(nullptr, SLH_EINVAL, "null pointer");
+  if (sig_len != s.sig) return 0;
+  switch (param) {
+    case SLH_SHA2_128F: return verify_impl<1>(msg, msg_len, sig, pk);
+    case SLH_SHA2_192F: return verify_impl<2>(msg, msg_len, sig, pk);
+    default: return verify_impl<3>(msg, msg_len, sig, pk);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,644 @@
+// kernels.hpp -- the HIP kernels of the batched signing path.
+//
+// One batch of messages of one parameter set is signed by four launches:
+//   k_prelude : one lane per message.  R = PRF_msg, digest = H_msg, FORS
+//               indices, idx_tree / idx_leaf  (FIPS 205 Algorithm 19 steps
+//               before fors_sign; the paper's Fig. 2 hash_message and
+//               message_to_indices).
+//   k_fors    : one workgroup per message builds all k FORS trees, writes the
+//               selected secret values and auth paths and the FORS public
+//               key (paper Section II-A "FORS Signature", Section III-B).
+//   k_tree    : one workgroup per 64 hypertree leaves (8 trees of 8 leaves or
+//               4 trees of 16 leaves, across messages and layers).  Lanes
+//               first run one WOTS+ chain each, then one lane per leaf runs
+//               T_len, then the leaves are reduced to the root in registers
+//               (paper Section III-A: every XMSS tree of every layer is
+//               independent once idx_tree and idx_leaf are known).
+//   k_wots    : one lane per WOTS+ chain of the signing leaves.  The TREE
+//               kernel kept every intermediate value of those chains, so the
+//               WOTS+ signature of layer j (a function of the FORS public key
+//               or of root j-1) is a gather, with no hashing.
+// The paper launches FORS_Sign and TREE_Sign concurrently and then
+// WOTS+_Sign (Section III-F); here the same dependency holds.
+#pragma once
+#include "slh_dev.hpp"
+
+namespace slh {
+
+constexpr int kTreeThreads = 256;   // 4 waves
+constexpr int kLeavesPerBlock = 64; // one wave's worth of leaves
+constexpr int kForsThreads = 256;
+
+// ------------------------------------------------------------------ keys
+// Chaining values after the PK.seed block, one lane per key.
+__global__ void k_key_midstates(DevKey* keys, uint32_t first, uint32_t count) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  DevKey& K = keys[first + i];
+  const int nw = int(K.n) / 4;
+  {
+    uint32_t st[8], w[16];
+    sha256_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++) w[j] = (j < 8 && j < nw) ? K.pk_seed[j] : 0u;
+    sha256_compress(st, w);
+#pragma unroll
+    for (int j = 0; j < 8; j++) K.mid256[j] = st[j];
+  }
+  {
+    u64p st[8], w[16];
+    sha512_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      uint32_t hi = (2 * j < nw && 2 * j < 8) ? K.pk_seed[2 * j] : 0u;
+      uint32_t lo = (2 * j + 1 < nw && 2 * j + 1 < 8) ? K.pk_seed[2 * j + 1] : 0u;
+      w[j] = u64p{hi, lo};
+    }
+    sha512_compress(st, w);
+#pragma unroll
+    for (int j = 0; j < 8; j++) { K.mid512[2 * j] = st[j].hi; K.mid512[2 * j + 1] = st[j].lo; }
+  }
+}
+
+// ------------------------------------------------------------------ prelude
+// Per-key values the message hashes need (a DevKey, or a verifier's copy).
+struct KeyView {
+  const uint32_t* sk_prf;
+  const uint32_t* pk_seed;
+  const uint32_t* pk_root;
+};
+
+// R = PRF_msg(SK.prf, opt_rand = PK.seed, M) = Trunc_n(HMAC-SHA-X(SK.prf, PK.seed | M))
+template <int ID>
+__device__ void prf_msg(const KeyView& K, const uint8_t* msg, uint64_t mlen, uint32_t* R) {
+  constexpr int NW = P<ID>::NW;
+  if constexpr (!P<ID>::wide) {
+    uint32_t st[8], blk[16];
+    sha256_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++) blk[j] = (j < NW ? K.sk_prf[j] : 0u) ^ 0x36363636u;
+    sha256_compress(st, blk);
+    sha256_stream<NW>(st, K.pk_seed, msg, mlen, 64);
+    uint32_t inner[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) inner[j] = st[j];
+    sha256_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++) blk[j] = (j < NW ? K.sk_prf[j] : 0u) ^ 0x5c5c5c5cu;
+    sha256_compress(st, blk);
+    sha256_stream<8>(st, inner, nullptr, 0, 64);
+#pragma unroll
+    for (int j = 0; j < NW; j++) R[j] = st[j];
+  } else {
+    u64p st[8], w[16];
+    sha512_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      w[j] = u64p{(2 * j < NW ? K.sk_prf[2 * j] : 0u) ^ 0x36363636u,
+                  (2 * j + 1 < NW ? K.sk_prf[2 * j + 1] : 0u) ^ 0x36363636u};
+    sha512_compress(st, w);
+    sha512_stream<NW>(st, K.pk_seed, msg, mlen, 128);
+    uint32_t inner[16];
+#pragma unroll
+    for (int j = 0; j < 8; j++) { inner[2 * j] = st[j].hi; inner[2 * j + 1] = st[j].lo; }
+    sha512_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      w[j] = u64p{(2 * j < NW ? K.sk_prf[2 * j] : 0u) ^ 0x5c5c5c5cu,
+                  (2 * j + 1 < NW ? K.sk_prf[2 * j + 1] : 0u) ^ 0x5c5c5c5cu};
+    sha512_compress(st, w);
+    sha512_stream<16>(st, inner, nullptr, 0, 128);
+#pragma unroll
+    for (int j = 0; j < NW; j++) R[j] = (j & 1) ? st[j >> 1].lo : st[j >> 1].hi;
+  }
+}
+
+// digest = H_msg(R, PK.seed, PK.root, M)
+//        = MGF1-SHA-X(R | PK.seed | SHA-X(R | PK.seed | PK.root | M), m)
+// (16 BE words; the first m bytes are meaningful)
+template <int ID>
+__device__ void h_msg(const KeyView& K, const uint32_t* R, const uint8_t* msg, uint64_t mlen,
+                      uint32_t digest[16]) {
+  constexpr int NW = P<ID>::NW;
+  uint32_t pre[3 * NW];
+#pragma unroll
+  for (int j = 0; j < NW; j++) { pre[j] = R[j]; pre[NW + j] = K.pk_seed[j]; pre[2 * NW + j] = K.pk_root[j]; }
+  if constexpr (!P<ID>::wide) {
+    uint32_t st[8];
+    sha256_iv(st);
+    sha256_stream<3 * NW>(st, pre, msg, mlen, 0);
+    uint32_t seed[2 * NW + 8 + 1];
+#pragma unroll
+    for (int j = 0; j < 2 * NW; j++) seed[j] = pre[j];
+#pragma unroll
+    for (int j = 0; j < 8; j++) seed[2 * NW + j] = st[j];
+    // MGF1-SHA-256: m = 34 bytes needs counters 0 and 1
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      seed[2 * NW + 8] = uint32_t(c);
+      uint32_t o[8];
+      sha256_words<2 * NW + 9>(seed, o);
+#pragma unroll
+      for (int j = 0; j < 8; j++) digest[8 * c + j] = o[j];
+    }
+  } else {
+    u64p st[8];
+    sha512_iv(st);
+    sha512_stream<3 * NW>(st, pre, msg, mlen, 0);
+    uint32_t seed[2 * NW + 16 + 1];
+#pragma unroll
+    for (int j = 0; j < 2 * NW; j++) seed[j] = pre[j];
+#pragma unroll
+    for (int j = 0; j < 8; j++) { seed[2 * NW + 2 * j] = st[j].hi; seed[2 * NW + 2 * j + 1] = st[j].lo; }
+    // MGF1-SHA-512: m <= 64 bytes needs counter 0 only
+    seed[2 * NW + 16] = 0u;
+    sha512_words<2 * NW + 17>(seed, digest);
+  }
+}
+
+// Split of the digest (FIPS 205 Algorithm 19): md -> k FORS indices of a
+// bits, most-significant bit first (base_2b); then idx_tree and idx_leaf.
+template <int ID>
+__device__ void split_digest(const uint32_t digest[16], uint16_t* indices, uint64_t* idx_tree,
+                             uint32_t* idx_leaf) {
+  using Q = P<ID>;
+  auto dbyte = [&](int b) -> uint32_t { return (digest[b >> 2] >> (24 - 8 * (b & 3))) & 0xFFu; };
+#pragma unroll
+  for (int t = 0; t < Q::k; t++) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < Q::a; j++) {
+      const int bit = t * Q::a + j;
+      v = (v << 1) | ((dbyte(bit >> 3) >> (7 - (bit & 7))) & 1u);
+    }
+    indices[t] = uint16_t(v);
+  }
+  uint64_t tree = 0;
+#pragma unroll
+  for (int j = 0; j < Q::tree_bytes; j++) tree = (tree << 8) | dbyte(Q::md_bytes + j);
+  if constexpr (Q::tree_bits < 64) tree &= (uint64_t(1) << Q::tree_bits) - 1;
+  uint32_t leaf = 0;
+#pragma unroll
+  for (int j = 0; j < Q::leaf_bytes; j++) leaf = (leaf << 8) | dbyte(Q::md_bytes + Q::tree_bytes + j);
+  *idx_tree = tree;
+  *idx_leaf = leaf & ((1u << Q::hp) - 1);
+}
+
+// One lane per message: R (written as the first n signature bytes), the
+// digest and its split into the message's work record.  The message is read
+// as bytes, so any length and alignment is accepted.
+template <int ID>
+__global__ void k_prelude(const DevKey* __restrict__ keys, const DevItem* __restrict__ items,
+                          uint32_t count, const uint8_t* __restrict__ msgs, uint8_t* sigs,
+                          WorkRec* __restrict__ recs) {
+  constexpr int NW = P<ID>::NW;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const DevItem it = items[i];
+  const DevKey& K = keys[it.key_slot];
+  const KeyView kv{K.sk_prf, K.pk_seed, K.pk_root};
+  const uint8_t* msg = msgs + it.msg_off;
+  uint32_t R[NW], digest[16];
+  prf_msg<ID>(kv, msg, it.msg_len, R);
+  store_be<NW>(sigs + it.sig_off, R);
+  h_msg<ID>(kv, R, msg, it.msg_len, digest);
+  WorkRec& W = recs[i];
+  uint64_t tree;
+  uint32_t leaf;
+  split_digest<ID>(digest, W.indices, &tree, &leaf);
+  W.idx_tree = tree;
+  W.idx_leaf = leaf;
+  W.key_slot = it.key_slot;
+  W.sig_off = it.sig_off;
+}
+
+// ------------------------------------------------------------------ FORS
+// One workgroup per message.  Each lane builds a subtree of 2^S leaves in
+// registers (PRF + F per leaf, then S levels of H); the level-S nodes go to
+// LDS, and the remaining a-S levels are reduced level by level, the node of
+// index q at level z written over its left child (slot q << (z - S)).
+// The selected secret value and every auth node are written by the lane
+// that computes it; the k roots then give the FORS public key via T_k.
+template <int ID, int S>
+__global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict__ keys,
+                                                       WorkRec* __restrict__ recs, uint32_t count,
+                                                       uint8_t* sigs) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, A = Q::a, KT = Q::k;
+  constexpr int NSUB = KT << (A - S);  // subtrees (= level-S nodes)
+  __shared__ uint32_t node[NSUB * NW];
+  const uint32_t msg = blockIdx.x;
+  if (msg >= count) return;
+  WorkRec& W = recs[msg];
+  const DevKey& K = keys[W.key_slot];
+  const uint64_t tree = W.idx_tree;
+  const uint32_t kp = W.idx_leaf;
+  uint8_t* sig = sigs + W.sig_off + Q::n;  // SIG_FORS
+  uint32_t mid[8], sks[NW];
+  load_words<8>(K.mid256, mid);
+  load_words<NW>(K.sk_seed, sks);
+
+  for (int q = threadIdx.x; q < NSUB; q += kForsThreads) {
+    const int t = q >> (A - S);
+    const int j = q & ((1 << (A - S)) - 1);
+    const uint32_t idx = W.indices[t];
+    const bool sel = int(idx >> S) == j;
+    uint8_t* tsig = sig + t * (A + 1) * Q::n;
+    uint32_t v[1 << S][NW];
+#pragma unroll
+    for (int i = 0; i < (1 << S); i++) {
+      const uint32_t g = (uint32_t(t) << A) + (uint32_t(j) << S) + i;
+      uint32_t sk[NW];
+      thF<ID>(mid, make_adrs(0, tree, A_FORS_PRF, kp, 0, g), sks, sk);
+      if (sel && (idx & ((1u << S) - 1)) == uint32_t(i)) store_be<NW>(tsig, sk);
+      thF<ID>(mid, make_adrs(0, tree, A_FORS_TREE, kp, 0, g), sk, v[i]);
+    }
+#pragma unroll
+    for (int z = 0; z < S; z++) {
+      // auth node of level z inside this subtree
+#pragma unroll
+      for (int i = 0; i < (1 << (S - z)); i++)
+        if (sel && (((idx >> z) ^ 1u) & ((1u << (S - z)) - 1)) == uint32_t(i))
+          store_be<NW>(tsig + (1 + z) * Q::n, v[i]);
+      // next level
+#pragma unroll
+      for (int i = 0; i < (1 << (S - z - 1)); i++) {
+        const uint32_t gi = (uint32_t(t) << (A - z - 1)) + (uint32_t(j) << (S - z - 1)) + i;
+        uint32_t lr[2 * NW];
+#pragma unroll
+        for (int u = 0; u < NW; u++) { lr[u] = v[2 * i][u]; lr[NW + u] = v[2 * i + 1][u]; }
+        thH<ID>(K, make_adrs(0, tree, A_FORS_TREE, kp, z + 1, gi), lr, v[i]);
+      }
+    }
+    store_words<NW>(&node[q * NW], v[0]);
+  }
+  __syncthreads();
+  for (int z = S + 1; z <= A; z++) {
+    const int cnt = KT << (A - z);
+    for (int q = threadIdx.x; q < cnt; q += kForsThreads) {
+      const int t = q >> (A - z);
+      const uint32_t idx = W.indices[t];
+      const int ls = (2 * q) << (z - 1 - S), rs = (2 * q + 1) << (z - 1 - S);
+      uint32_t lr[2 * NW];
+      load_words<NW>(&node[ls * NW], lr);
+      load_words<NW>(&node[rs * NW], lr + NW);
+      // auth node of level z-1 for tree t is one of the two children
+      const uint32_t sib = (uint32_t(t) << (A - z + 1)) + ((idx >> (z - 1)) ^ 1u);
+      uint8_t* tsig = sig + t * (A + 1) * Q::n + z * Q::n;
+      if (sib == uint32_t(2 * q)) store_be<NW>(tsig, lr);
+      if (sib == uint32_t(2 * q + 1)) store_be<NW>(tsig, lr + NW);
+      uint32_t out[NW];
+      thH<ID>(K, make_adrs(0, tree, A_FORS_TREE, kp, z, q), lr, out);
+      store_words<NW>(&node[ls * NW], out);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // FORS public key = T_k(FORS_ROOTS address, roots); root t at slot t << (A - S)
+    auto get = [&](int wi) -> uint32_t {
+      const int t = wi / NW, u = wi - t * NW;
+      return node[(t << (A - S)) * NW + u];
+    };
+    uint32_t pk[NW];
+    thT<ID, KT>(K.mid256, K.mid512, make_adrs(0, tree, A_FORS_ROOTS, kp, 0, 0), get, pk);
+    store_words<NW>(W.fors_pk, pk);
+  }
+}
+
+// ------------------------------------------------------------------ TREE
+// Tree-job description: which XMSS tree a group of 2^h' leaves belongs to.
+struct TreeJob {
+  const DevKey* key;
+  uint32_t layer;
+  uint64_t tree;
+  int32_t sign_leaf;   // leaf whose WOTS+ chains are kept, or -1
+  uint8_t* sig_xmss;   // XMSS signature slot of this layer, or null
+  uint32_t* root_out;  // where the root goes (BE words), or null
+  uint32_t* spill;     // len * 16 * NW words for the signing leaf, or null
+};
+
+template <int ID>
+__device__ __forceinline__ TreeJob sign_job(const DevKey* keys, WorkRec* recs, uint8_t* sigs,
+                                            uint32_t* spill, uint32_t ftree) {
+  using Q = P<ID>;
+  const uint32_t msg = ftree / Q::d, layer = ftree - msg * Q::d;
+  WorkRec& W = recs[msg];
+  TreeJob J;
+  J.key = &keys[W.key_slot];
+  J.layer = layer;
+  const uint32_t sh = Q::hp * layer;
+  J.tree = sh >= 64 ? 0 : (W.idx_tree >> sh);
+  if (layer == 0) {
+    J.sign_leaf = int32_t(W.idx_leaf);
+  } else {
+    const uint32_t sh1 = Q::hp * (layer - 1);
+    J.sign_leaf = int32_t((W.idx_tree >> sh1) & ((1u << Q::hp) - 1));
+  }
+  J.sig_xmss = sigs + W.sig_off + Q::ht_off + size_t(layer) * Q::xmss_bytes;
+  J.root_out = (layer + 1 < uint32_t(Q::d)) ? W.roots[layer] : nullptr;
+  J.spill = spill + size_t(ftree) * Q::len * 16 * Q::NW;
+  return J;
+}
+
+// One WOTS+ chain: PRF then 15 F steps.  If `keep` is set, every value of
+// the chain (steps 0..15) is written to keep[step * NW ...].
+template <int ID>
+__device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t* sks, uint32_t layer,
+                                           uint64_t tree, uint32_t kp, uint32_t c, uint32_t* keep,
+                                           uint32_t x[P<ID>::NW]) {
+  constexpr int NW = P<ID>::NW;
+  thF<ID>(mid, make_adrs(layer, tree, A_WOTS_PRF, kp, c, 0), sks, x);
+  if (keep) store_words<NW>(keep, x);
+  const Adrs A0 = make_adrs(layer, tree, A_WOTS_HASH, kp, c, 0);
+  for (uint32_t s = 0; s < 15; s++) {
+    Adrs A = A0;
+    A.tail = s << 16;
+    uint32_t y[NW];
+    th256<NW, NW>(mid, A, x, y);
+#pragma unroll
+    for (int u = 0; u < NW; u++) x[u] = y[u];
+    if (keep) store_words<NW>(keep + (s + 1) * NW, x);
+  }
+}
+
+// KEYGEN = true: a single tree (layer d-1, tree 0) whose root is written to
+// root_out; otherwise trees are taken from the batch's work records.
+template <int ID, bool KEYGEN>
+__global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict__ keys,
+                                                       WorkRec* __restrict__ recs, uint32_t ntrees,
+                                                       uint8_t* sigs, uint32_t* __restrict__ stage,
+                                                       uint32_t* __restrict__ spill,
+                                                       uint32_t key_slot, uint32_t* root_out) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
+  constexpr int TPB = kLeavesPerBlock / LV;  // trees per block
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t tree0 = blockIdx.x * TPB;
+  uint32_t* st = stage + size_t(blockIdx.x) * LEN * kLeavesPerBlock * NW;
+
+  auto job_of = [&](uint32_t lt) -> TreeJob {
+    if constexpr (KEYGEN) {
+      TreeJob J;
+      J.key = &keys[key_slot];
+      J.layer = Q::d - 1;
+      J.tree = 0;
+      J.sign_leaf = -1;
+      J.sig_xmss = nullptr;
+      J.root_out = root_out;
+      J.spill = nullptr;
+      return J;
+    } else {
+      return sign_job<ID>(keys, recs, sigs, spill, tree0 + lt);
+    }
+  };
+
+  // phase 1: chain c of leaf `lane` for c = wave, wave + 4, ...
+  {
+    const uint32_t lt = lane / LV, kp = lane % LV;
+    const bool valid = tree0 + lt < ntrees;
+    if (valid) {
+      const TreeJob J = job_of(lt);
+      uint32_t mid[8], sks[NW];
+      load_words<8>(J.key->mid256, mid);
+      load_words<NW>(J.key->sk_seed, sks);
+      const bool keepit = J.spill != nullptr && int32_t(kp) == J.sign_leaf;
+      for (int c = wave; c < LEN; c += kTreeThreads / 64) {
+        uint32_t x[NW];
+        wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keepit ? J.spill + c * 16 * NW : nullptr, x);
+        store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
+      }
+    }
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  // phase 2: one lane per leaf computes T_len over its chain ends
+  const uint32_t lt = lane / LV, kp = lane % LV;
+  const bool valid = tree0 + lt < ntrees;
+  uint32_t v[NW];
+  TreeJob J{};
+  if (valid) {
+    J = job_of(lt);
+    auto get = [&](int wi) -> uint32_t {
+      const int c = wi / NW, u = wi - c * NW;
+      return st[(c * kLeavesPerBlock + lane) * NW + u];
+    };
+    thT<ID, LEN>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_WOTS_PK, kp, 0, 0), get, v);
+  } else {
+#pragma unroll
+    for (int u = 0; u < NW; u++) v[u] = 0;
+  }
+  // phase 3: XMSS levels inside the wave; node of level z lives in lanes
+  // with kp % 2^z == 0, its partner is 2^(z-1) lanes up.
+#pragma unroll
+  for (int z = 1; z <= HP; z++) {
+    const uint32_t span = 1u << (z - 1);
+    // auth node of level z-1
+    if (valid && J.sig_xmss && (kp & (span - 1)) == 0) {
+      const uint32_t i = kp >> (z - 1);
+      if (i == ((uint32_t(J.sign_leaf) >> (z - 1)) ^ 1u))
+        store_be<NW>(J.sig_xmss + (LEN + z - 1) * Q::n, v);
+    }
+    uint32_t lr[2 * NW];
+#pragma unroll
+    for (int u = 0; u < NW; u++) {
+      lr[u] = v[u];
+      lr[NW + u] = __shfl_down(v[u], span, 64);
+    }
+    if (valid && (kp & ((span << 1) - 1)) == 0) {
+      thH<ID>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_TREE, 0, z, kp >> z), lr, v);
+    }
+  }
+  if (valid && kp == 0 && J.root_out) store_words<NW>(J.root_out, v);
+}
+
+// ------------------------------------------------------------------ WOTS
+// One lane per (message, layer, chain): digit of the layer's message
+// (FORS pk for layer 0, root of layer j-1 otherwise) with the checksum
+// digits appended (FIPS 205 Algorithm 7), then the kept chain value.
+template <int ID>
+__global__ void k_wots(const WorkRec* __restrict__ recs, uint32_t count, uint8_t* sigs,
+                       const uint32_t* __restrict__ spill) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t total = count * Q::d * LEN;
+  if (gid >= total) return;
+  const uint32_t ftree = gid / LEN, c = gid - ftree * LEN;
+  const uint32_t msg = ftree / Q::d, layer = ftree - msg * Q::d;
+  const WorkRec& W = recs[msg];
+  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
+  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
+  uint32_t digit;
+  if (c < uint32_t(Q::len1)) {
+    digit = nib(c);
+  } else {
+    uint32_t csum = 0;
+    for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
+    csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
+    digit = (csum >> (12 - 4 * (c - Q::len1))) & 15u;
+  }
+  const uint32_t* src = spill + ((size_t(ftree) * LEN + c) * 16 + digit) * NW;
+  uint32_t v[NW];
+  load_words<NW>(src, v);
+  store_be<NW>(sigs + W.sig_off + Q::ht_off + size_t(layer) * Q::xmss_bytes + c * Q::n, v);
+}
+
+// ------------------------------------------------------------------ verify
+// One workgroup of 128 lanes per signature (FIPS 205 Algorithm 20): the
+// digest on lane 0; FORS pkFromSig with one lane per tree; then, layer by
+// layer, WOTS+ pkFromSig with one lane per chain, T_len and the auth-path
+// climb on lane 0.  The result is 1 (valid) or 0.
+struct VerifyItem {
+  uint64_t msg_off, msg_len, sig_off, pk_off;
+};
+constexpr int kVerifyThreads = 128;
+
+__device__ __forceinline__ uint32_t load_be32(const uint8_t* p) {
+  return (uint32_t(p[0]) << 24) | (uint32_t(p[1]) << 16) | (uint32_t(p[2]) << 8) | uint32_t(p[3]);
+}
+template <int NW>
+__device__ __forceinline__ void load_be(const uint8_t* p, uint32_t* v) {
+#pragma unroll
+  for (int i = 0; i < NW; i++) v[i] = load_be32(p + 4 * i);
+}
+
+template <int ID>
+__global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __restrict__ items,
+                                                          uint32_t count, const uint8_t* msgs,
+                                                          const uint8_t* sigs, const uint8_t* pks,
+                                                          int* results) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a;
+  static_assert(LEN <= kVerifyThreads && KT <= kVerifyThreads, "one lane per chain / tree");
+  __shared__ uint32_t pk_seed[8], pk_root[8], mid256[8], mid512[16];
+  __shared__ uint32_t vals[(LEN > KT ? LEN : KT) * NW];
+  __shared__ uint32_t cur[8];
+  __shared__ uint16_t indices[64];
+  __shared__ uint64_t s_tree;
+  __shared__ uint32_t s_leaf;
+  const uint32_t b = blockIdx.x;
+  if (b >= count) return;
+  const VerifyItem it = items[b];
+  const uint8_t* sig = sigs + it.sig_off;
+  const uint8_t* msg = msgs + it.msg_off;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    load_be<NW>(pks + it.pk_off, pk_seed);
+    load_be<NW>(pks + it.pk_off + Q::n, pk_root);
+    uint32_t st[8], w[16];
+    sha256_iv(st);
+#pragma unroll
+    for (int j = 0; j < 16; j++) w[j] = j < NW ? pk_seed[j] : 0u;
+    sha256_compress(st, w);
+#pragma unroll
+    for (int j = 0; j < 8; j++) mid256[j] = st[j];
+    u64p s5[8], w5[16];
+    sha512_iv(s5);
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      w5[j] = u64p{2 * j < NW ? pk_seed[2 * j] : 0u, 2 * j + 1 < NW ? pk_seed[2 * j + 1] : 0u};
+    sha512_compress(s5, w5);
+#pragma unroll
+    for (int j = 0; j < 8; j++) { mid512[2 * j] = s5[j].hi; mid512[2 * j + 1] = s5[j].lo; }
+    uint32_t R[NW], digest[16];
+    load_be<NW>(sig, R);
+    const KeyView kv{nullptr, pk_seed, pk_root};
+    h_msg<ID>(kv, R, msg, it.msg_len, digest);
+    uint64_t tree;
+    uint32_t leaf;
+    split_digest<ID>(digest, indices, &tree, &leaf);
+    s_tree = tree;
+    s_leaf = leaf;
+  }
+  __syncthreads();
+  uint64_t tree = s_tree;
+  uint32_t leaf = s_leaf;
+  // FORS: root of tree t from its secret value and auth path
+  if (tid < KT) {
+    const uint8_t* ts = sig + Q::n + tid * (A + 1) * Q::n;
+    const uint32_t idx = indices[tid];
+    uint32_t x[NW], y[NW], lr[2 * NW];
+    load_be<NW>(ts, x);
+    uint32_t gi = (uint32_t(tid) << A) + idx;
+    thF<ID>(mid256, make_adrs(0, tree, A_FORS_TREE, leaf, 0, gi), x, y);
+    for (int j = 0; j < A; j++) {
+      uint32_t au[NW];
+      load_be<NW>(ts + (1 + j) * Q::n, au);
+      const bool even = ((idx >> j) & 1u) == 0;
+#pragma unroll
+      for (int u = 0; u < NW; u++) {
+        lr[u] = even ? y[u] : au[u];
+        lr[NW + u] = even ? au[u] : y[u];
+      }
+      gi >>= 1;
+      thH<ID>(mid256, mid512, make_adrs(0, tree, A_FORS_TREE, leaf, j + 1, gi), lr, y);
+    }
+    store_words<NW>(&vals[tid * NW], y);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    auto get = [&](int wi) -> uint32_t { return vals[wi]; };
+    uint32_t pk[NW];
+    thT<ID, KT>(mid256, mid512, make_adrs(0, tree, A_FORS_ROOTS, leaf, 0, 0), get, pk);
+    store_words<NW>(cur, pk);
+  }
+  __syncthreads();
+  const uint8_t* ht = sig + Q::ht_off;
+  for (int layer = 0; layer < Q::d; layer++) {
+    const uint8_t* xs = ht + layer * Q::xmss_bytes;
+    if (tid < LEN) {
+      auto nib = [&](int i) -> uint32_t { return (cur[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
+      uint32_t digit;
+      if (tid < Q::len1) {
+        digit = nib(tid);
+      } else {
+        uint32_t csum = 0;
+        for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
+        csum <<= 4;
+        digit = (csum >> (12 - 4 * (tid - Q::len1))) & 15u;
+      }
+      uint32_t x[NW];
+      load_be<NW>(xs + tid * Q::n, x);
+      Adrs Ad = make_adrs(layer, tree, A_WOTS_HASH, leaf, tid, 0);
+      for (uint32_t s = digit; s < 15; s++) {
+        Ad.tail = s << 16;
+        uint32_t y[NW];
+        th256<NW, NW>(mid256, Ad, x, y);
+#pragma unroll
+        for (int u = 0; u < NW; u++) x[u] = y[u];
+      }
+      store_words<NW>(&vals[tid * NW], x);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      auto get = [&](int wi) -> uint32_t { return vals[wi]; };
+      uint32_t node[NW], lr[2 * NW];
+      thT<ID, LEN>(mid256, mid512, make_adrs(layer, tree, A_WOTS_PK, leaf, 0, 0), get, node);
+      uint32_t ti = leaf;
+      for (int j = 0; j < Q::hp; j++) {
+        uint32_t au[NW];
+        load_be<NW>(xs + (LEN + j) * Q::n, au);
+        const bool even = ((leaf >> j) & 1u) == 0;
+#pragma unroll
+        for (int u = 0; u < NW; u++) {
+          lr[u] = even ? node[u] : au[u];
+          lr[NW + u] = even ? au[u] : node[u];
+        }
+        ti >>= 1;
+        thH<ID>(mid256, mid512, make_adrs(layer, tree, A_TREE, 0, j + 1, ti), lr, node);
+      }
+      store_words<NW>(cur, node);
+    }
+    __syncthreads();
+    leaf = uint32_t(tree & ((1u << Q::hp) - 1));
+    tree = Q::hp >= 64 ? 0 : (tree >> Q::hp);
+  }
+  if (tid == 0) {
+    bool ok = true;
+#pragma unroll
+    for (int u = 0; u < NW; u++) ok = ok && (cur[u] == pk_root[u]);
+    results[b] = ok ? 1 : 0;
+  }
+}
+
+}  // namespace slh

@@ -1,0 +1,408 @@
+// slh_dev.hpp -- SPHINCS+ device primitives for gfx950: parameter sets,
+// compressed addresses, the tweakable hashes F / PRF / H / T_l and the
+// byte-stream hashes of the message prelude.
+//
+// Definitions: the paper's Table 1 (parameter sets) and Section II-A (WOTS+,
+// FORS, XMSS, hypertree); the SHA2 instantiation of the tweakable hashes is
+// that of FIPS 205 Section 11.2 (PK.seed padded to one hash block, then the
+// 22-byte compressed address, then the input).
+//
+// Representation: every n-byte value is held as n/4 32-bit words in
+// big-endian interpretation ("BE words"), which is exactly the form SHA-2
+// consumes and produces.  Because the compressed address is 22 bytes long,
+// an input that follows it starts at byte 2 of a message word; each message
+// word is then one v_alignbit_b32 of two neighbouring BE words.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sha2_dev.hpp"
+
+namespace slh {
+
+// ---------------------------------------------------------------- params
+template <int ID>
+struct Prm;
+// SHA2-128f: n=16, h=66, d=22, h'=3, a=6, k=33, w=16 (paper Table 1)
+template <>
+struct Prm<1> {
+  static constexpr int n = 16, h = 66, d = 22, hp = 3, a = 6, k = 33, len1 = 32, len2 = 3, m = 34;
+  static constexpr bool wide = false;
+};
+// SHA2-192f: n=24, h=66, d=22, h'=3, a=8, k=33, w=16
+template <>
+struct Prm<2> {
+  static constexpr int n = 24, h = 66, d = 22, hp = 3, a = 8, k = 33, len1 = 48, len2 = 3, m = 42;
+  static constexpr bool wide = true;
+};
+// SHA2-256f: n=32, h=68, d=17, h'=4, a=9, k=35, w=16
+template <>
+struct Prm<3> {
+  static constexpr int n = 32, h = 68, d = 17, hp = 4, a = 9, k = 35, len1 = 64, len2 = 3, m = 49;
+  static constexpr bool wide = true;
+};
+
+template <int ID>
+struct P : Prm<ID> {
+  using B = Prm<ID>;
+  static constexpr int NW = B::n / 4;                       // words per value
+  static constexpr int len = B::len1 + B::len2;             // WOTS+ chains
+  static constexpr int leaves = 1 << B::hp;                 // leaves per XMSS tree
+  static constexpr int fors_bytes = B::k * (B::a + 1) * B::n;
+  static constexpr int xmss_bytes = (len + B::hp) * B::n;
+  static constexpr int ht_off = B::n + fors_bytes;          // offset of SIG_HT
+  static constexpr int sig_bytes = B::n + fors_bytes + B::d * xmss_bytes;
+  static constexpr int md_bytes = (B::k * B::a + 7) / 8;
+  static constexpr int tree_bits = B::h - B::hp;
+  static constexpr int tree_bytes = (tree_bits + 7) / 8;
+  static constexpr int leaf_bytes = (B::hp + 7) / 8;
+};
+
+// Address types (FIPS 205 Section 4.2)
+enum : uint32_t { A_WOTS_HASH = 0, A_WOTS_PK = 1, A_TREE = 2, A_FORS_TREE = 3, A_FORS_ROOTS = 4,
+                  A_WOTS_PRF = 5, A_FORS_PRF = 6 };
+
+// ---------------------------------------------------------------- tables in HBM
+// Per-key record in the device key table (256 bytes).  All values are BE words.
+struct DevKey {
+  uint32_t param, n, pad0, pad1;
+  uint32_t sk_seed[8];
+  uint32_t sk_prf[8];
+  uint32_t pk_seed[8];
+  uint32_t pk_root[8];
+  uint32_t mid256[8];   // SHA-256 chaining value after PK.seed || 0^(64-n)
+  uint32_t mid512[16];  // SHA-512 chaining value after PK.seed || 0^(128-n), (hi, lo) pairs
+  uint32_t pad2[4];
+};
+static_assert(sizeof(DevKey) == 256, "DevKey layout");
+
+// One sign request as handed to the library (mirrors slh_item of slh.h).
+struct DevItem {
+  uint32_t param;
+  uint32_t key_slot;
+  uint64_t msg_off;
+  uint64_t msg_len;
+  uint64_t sig_off;
+};
+static_assert(sizeof(DevItem) == 32, "DevItem layout");
+
+// Per-message state shared by the kernels of one batch (1 KiB).
+struct WorkRec {
+  uint64_t idx_tree;
+  uint32_t idx_leaf;
+  uint32_t key_slot;
+  uint64_t sig_off;
+  uint32_t pad[2];
+  uint16_t indices[64];   // FORS indices (k <= 35)
+  uint32_t fors_pk[8];    // FORS public key = message of layer 0
+  uint32_t roots[24][8];  // XMSS root of each layer = message of the next layer
+  uint32_t pad2[16];
+};
+static_assert(sizeof(WorkRec) == 1024, "WorkRec layout");
+
+// ---------------------------------------------------------------- byte order
+__device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
+
+// Write NW BE words as n bytes (4-byte aligned destination).
+template <int NW>
+__device__ __forceinline__ void store_be(uint8_t* dst, const uint32_t v[NW]) {
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+  for (int i = 0; i < NW; i++) d[i] = bswap32(v[i]);
+}
+template <int NW>
+__device__ __forceinline__ void load_words(const uint32_t* src, uint32_t v[NW]) {
+#pragma unroll
+  for (int i = 0; i < NW; i++) v[i] = src[i];
+}
+template <int NW>
+__device__ __forceinline__ void store_words(uint32_t* dst, const uint32_t v[NW]) {
+#pragma unroll
+  for (int i = 0; i < NW; i++) dst[i] = v[i];
+}
+
+// ---------------------------------------------------------------- addresses
+// The 22-byte compressed address ADRSc = layer(1) | tree(8) | type(1) |
+// word1(4) | word2(4) | word3(4) (FIPS 205 Section 11.2) as message words
+// 0..4 plus the upper half of word 5 (the low 16 bits of word3).
+struct Adrs {
+  uint32_t w[5];
+  uint32_t tail;  // low 16 bits of word3, already shifted to bits 31..16
+};
+__device__ __forceinline__ Adrs make_adrs(uint32_t layer, uint64_t tree, uint32_t type, uint32_t w1,
+                                          uint32_t w2, uint32_t w3) {
+  Adrs A;
+  uint32_t thi = uint32_t(tree >> 32), tlo = uint32_t(tree);
+  A.w[0] = (layer << 24) | (thi >> 8);
+  A.w[1] = (thi << 24) | (tlo >> 8);
+  A.w[2] = (tlo << 24) | ((type & 0xFF) << 16) | (w1 >> 16);
+  A.w[3] = (w1 << 16) | (w2 >> 16);
+  A.w[4] = (w2 << 16) | (w3 >> 16);
+  A.tail = w3 << 16;
+  return A;
+}
+
+// Message words 0..15 of a block holding ADRSc | x (NX BE words) | padding,
+// where the block follows one earlier block (the PK.seed block).
+// For SHA-256: 22 + 4 NX + 9 <= 64, i.e. NX <= 8.
+template <int NX>
+__device__ __forceinline__ void th256_words(const Adrs& A, const uint32_t* x, uint32_t w[16]) {
+  static_assert(NX <= 8, "single block");
+#pragma unroll
+  for (int i = 0; i < 5; i++) w[i] = A.w[i];
+  w[5] = A.tail | (x[0] >> 16);
+#pragma unroll
+  for (int i = 1; i < NX; i++) w[5 + i] = __builtin_amdgcn_alignbit(x[i - 1], x[i], 16);
+  w[5 + NX] = (x[NX - 1] << 16) | 0x8000u;
+#pragma unroll
+  for (int i = 6 + NX; i < 15; i++) w[i] = 0;
+  w[15] = (64 + 22 + 4 * NX) * 8;
+}
+
+// Tweakable hash with SHA-256 over one block: out = first NOUT words of
+// SHA-256(PK.seed || 0^(64-n) || ADRSc || x).
+template <int NX, int NOUT>
+__device__ __forceinline__ void th256(const uint32_t mid[8], const Adrs& A, const uint32_t* x,
+                                      uint32_t* out) {
+  uint32_t w[16], st[8];
+  th256_words<NX>(A, x, w);
+#pragma unroll
+  for (int i = 0; i < 8; i++) st[i] = mid[i];
+  sha256_rounds<0>(st, w);
+#pragma unroll
+  for (int i = 0; i < NOUT; i++) out[i] = mid[i] + st[i];
+}
+
+// Tweakable hash with SHA-512 over one block: out = first NOUT BE words of
+// SHA-512(PK.seed || 0^(128-n) || ADRSc || x).  22 + 4 NX + 17 <= 128.
+template <int NX, int NOUT>
+__device__ __forceinline__ void th512(const uint32_t mid[16], const Adrs& A, const uint32_t* x,
+                                      uint32_t* out) {
+  static_assert(NX <= 22, "single block");
+  uint32_t v[32];
+#pragma unroll
+  for (int i = 0; i < 5; i++) v[i] = A.w[i];
+  v[5] = A.tail | (x[0] >> 16);
+#pragma unroll
+  for (int i = 1; i < NX; i++) v[5 + i] = __builtin_amdgcn_alignbit(x[i - 1], x[i], 16);
+  v[5 + NX] = (x[NX - 1] << 16) | 0x8000u;
+#pragma unroll
+  for (int i = 6 + NX; i < 31; i++) v[i] = 0;
+  v[31] = (128 + 22 + 4 * NX) * 8;
+  u64p w[16], st[8];
+#pragma unroll
+  for (int i = 0; i < 16; i++) w[i] = u64p{v[2 * i], v[2 * i + 1]};
+#pragma unroll
+  for (int i = 0; i < 8; i++) st[i] = u64p{mid[2 * i], mid[2 * i + 1]};
+  sha512_compress(st, w);
+#pragma unroll
+  for (int i = 0; i < NOUT; i++) out[i] = (i & 1) ? st[i >> 1].lo : st[i >> 1].hi;
+}
+
+// F and PRF: always SHA-256 (FIPS 205 Section 11.2.1 and 11.2.2).
+template <int ID>
+__device__ __forceinline__ void thF(const uint32_t mid256[8], const Adrs& A, const uint32_t* x,
+                                    uint32_t* out) {
+  th256<P<ID>::NW, P<ID>::NW>(mid256, A, x, out);
+}
+// H: SHA-256 for n = 16, SHA-512 for n = 24, 32.
+template <int ID>
+__device__ __forceinline__ void thH(const DevKey& key, const Adrs& A, const uint32_t* lr,
+                                    uint32_t* out) {
+  if constexpr (P<ID>::wide)
+    th512<2 * P<ID>::NW, P<ID>::NW>(key.mid512, A, lr, out);
+  else
+    th256<2 * P<ID>::NW, P<ID>::NW>(key.mid256, A, lr, out);
+}
+template <int ID>
+__device__ __forceinline__ void thH(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
+                                    const uint32_t* lr, uint32_t* out) {
+  if constexpr (P<ID>::wide)
+    th512<2 * P<ID>::NW, P<ID>::NW>(mid512, A, lr, out);
+  else
+    th256<2 * P<ID>::NW, P<ID>::NW>(mid256, A, lr, out);
+}
+
+// ---------------------------------------------------------------- T_l
+// T_l over l n-byte values read through a getter `get(word_index)` that
+// returns BE word `word_index` of the concatenated values.  The message is
+// ADRSc (22 bytes) | values, after the PK.seed block; SHA-256 for n = 16,
+// SHA-512 for n >= 24.  Message word q >= 6 is alignbit(V[q-6], V[q-5], 16).
+template <int ID, int L, class Get>
+__device__ __forceinline__ void thT(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
+                                    Get get, uint32_t* out) {
+  constexpr int NW = P<ID>::NW;
+  constexpr int NV = L * NW;                 // value words
+  constexpr int MB = 22 + 4 * NV;            // message bytes after the seed block
+  constexpr bool wide = P<ID>::wide;
+  constexpr int BW = wide ? 32 : 16;         // 32-bit words per block
+  constexpr int NBLK = (MB + (wide ? 17 : 9) + 4 * BW - 1) / (4 * BW);
+  constexpr int LASTQ = 5 + NV;              // word holding the 0x80 byte
+  constexpr uint32_t BITS = ((wide ? 128 : 64) + MB) * 8;
+  // Message word q of the stream.  The first block is built with
+  // compile-time indices (it holds the address words); later blocks only
+  // hold value words, padding and the length.
+  auto tail_word = [&](int q) -> uint32_t {
+    if (q < LASTQ) return __builtin_amdgcn_alignbit(get(q - 6), get(q - 5), 16);
+    if (q == LASTQ) return (get(NV - 1) << 16) | 0x8000u;
+    if (q == NBLK * BW - 1) return BITS;
+    return 0u;
+  };
+  auto first_word = [&](int q) -> uint32_t {
+    if (q < 5) return A.w[q];
+    if (q == 5) return A.tail | (get(0) >> 16);
+    return tail_word(q);
+  };
+  if constexpr (!wide) {
+    uint32_t st[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) st[i] = mid256[i];
+    {
+      uint32_t w[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) w[j] = first_word(j);
+      sha256_compress(st, w);
+    }
+    for (int b = 1; b < NBLK; b++) {
+      uint32_t w[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) w[j] = tail_word(16 * b + j);
+      sha256_compress(st, w);
+    }
+#pragma unroll
+    for (int i = 0; i < NW; i++) out[i] = st[i];
+  } else {
+    u64p st[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) st[i] = u64p{mid512[2 * i], mid512[2 * i + 1]};
+    {
+      u64p w[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) w[j] = u64p{first_word(2 * j), first_word(2 * j + 1)};
+      sha512_compress(st, w);
+    }
+    for (int b = 1; b < NBLK; b++) {
+      u64p w[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) w[j] = u64p{tail_word(32 * b + 2 * j), tail_word(32 * b + 2 * j + 1)};
+      sha512_compress(st, w);
+    }
+#pragma unroll
+    for (int i = 0; i < NW; i++) out[i] = (i & 1) ? st[i >> 1].lo : st[i >> 1].hi;
+  }
+}
+
+// ---------------------------------------------------------------- byte streams
+// SHA-256 / SHA-512 over  prefix (PW BE words held by the caller, PW*4 bytes
+// that fit in the first block) | msg (mlen bytes in global memory) with the
+// standard padding; `pre` bytes were already absorbed into `st`.
+__device__ __forceinline__ uint32_t msg_word(const uint8_t* msg, uint64_t mlen, int64_t p) {
+  // 4 bytes of the padded message portion starting at byte p (p may be < 0
+  // only for positions covered by the prefix, which callers never ask for)
+  uint32_t w = 0;
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    int64_t q = p + t;
+    uint32_t byte = (q < (int64_t)mlen) ? msg[q] : (q == (int64_t)mlen ? 0x80u : 0u);
+    w = (w << 8) | byte;
+  }
+  return w;
+}
+
+template <int PW>
+__device__ void sha256_stream(uint32_t st[8], const uint32_t* prefix, const uint8_t* msg,
+                              uint64_t mlen, uint64_t pre) {
+  static_assert(PW <= 13, "prefix plus padding start must fit the first block");
+  const uint64_t total = PW * 4 + mlen;
+  const uint64_t nblk = (total + 9 + 63) / 64;
+  const uint64_t bits = (pre + total) * 8;
+  for (uint64_t b = 0; b < nblk; b++) {
+    uint32_t w[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      int64_t q = int64_t(b) * 16 + j;
+      if (b == 0 && j < PW) w[j] = prefix[j];
+      else w[j] = msg_word(msg, mlen, 4 * q - PW * 4);
+    }
+    if (b == nblk - 1) {
+      w[14] = uint32_t(bits >> 32);
+      w[15] = uint32_t(bits);
+    }
+    sha256_compress(st, w);
+  }
+}
+
+template <int PW>
+__device__ void sha512_stream(u64p st[8], const uint32_t* prefix, const uint8_t* msg,
+                              uint64_t mlen, uint64_t pre) {
+  static_assert(PW <= 27, "prefix plus padding start must fit the first block");
+  const uint64_t total = PW * 4 + mlen;
+  const uint64_t nblk = (total + 17 + 127) / 128;
+  const uint64_t bits = (pre + total) * 8;
+  for (uint64_t b = 0; b < nblk; b++) {
+    uint32_t v[32];
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      int64_t q = int64_t(b) * 32 + j;
+      if (b == 0 && j < PW) v[j] = prefix[j];
+      else v[j] = msg_word(msg, mlen, 4 * q - PW * 4);
+    }
+    if (b == nblk - 1) {
+      v[28] = 0; v[29] = 0;
+      v[30] = uint32_t(bits >> 32);
+      v[31] = uint32_t(bits);
+    }
+    u64p w[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) w[j] = u64p{v[2 * j], v[2 * j + 1]};
+    sha512_compress(st, w);
+  }
+}
+
+// Hash of exactly NWORDS BE words held in registers (fixed layout, unrolled).
+template <int NWORDS>
+__device__ __forceinline__ void sha256_words(const uint32_t* in, uint32_t out[8]) {
+  constexpr int total = NWORDS * 4;
+  constexpr int nblk = (total + 9 + 63) / 64;
+  uint32_t st[8];
+  sha256_iv(st);
+#pragma unroll
+  for (int b = 0; b < nblk; b++) {
+    uint32_t w[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      int q = 16 * b + j;
+      w[j] = q < NWORDS ? in[q] : (q == NWORDS ? 0x80000000u : 0u);
+    }
+    if (b == nblk - 1) w[15] = total * 8;
+    sha256_compress(st, w);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) out[i] = st[i];
+}
+
+template <int NWORDS>
+__device__ __forceinline__ void sha512_words(const uint32_t* in, uint32_t out[16]) {
+  constexpr int total = NWORDS * 4;
+  constexpr int nblk = (total + 17 + 127) / 128;
+  u64p st[8];
+  sha512_iv(st);
+#pragma unroll
+  for (int b = 0; b < nblk; b++) {
+    uint32_t v[32];
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+      int q = 32 * b + j;
+      v[j] = q < NWORDS ? in[q] : (q == NWORDS ? 0x80000000u : 0u);
+    }
+    if (b == nblk - 1) v[31] = total * 8;
+    u64p w[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) w[j] = u64p{v[2 * j], v[2 * j + 1]};
+    sha512_compress(st, w);
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) { out[2 * i] = st[i].hi; out[2 * i + 1] = st[i].lo; }
+}
+
+}  // namespace slh

@@ -1,0 +1,205 @@
+"""Python binding of the C ABI in ``include/slh.h`` (argument marshalling only).
+
+Every hash of the signing path runs in the HIP kernels of ``libslh.so``.
+PyTorch supplies device memory and streams.  If the shared library is not
+built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslh.so")
+
+SHA2_128F, SHA2_192F, SHA2_256F = 1, 2, 3
+NAMES = {1: "128f", 2: "192f", 3: "256f"}
+IDS = {v: k for k, v in NAMES.items()}
+MODE_PLAIN = 0
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
+PHASES = ("prelude", "fors", "tree", "wots")
+
+ITEM_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"),
+                       ("msg_len", "<u8"), ("sig_off", "<u8")])
+assert ITEM_DTYPE.itemsize == 32
+
+
+class SlhError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("slh error %d: %s" % (code, msg))
+        self.code = code
+
+
+class slh_sizes(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in
+                ("n", "h", "d", "hp", "a", "k", "len", "m", "seed_bytes", "pk_bytes", "sk_bytes",
+                 "sig_bytes")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libslh.so is not built; run python -m paper_2512_23969_amd.build")
+    # torch carries its own copy of the HIP runtime (same soname).  Loading
+    # torch first makes libslh.so bind to that copy, so the process has one
+    # HIP runtime; the other order would load two and the second sees no GPU.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    L.slh_params.argtypes = [u32, ctypes.POINTER(slh_sizes)]
+    L.slh_ctx_create.argtypes = [ctypes.c_int, u64, ctypes.POINTER(vp)]
+    L.slh_ctx_destroy.argtypes = [vp]
+    L.slh_last_error.argtypes = [vp]
+    L.slh_last_error.restype = ctypes.c_char_p
+    L.slh_keygen.argtypes = [u32, ctypes.c_char_p, vp, vp]
+    L.slh_ctx_add_keys.argtypes = [vp, u32, ctypes.c_char_p, u32, ctypes.POINTER(u32)]
+    L.slh_sign_batch.argtypes = [vp, vp, u32, vp, u64, vp, u64, u32, vp]
+    L.slh_verify.argtypes = [u32, ctypes.c_char_p, sz, ctypes.c_char_p, sz, ctypes.c_char_p]
+    L.slh_ctx_profile.argtypes = [vp, ctypes.c_int]
+    L.slh_ctx_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                      ctypes.POINTER(u64), ctypes.c_int]
+    return L
+
+
+lib = _load()
+
+
+def _check(rc, ctx=None):
+    if rc < 0:
+        raise SlhError(rc, lib.slh_last_error(ctx).decode(errors="replace"))
+    return rc
+
+
+def sizes(param: int) -> dict:
+    s = slh_sizes()
+    _check(lib.slh_params(int(param), ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in s._fields_}
+
+
+def keygen(param: int, seed: bytes):
+    """(pk, sk) from seed = SK.seed | SK.prf | PK.seed, computed on the GPU."""
+    s = sizes(param)
+    if len(seed) != s["seed_bytes"]:
+        raise ValueError("seed must be %d bytes" % s["seed_bytes"])
+    pk = ctypes.create_string_buffer(s["pk_bytes"])
+    sk = ctypes.create_string_buffer(s["sk_bytes"])
+    _check(lib.slh_keygen(int(param), seed, pk, sk))
+    return pk.raw, sk.raw
+
+
+def verify(param: int, msg: bytes, sig: bytes, pk: bytes) -> bool:
+    """Signature check on the GPU; True if valid."""
+    if len(pk) != sizes(param)["pk_bytes"]:
+        raise ValueError("wrong public key length")
+    rc = _check(lib.slh_verify(int(param), msg, len(msg), sig, len(sig), pk))
+    return rc == 1
+
+
+class Context:
+    """A signing context: a device key table and working memory on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib.slh_ctx_create(int(device), int(hbm_budget), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+        self.key_params: list[int] = []
+
+    def close(self):
+        if self.h:
+            lib.slh_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def error(self) -> str:
+        return lib.slh_last_error(self.h).decode(errors="replace")
+
+    def add_keys(self, param: int, sks) -> int:
+        """Upload secret keys (bytes or list of bytes, 4n each); returns the first slot."""
+        blob = b"".join(sks) if isinstance(sks, (list, tuple)) else bytes(sks)
+        skb = sizes(param)["sk_bytes"]
+        if len(blob) == 0 or len(blob) % skb:
+            raise ValueError("keys must be a positive multiple of %d bytes" % skb)
+        first = ctypes.c_uint32()
+        _check(lib.slh_ctx_add_keys(self.h, int(param), blob, len(blob) // skb, ctypes.byref(first)),
+               self.h)
+        self.key_params += [param] * (len(blob) // skb)
+        return first.value
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every kernel of later sign_batch calls."""
+        _check(lib.slh_ctx_profile(self.h, 1 if enable else 0), self.h)
+
+    def phase_times(self, reset: bool = True) -> dict:
+        """{phase: (milliseconds, launches, messages)} accumulated so far."""
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        la = (ctypes.c_uint64 * n)()
+        me = (ctypes.c_uint64 * n)()
+        _check(lib.slh_ctx_phase_times(self.h, ms, la, me, 1 if reset else 0), self.h)
+        return {p: (ms[i], la[i], me[i]) for i, p in enumerate(PHASES)}
+
+    def sign_batch(self, items: np.ndarray, msgs, sigs, mode: int = MODE_PLAIN, stream=None):
+        """Enqueue signing of `items` (ITEM_DTYPE array) on `stream`.
+
+        msgs / sigs are uint8 CUDA tensors (or (pointer, nbytes) pairs)."""
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        mp, mb = _ptr(msgs)
+        sp, sb = _ptr(sigs)
+        st = _stream_handle(stream)
+        _check(lib.slh_sign_batch(self.h, items.ctypes.data, len(items), mp, mb, sp, sb, int(mode), st),
+               self.h)
+
+
+def _ptr(t):
+    if isinstance(t, tuple):
+        return ctypes.c_void_p(int(t[0])), int(t[1])
+    return ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def pack_batch(params, slots, messages, align: int = 16):
+    """Lay out messages and signature slots; returns (items, msg_blob, sig_bytes_total)."""
+    items = np.zeros(len(messages), dtype=ITEM_DTYPE)
+    moff = 0
+    soff = 0
+    for i, (p, s, m) in enumerate(zip(params, slots, messages)):
+        items[i] = (p, s, moff, len(m), soff)
+        moff += len(m)
+        soff += (sizes(p)["sig_bytes"] + align - 1) // align * align
+    return items, b"".join(messages), soff
+
+
+def sign_messages(ctx: Context, params, slots, messages, mode: int = MODE_PLAIN):
+    """Sign a list of messages synchronously; returns a list of signatures (bytes)."""
+    import torch
+    items, blob, total = pack_batch(params, slots, messages)
+    dev = torch.device("cuda", ctx.device)
+    msgs = torch.frombuffer(bytearray(blob or b"\0"), dtype=torch.uint8).to(dev)
+    sigs = torch.zeros(max(total, 16), dtype=torch.uint8, device=dev)
+    ctx.sign_batch(items, (msgs.data_ptr(), len(blob)), sigs, mode)
+    torch.cuda.synchronize(dev)
+    host = sigs.cpu().numpy().tobytes()
+    return [host[int(it["sig_off"]):int(it["sig_off"]) + sizes(int(it["param"]))["sig_bytes"]]
+            for it in items]
