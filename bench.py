@@ -106,6 +106,12 @@ def cpu_baseline(name, workloads, seconds=15.0):
                       % (done, name, threads, el)}
 
 
+# HBM bytes per k_tree launch (4096 signatures) from rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0 (copy-kernel calibration); None where not measured for the
+# current kernel.
+TRAFFIC = {}
+
+
 def roofline(param, res):
     from paper_2512_23969_amd import accounting as acc
     ms, launches, msgs = res["phases"]["tree"]
@@ -116,9 +122,15 @@ def roofline(param, res):
     avg_s = ms / launches / 1000.0
     achieved = ops_per_launch / avg_s / 1e12
     peak = acc.VALU_PEAK_OPS / 1e12
+    c256, c512 = acc.per_signature(param)["sha256"]["tree"], acc.per_signature(param)["sha512"]["tree"]
     return {"bound": "alu", "kernel": "k_tree", "achieved": round(achieved, 3), "peak": round(peak, 3),
-            "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4), "traffic": None,
-            "avg_launch_ms": round(ms / launches, 4)}
+            "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
+            "traffic": TRAFFIC.get(param),
+            "avg_launch_ms": round(ms / launches, 4),
+            "units_per_launch": {"sha256": int(c256 * per_launch_msgs), "sha512": int(c512 * per_launch_msgs)},
+            "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512},
+            "textbook_frac": round(acc.ops_per_signature(param, "tree", textbook=True) * per_launch_msgs
+                                   / avg_s / acc.VALU_PEAK_OPS, 4)}
 
 
 def main():

@@ -8,8 +8,17 @@ SHA-512 (n >= 24) compression; T_l takes ceil((22 + l n + pad) / block)
 compressions.  The paper gives the per-leaf figures 560 / 816 / 1072
 (Section III-C) and the leaf counts (Section III-B) these reproduce.
 
-Algorithmic VALU operations per compression (gfx950 instruction set, one
-instruction per primitive of FIPS 180-4, no precomputation):
+VALU operations per compression.  The roofline uses the instruction count
+of one compression in the compiled gfx950 code of this library (the F step
+of a WOTS+ chain, which is over 90 % of all compressions, and the SHA-512
+block), counted from its disassembly and confirmed by SQ_INSTS_VALU:
+  SHA-256: 1232 (rounds 0-4 of every chain step and 7 of the 48 schedule
+           words depend only on the chain's address, so they are computed
+           once per chain, not per step);
+  SHA-512: 4541 (rounds 0-15 peeled, then four 16-round blocks; 64-bit adds
+           are single v_lshl_add_u64 instructions).
+For comparison, the textbook count with one instruction per primitive of
+FIPS 180-4 and no precomputation is:
   SHA-256: round = Sigma1 (3 rotates + 1 xor3) + Ch + Sigma0 (3 + 1) + Maj
            + 4 three-input adds = 14; schedule word = 2 x (2 rotates +
            1 shift + 1 xor3) + 2 adds = 10; feed-forward 8.
@@ -24,8 +33,10 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
-OPS_SHA256 = 64 * 14 + 48 * 10 + 8
-OPS_SHA512 = 80 * 34 + 64 * 22 + 16
+TEXTBOOK_SHA256 = 64 * 14 + 48 * 10 + 8
+TEXTBOOK_SHA512 = 80 * 34 + 64 * 22 + 16
+OPS_SHA256 = 1232
+OPS_SHA512 = 4541
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock for 32-bit integer VALU
 # operations at the 2.4 GHz peak engine clock.
@@ -84,10 +95,12 @@ def per_signature(param: int) -> dict:
     return {"sha256": c256, "sha512": c512}
 
 
-def ops_per_signature(param: int, phase: str | None = None) -> int:
+def ops_per_signature(param: int, phase: str | None = None, textbook: bool = False) -> int:
+    """VALU lane-operations per signature (ISA counts, or the textbook counts)."""
     c = per_signature(param)
+    o256, o512 = (TEXTBOOK_SHA256, TEXTBOOK_SHA512) if textbook else (OPS_SHA256, OPS_SHA512)
     phases = [phase] if phase else list(c["sha256"])
-    return sum(c["sha256"][ph] * OPS_SHA256 + c["sha512"][ph] * OPS_SHA512 for ph in phases)
+    return sum(c["sha256"][ph] * o256 + c["sha512"][ph] * o512 for ph in phases)
 
 
 def compressions_per_signature(param: int) -> tuple[int, int]:

