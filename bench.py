@@ -50,19 +50,31 @@ def setup(slh, workloads, name):
     return ctx, items, d_m, d_s, cfg, msgs, kidx
 
 
-def run(slh, workloads, name, steps, warmup):
+def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None):
     import torch
+    from paper_2512_23969_amd import autotune
     ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
+    path = tune_out or autotune.DEFAULT_CACHE
+    if tune:
+        best, _ = autotune.tune_and_store(slh, ctx, cfg["param"], items, d_m, d_s, cfg["batch"], path, log=log)
+    else:
+        best = (autotune.lookup(cfg["param"], cfg["batch"], path) or {}).get("best")
+    tuned = None
+    if best:
+        tuned = autotune.apply(ctx, cfg["param"], best)
+    if mode == "auto":
+        mode = {"plain": "plain", "fused": "fused"}.get(tuned or "plain", "plain")
+    m = slh.MODES[mode]
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        ctx.sign_batch(items, d_m, d_s, stream=stream)
+        ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
     torch.cuda.synchronize()
     ctx.phase_times(reset=True)
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        ctx.sign_batch(items, d_m, d_s, stream=stream)
+        ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
@@ -75,6 +87,9 @@ def run(slh, workloads, name, steps, warmup):
         "sig_per_s": cfg["batch"] * steps / elapsed,
         "phases": phases,
         "cfg": cfg,
+        "steps": steps,
+        "mode": mode,
+        "tuning": best,
     }
 
 
@@ -109,28 +124,42 @@ def cpu_baseline(name, workloads, seconds=15.0):
 # HBM bytes per k_tree launch (4096 signatures) from rocprofv3 FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0 (copy-kernel calibration); None where not measured for the
 # current kernel.
-TRAFFIC = {}
+TRAFFIC = {}  # (param, kernel) -> bytes per launch
 
 
 def roofline(param, res):
+    """Roofline of the dominant kernel: k_fused (FORS + TREE) in the fused
+    modes, k_tree in the plain mode.  Kernel time from the library's HIP
+    events around that kernel on the benchmark's stream."""
     from paper_2512_23969_amd import accounting as acc
-    ms, launches, msgs = res["phases"]["tree"]
+    phase, kernel, parts = ("fused", "k_fused", ("fors", "tree")) if res["phases"]["fused"][1] else \
+        ("tree", "k_tree", ("tree",))
+    ms, launches, msgs = res["phases"][phase]
     if launches == 0:
         return None
     per_launch_msgs = msgs / launches
-    ops_per_launch = acc.ops_per_signature(param, "tree") * per_launch_msgs
+    ops = sum(acc.ops_per_signature(param, p) for p in parts) * per_launch_msgs
+    tb = sum(acc.ops_per_signature(param, p, textbook=True) for p in parts) * per_launch_msgs
     avg_s = ms / launches / 1000.0
-    achieved = ops_per_launch / avg_s / 1e12
+    achieved = ops / avg_s / 1e12
     peak = acc.VALU_PEAK_OPS / 1e12
-    c256, c512 = acc.per_signature(param)["sha256"]["tree"], acc.per_signature(param)["sha512"]["tree"]
-    return {"bound": "alu", "kernel": "k_tree", "achieved": round(achieved, 3), "peak": round(peak, 3),
+    c = acc.per_signature(param)
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": round(peak, 3),
             "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
-            "traffic": TRAFFIC.get(param),
+            "traffic": TRAFFIC.get((param, kernel)),
             "avg_launch_ms": round(ms / launches, 4),
-            "units_per_launch": {"sha256": int(c256 * per_launch_msgs), "sha512": int(c512 * per_launch_msgs)},
+            "units_per_launch": {h: int(sum(c[h][p] for p in parts) * per_launch_msgs)
+                                 for h in ("sha256", "sha512")},
             "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512},
-            "textbook_frac": round(acc.ops_per_signature(param, "tree", textbook=True) * per_launch_msgs
-                                   / avg_s / acc.VALU_PEAK_OPS, 4)}
+            "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4)}
+
+
+def summary(acc, r, mode):
+    prm = r["cfg"]["param"]
+    return {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3), "mode": mode,
+            "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
+            "roofline": roofline(prm, r) if mode != "graph" else None,
+            "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]}}
 
 
 def main():
@@ -139,6 +168,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2_128f_4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="auto", choices=["auto", "plain", "fused", "graph"],
+                    help="execution mode; auto = the autotuned mode for the workload")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner first and store its result")
+    ap.add_argument("--tune-out", default=None, help="tuning cache file (default: the package's tuning.json)")
     ap.add_argument("--all", action="store_true", help="also time the 192f and 256f workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -163,7 +196,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log("bench: workload", args.workload)
-    res = run(slh, workloads, args.workload, args.steps, args.warmup)
+    res = run(slh, workloads, args.workload, args.steps, args.warmup, args.mode, args.tune, args.tune_out)
     param = res["cfg"]["param"]
     c256, c512 = acc.compressions_per_signature(param)
     line = {
@@ -181,27 +214,26 @@ def main():
         "data": "synthetic (seeded random keys and 32-byte messages)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "batch": res["cfg"]["batch"], "keys": res["cfg"]["keys"], "msg_bytes": 32,
-                   "mode": "plain"},
+                   "mode": res["mode"], "tuning": res["tuning"]},
         "compressions_per_s": {"sha256": round(res["sig_per_s"] * c256, 0),
                                "sha512": round(res["sig_per_s"] * c512, 0)},
         "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param) / acc.VALU_PEAK_OPS, 4),
-        "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items()},
+        "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items() if v[1]},
         "roofline": roofline(param, res),
     }
     if args.all:
+        # every batch-4096 workload in the plain per-phase path and in the
+        # batched modes (fused persistent kernel; hipGraph-captured pipeline)
         extra = {}
-        for name in ("c3_192f_4096", "c4_256f_4096x64"):
-            if name == args.workload:
-                continue
-            log("bench: workload", name)
-            steps_c = max(3, args.steps // 2)
-            r = run(slh, workloads, name, steps_c, args.warmup)
-            prm = r["cfg"]["param"]
-            extra[name] = {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3),
-                           "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
-                           "roofline": roofline(prm, r),
-                           "phase_ms_per_step": {k: round(v[0] / steps_c, 3)
-                                                 for k, v in r["phases"].items()}}
+        steps_c = max(3, args.steps // 2)
+        for name in ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64"):
+            for mode in ("plain", "fused", "graph"):
+                if name == args.workload and mode == res["mode"]:
+                    continue
+                log("bench: workload", name, mode)
+                r = run(slh, workloads, name, steps_c, args.warmup, mode,
+                        args.tune and mode == "plain" and name != args.workload, args.tune_out)
+                extra["%s/%s" % (name, mode)] = summary(acc, r, mode)
         line["extra"] = extra
     if not args.no_cpu:
         log("bench: cpu baseline")

@@ -86,8 +86,22 @@ typedef struct {
 
 typedef struct slh_ctx slh_ctx;
 
-/* Execution modes of slh_sign_batch.  Every mode produces the same bytes. */
-#define SLH_MODE_PLAIN 0u  /* per-phase kernels launched one after another */
+/* Execution modes of slh_sign_batch (bit flags).  Every mode produces the
+ * same bytes.
+ *   SLH_MODE_PLAIN  per-phase kernels (prelude, FORS, TREE, FORS pk, WOTS)
+ *                   launched one after another on the caller's stream.
+ *   SLH_MODE_FUSED  FORS and TREE work of each parameter set in one
+ *                   persistent kernel fed by a device work counter; the
+ *                   parameter sets of a mixed batch run concurrently on
+ *                   branch streams joined back into the caller's stream.
+ *   SLH_MODE_GRAPH  the launch sequence is captured once into a hipGraph
+ *                   (per batch shape, buffers and tuning) and replayed with a
+ *                   single hipGraphLaunch; combine with SLH_MODE_FUSED for the
+ *                   batched fused pipeline.  Per-phase timing is not recorded
+ *                   inside graphs. */
+#define SLH_MODE_PLAIN 0u
+#define SLH_MODE_FUSED 1u
+#define SLH_MODE_GRAPH 2u
 
 /* Fill *out with the sizes of parameter set `param`.
  * Errors: SLH_EINVAL for an unknown set or a null pointer. */
@@ -145,11 +159,34 @@ int slh_verify(uint32_t param, const uint8_t *msg, size_t msg_len, const uint8_t
                size_t sig_len, const uint8_t *pk);
 
 /* Kernel phases of the signing path, for per-phase timing. */
-#define SLH_PHASE_PRELUDE 0 /* PRF_msg, H_msg, index split           */
-#define SLH_PHASE_FORS 1    /* FORS trees, auth paths, FORS pk       */
-#define SLH_PHASE_TREE 2    /* WOTS+ chains, leaves, XMSS roots/auth */
-#define SLH_PHASE_WOTS 3    /* WOTS+ signatures of the signing leaves */
-#define SLH_NPHASES 4
+#define SLH_PHASE_PRELUDE 0 /* PRF_msg, H_msg, index split                     */
+#define SLH_PHASE_FORS 1    /* FORS trees and auth paths (plain mode)          */
+#define SLH_PHASE_TREE 2    /* WOTS+ chains, leaves, XMSS roots/auth (plain)   */
+#define SLH_PHASE_WOTS 3    /* FORS public key and WOTS+ signatures            */
+#define SLH_PHASE_FUSED 4   /* FORS and TREE in the persistent kernel (fused)  */
+#define SLH_NPHASES 5
+
+/* Per-parameter-set knobs of the signing kernels (the autotuner's search
+ * space; the paper tunes its FORS fusion per GPU with Algorithm 1).
+ *   fors_trees_per_group  FORS trees reduced together by one workgroup:
+ *                         4, 8 or 16 for 128f and 192f, 2, 4 or 8 for 256f
+ *                         (0 = default: 8, 8, 4)
+ *   wgs_per_cu            fused mode: persistent workgroups per compute unit
+ *                         (0 = as many as fit, at most 64)
+ *   keep_chains           1: the TREE phase keeps every value of the signing
+ *                         leaves' WOTS+ chains and the WOTS phase gathers the
+ *                         signature from them; 0: nothing is kept (less
+ *                         memory) and the WOTS phase recomputes the chains */
+typedef struct {
+    uint32_t fors_trees_per_group;
+    uint32_t wgs_per_cu;
+    uint32_t keep_chains;
+} slh_tuning;
+
+/* Set or read the knobs of parameter set `param` on a context.  Setting
+ * waits for the context's pending work.  Errors: SLH_EINVAL. */
+int slh_ctx_set_tuning(slh_ctx *ctx, uint32_t param, const slh_tuning *t);
+int slh_ctx_get_tuning(const slh_ctx *ctx, uint32_t param, slh_tuning *t);
 
 /* Turn per-phase timing on or off for later slh_sign_batch calls.  When on,
  * the library records a HIP event before and after every kernel it

@@ -1,0 +1,159 @@
+"""Autotuner of the signing kernels.
+
+Two stages, as in the paper's Section III-B ("Fusion Trade-offs in FORS"):
+an analytic search proposes candidate FORS groupings, then the candidates
+are timed on the GPU and the fastest is kept.
+
+* ``tree_tuning(...)`` is the paper's Algorithm 1 (Auto Tree Tuning): for a
+  per-block shared-memory budget S_max and thread limit T_max it enumerates
+  Set sizes T_set (a multiple of the leaves per tree) and fusion factors F,
+  drops configurations that use all threads and all shared memory or fewer
+  than alpha * T_max threads, and keeps the one with the fewest
+  synchronisation points, then the highest thread and memory utilisation.
+  With the RTX 4090's 48 KiB static shared memory it gives the paper's
+  Table 4.
+* ``gfx950_groups(param)`` re-expresses the same trade-off for this
+  library's FORS kernels, whose unit is a group of trees reduced by one
+  256-lane workgroup with two leaves per lane: the LDS per group must fit the
+  160 KiB of a CU, and the groups are ranked by barrier count per message.
+* ``tune(...)`` times every compiled variant (execution mode, FORS trees per
+  group, persistent workgroups per CU) on a real batch and returns the
+  fastest; results are cached in a JSON file keyed by GPU architecture,
+  parameter set and batch size.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
+
+# (n, a = log t, k) of the parameter sets (the paper's Table 1)
+FORS_SHAPE = {1: (16, 6, 33), 2: (24, 8, 33), 3: (32, 9, 35)}
+
+
+def tree_tuning(k: int, log_t: int, n: int, s_max: int, t_max: int = 1024, alpha: float = 0.6):
+    """Algorithm 1 of the paper.  Returns (best, candidates); each candidate
+    is a dict with T_set, F, U_T, U_S and sync."""
+    t = 1 << log_t
+    t_min = t
+    cand = []
+    for t_set in range(t_min, t_max + 1, t_min):
+        n_tree = t_set // t_min
+        s_set = n_tree * t * n
+        if s_set > s_max:
+            continue
+        f_max = min(s_max // s_set, k // n_tree)
+        for f in range(1, f_max + 1):
+            t_used = t_set
+            s_used = f * s_set
+            if t_used > t_max or s_used > s_max:
+                continue
+            u_t = t_used / t_max
+            u_s = s_used / s_max
+            if (u_t == 1 and u_s == 1) or u_t < alpha:
+                continue
+            sync = log_t * math.ceil(k / n_tree) / f
+            cand.append({"T_set": t_set, "F": f, "U_T": u_t, "U_S": u_s, "sync": sync})
+    if not cand:
+        return None, cand
+    best = min(cand, key=lambda c: (c["sync"], -c["U_T"], -c["U_S"]))
+    return best, cand
+
+
+COMPILED_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8)}
+
+
+def gfx950_groups(param: int, lds_bytes: int = 160 * 1024, lanes: int = 256, compiled=None):
+    """FORS groupings of this library ranked analytically for gfx950.
+
+    A group of FG trees keeps FG * 2^(a-1) level-1 nodes of n bytes in LDS
+    and is reduced by one workgroup of `lanes` lanes.  Returns a list of
+    dicts sorted by (barriers per message, idle lanes in the pair phase)."""
+    n, a, k = FORS_SHAPE[param]
+    out = []
+    for fg in compiled or COMPILED_GROUPS[param]:
+        lds = fg * (1 << (a - 1)) * n
+        if lds > lds_bytes:
+            continue
+        pairs = fg * (1 << (a - 1))
+        rounds = math.ceil(pairs / lanes)
+        idle = rounds * lanes - pairs
+        groups_per_msg = k / fg
+        barriers = groups_per_msg * a  # one per level of every group
+        out.append({"fg": fg, "lds_bytes": lds, "pair_rounds": rounds, "idle_lanes": idle,
+                    "barriers_per_msg": barriers, "wgs_per_cu_lds": lds_bytes // max(1, lds)})
+    out.sort(key=lambda c: (c["barriers_per_msg"], c["idle_lanes"]))
+    return out
+
+
+def _arch():
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def cache_key(arch: str, param: int, batch: int) -> str:
+    # batches are bucketed by powers of two
+    b = 1 << max(0, int(math.ceil(math.log2(max(1, batch)))))
+    return "%s/%d/%d" % (arch, param, b)
+
+
+def lookup(param: int, batch: int, path: str = DEFAULT_CACHE):
+    """Tuned setting for (this GPU, param, batch) or None."""
+    c = load_cache(path)
+    return c.get(cache_key(_arch(), param, batch))
+
+
+def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 3, modes=("plain", "fused"),
+         wgs=(0, 1, 2, 3), log=None):
+    """Time every compiled variant on this batch; returns (best, table)."""
+    import torch
+    table = []
+    for mode in modes:
+        for fg in slh.FORS_GROUPS[param]:
+            for wpc in (wgs if mode == "fused" else (0,)):
+                ctx.set_tuning(param, fg, wpc, 1)
+                m = slh.MODES[mode]
+                ctx.sign_batch(items, d_msgs, d_sigs, mode=m)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    ctx.sign_batch(items, d_msgs, d_sigs, mode=m)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1000.0 / reps
+                row = {"mode": mode, "fors_trees_per_group": fg, "wgs_per_cu": wpc, "keep_chains": 1,
+                       "ms": round(ms, 4)}
+                table.append(row)
+                if log:
+                    log("tune %s %s" % (param, row))
+    best = min(table, key=lambda r: r["ms"])
+    return best, table
+
+
+def tune_and_store(slh, ctx, param, items, d_msgs, d_sigs, batch, path: str = DEFAULT_CACHE, log=None):
+    best, table = tune(slh, ctx, param, items, d_msgs, d_sigs, log=log)
+    c = load_cache(path)
+    c[cache_key(_arch(), param, batch)] = {"best": best, "table": table,
+                                            "analytic": gfx950_groups(param)}
+    with open(path, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    return best, table
+
+
+def apply(ctx, param: int, setting: dict):
+    """Set the tuned knobs on a context; returns the tuned mode name."""
+    ctx.set_tuning(param, setting["fors_trees_per_group"], setting["wgs_per_cu"], setting["keep_chains"])
+    return setting["mode"]

@@ -81,19 +81,42 @@ DevKey make_devkey(uint32_t param, uint32_t n, const uint8_t* sk_seed, const uin
 
 }  // namespace
 
+// Knobs of one parameter set (see slh_tuning in slh.h).
+struct Tuning {
+  uint32_t fg = 0;          // FORS trees per workgroup (0 = default of the set)
+  uint32_t wgs_per_cu = 0;  // fused mode: persistent workgroups per CU (0 = occupancy limit)
+  uint32_t keep = 1;        // keep signing-leaf chain values for the WOTS gather
+};
+
+struct GraphKey {
+  size_t n[4];
+  const void* msgs;
+  void* sigs;
+  uint8_t* ws[4];
+  size_t ws_bytes[4];
+  uint32_t fg[4], wpc[4], keep[4];
+  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof o) == 0; }
+};
+
 struct slh_ctx {
   int device = 0;
+  int cus = 0;
   uint64_t budget = 0;
   std::string err;
   DevKey* keys = nullptr;
   uint32_t nkeys = 0, cap = 0;
   std::vector<uint32_t> key_param;
-  uint8_t* ws = nullptr;
-  size_t ws_bytes = 0;
+  uint8_t* ws[4] = {nullptr, nullptr, nullptr, nullptr};  // working memory per parameter set
+  size_t ws_bytes[4] = {0, 0, 0, 0};
+  Tuning tune[4];
   DevItem* staging = nullptr;  // pinned host copy of the items of a call
   size_t staging_cap = 0;
   hipEvent_t done = nullptr;   // end of the last call's GPU work
   bool pending = false;
+  hipStream_t cap_stream = nullptr;          // stream graphs are captured on
+  hipStream_t branch[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
   // optional per-phase timing: event pairs around every kernel launch
   bool profile = false;
   std::vector<hipEvent_t> ev_pool;
@@ -128,8 +151,8 @@ struct PhaseTimer {
   uint64_t units;
   size_t a = 0;
   bool on;
-  PhaseTimer(slh_ctx* c_, hipStream_t s_, int phase_, uint64_t units_)
-      : c(c_), s(s_), phase(phase_), units(units_), on(c_->profile) {
+  PhaseTimer(slh_ctx* c_, hipStream_t s_, int phase_, uint64_t units_, bool allowed)
+      : c(c_), s(s_), phase(phase_), units(units_), on(c_->profile && allowed) {
     if (on) a = take();
   }
   size_t take() {
@@ -149,78 +172,214 @@ struct PhaseTimer {
   }
 };
 
-// Make sure `bytes` of working memory are available (waits for pending work
-// before replacing the buffer).
-int ensure_ws(slh_ctx* c, size_t bytes) {
-  if (c->ws_bytes >= bytes) return SLH_OK;
+void drop_graphs(slh_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+  c->graphs.clear();
+}
+
+// FORS trees per workgroup that have a compiled variant, per parameter set.
+bool fg_ok(uint32_t param, uint32_t fg) {
+  if (param == 3) return fg == 2 || fg == 4 || fg == 8;
+  return fg == 4 || fg == 8 || fg == 16;
+}
+uint32_t fg_default(uint32_t param) { return param == 3 ? 4u : 8u; }
+
+template <int ID, int FG>
+int occupancy_of() {
+  static int occ = -1;
+  if (occ < 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused<ID, FG>),
+                                                     kTreeThreads, 0) != hipSuccess || nb < 1)
+      nb = 1;
+    occ = nb;
+  }
+  return occ;
+}
+template <int ID>
+int occupancy(uint32_t fg) {
+  if constexpr (ID == 3) {
+    return fg == 2 ? occupancy_of<ID, 2>() : fg == 8 ? occupancy_of<ID, 8>() : occupancy_of<ID, 4>();
+  } else {
+    return fg == 4 ? occupancy_of<ID, 4>() : fg == 16 ? occupancy_of<ID, 16>() : occupancy_of<ID, 8>();
+  }
+}
+
+// Working-memory plan of one chunk of `n` messages of parameter set ID.
+template <int ID>
+struct Plan {
+  using Q = P<ID>;
+  size_t n = 0;
+  bool fused = false, keep = true;
+  uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0;
+  size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0, total = 0;
+  static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
+  Plan(size_t n_, bool fused_, const Tuning& t, int cus) : n(n_), fused(fused_), keep(t.keep != 0) {
+    fg = t.fg ? t.fg : fg_default(ID);
+    const size_t trees = n * Q::d;
+    ntb = uint32_t((trees + kLeavesPerBlock / Q::leaves - 1) / (kLeavesPerBlock / Q::leaves));
+    nfg = uint32_t((n * Q::k + fg - 1) / fg);
+    if (fused) {
+      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg));
+      grid = std::min<uint32_t>(per_cu * uint32_t(cus), ntb + nfg);
+    } else {
+      grid = ntb;
+    }
+    o_recs = 0;
+    o_items = o_recs + up(n * sizeof(WorkRec));
+    o_stage = o_items + up(n * sizeof(DevItem));
+    o_spill = o_stage + up(size_t(grid) * stage_per_block);
+    o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
+    o_queue = o_roots + up(n * Q::k * Q::NW * 4);
+    total = o_queue + kAlign;
+  }
+};
+
+// Make sure parameter set p has `bytes` of working memory (waits for pending
+// work and drops captured graphs before replacing the buffer).
+int ensure_ws(slh_ctx* c, int p, size_t bytes) {
+  if (c->ws_bytes[p] >= bytes) return SLH_OK;
   if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
-  if (c->ws) HIPCHK(c, hipFree(c->ws));
-  c->ws = nullptr;
-  c->ws_bytes = 0;
-  hipError_t e = hipMalloc(&c->ws, bytes);
+  drop_graphs(c);
+  if (c->ws[p]) HIPCHK(c, hipFree(c->ws[p]));
+  c->ws[p] = nullptr;
+  c->ws_bytes[p] = 0;
+  hipError_t e = hipMalloc(&c->ws[p], bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, SLH_ENOMEM, "hipMalloc of working memory failed");
   }
-  c->ws_bytes = bytes;
+  c->ws_bytes[p] = bytes;
   return SLH_OK;
 }
 
+template <int ID, int FG>
+void launch_fors(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* roots, hipStream_t s) {
+  hipLaunchKernelGGL((k_fors<ID, FG>), dim3(pl.nfg), dim3(kForsThreads), 0, s, c->keys, recs,
+                     uint32_t(pl.n * P<ID>::k), sigs, roots);
+}
+template <int ID, int FG>
+void launch_fused(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
+                  uint32_t* roots, uint32_t* queue, hipStream_t s) {
+  hipLaunchKernelGGL((k_fused<ID, FG>), dim3(pl.grid), dim3(kTreeThreads), 0, s, c->keys, recs, uint32_t(pl.n),
+                     sigs, stage, spill, roots, queue, pl.ntb, pl.nfg);
+}
+
+// Enqueue one chunk on stream s.  `timing` is false while a graph is captured.
 template <int ID>
-int launch_chunk(slh_ctx* c, const DevItem* h_items, size_t count, const uint8_t* msgs, uint8_t* sigs,
-                 hipStream_t s) {
-  using L = Layout<ID>;
+int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const uint8_t* msgs, uint8_t* sigs,
+                 hipStream_t s, bool timing) {
   using Q = P<ID>;
-  uint8_t* base = c->ws;
-  WorkRec* recs = reinterpret_cast<WorkRec*>(base);
-  DevItem* items = reinterpret_cast<DevItem*>(base + L::recs(count));
-  uint32_t* stage = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count));
-  uint32_t* spill = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count) + L::stage(count));
-  uint32_t* roots = reinterpret_cast<uint32_t*>(base + L::recs(count) + L::items(count) + L::stage(count) +
-                                                L::spill(count));
-  HIPCHK(c, hipMemcpyAsync(items, h_items, count * sizeof(DevItem), hipMemcpyHostToDevice, s));
-  const uint32_t n = uint32_t(count);
+  uint8_t* base = c->ws[ID];
+  WorkRec* recs = reinterpret_cast<WorkRec*>(base + pl.o_recs);
+  DevItem* items = reinterpret_cast<DevItem*>(base + pl.o_items);
+  uint32_t* stage = reinterpret_cast<uint32_t*>(base + pl.o_stage);
+  uint32_t* spill = pl.keep ? reinterpret_cast<uint32_t*>(base + pl.o_spill) : nullptr;
+  uint32_t* roots = reinterpret_cast<uint32_t*>(base + pl.o_roots);
+  uint32_t* queue = reinterpret_cast<uint32_t*>(base + pl.o_queue);
+  HIPCHK(c, hipMemcpyAsync(items, h_items, pl.n * sizeof(DevItem), hipMemcpyHostToDevice, s));
+  const uint32_t n = uint32_t(pl.n);
   {
-    PhaseTimer t(c, s, SLH_PHASE_PRELUDE, n);
-    hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs,
-                       sigs, recs);
+    PhaseTimer t(c, s, SLH_PHASE_PRELUDE, n, timing);
+    hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs, sigs, recs,
+                       pl.fused ? queue : nullptr);
+  }
+  if (pl.fused) {
+    PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
+    if constexpr (ID == 3) {
+      if (pl.fg == 2) launch_fused<ID, 2>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+      else if (pl.fg == 8) launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+      else launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+    } else {
+      if (pl.fg == 4) launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+      else if (pl.fg == 16) launch_fused<ID, 16>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+      else launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+    }
+  } else {
+    {
+      PhaseTimer t(c, s, SLH_PHASE_FORS, n, timing);
+      if constexpr (ID == 3) {
+        if (pl.fg == 2) launch_fors<ID, 2>(c, pl, sigs, recs, roots, s);
+        else if (pl.fg == 8) launch_fors<ID, 8>(c, pl, sigs, recs, roots, s);
+        else launch_fors<ID, 4>(c, pl, sigs, recs, roots, s);
+      } else {
+        if (pl.fg == 4) launch_fors<ID, 4>(c, pl, sigs, recs, roots, s);
+        else if (pl.fg == 16) launch_fors<ID, 16>(c, pl, sigs, recs, roots, s);
+        else launch_fors<ID, 8>(c, pl, sigs, recs, roots, s);
+      }
+    }
+    {
+      PhaseTimer t(c, s, SLH_PHASE_TREE, n, timing);
+      hipLaunchKernelGGL((k_tree<ID, false>), dim3(pl.ntb), dim3(kTreeThreads), 0, s, c->keys, recs,
+                         uint32_t(n * Q::d), sigs, stage, spill, 0u, nullptr);
+    }
   }
   {
-    PhaseTimer t(c, s, SLH_PHASE_FORS, n);
-    const uint32_t nft = n * Q::k;
-    const uint32_t fg = ForsShape<ID>::FG;
-    hipLaunchKernelGGL((k_fors<ID>), dim3((nft + fg - 1) / fg), dim3(kForsThreads), 0, s, c->keys, recs, nft,
-                       sigs, roots);
+    PhaseTimer t(c, s, SLH_PHASE_WOTS, n, timing);
     hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, roots);
-  }
-  const uint32_t ntrees = n * Q::d;
-  {
-    PhaseTimer t(c, s, SLH_PHASE_TREE, n);
-    hipLaunchKernelGGL((k_tree<ID, false>), dim3(uint32_t(L::tree_blocks(count))), dim3(kTreeThreads), 0,
-                       s, c->keys, recs, ntrees, sigs, stage, spill, 0u, nullptr);
-  }
-  const uint32_t nw = n * Q::d * Q::len;
-  {
-    PhaseTimer t(c, s, SLH_PHASE_WOTS, n);
-    hipLaunchKernelGGL((k_wots<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, recs, n, sigs, spill);
+    const uint32_t nw = n * Q::d * Q::len;
+    if (pl.keep)
+      hipLaunchKernelGGL((k_wots<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, recs, n, sigs, spill);
+    else
+      hipLaunchKernelGGL((k_wots_recompute<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs);
   }
   HIPCHK(c, hipGetLastError());
   return SLH_OK;
 }
 
+// Messages per chunk for parameter set ID within `budget` bytes.
 template <int ID>
-int sign_group(slh_ctx* c, const DevItem* h_items, size_t count, const uint8_t* msgs, uint8_t* sigs,
-               hipStream_t s) {
-  using L = Layout<ID>;
-  size_t chunk = c->budget / per_message_bytes(ID);
-  if (chunk < 1) chunk = 1;
-  chunk = std::min(chunk, count);
-  int rc = ensure_ws(c, L::total(chunk));
-  if (rc) return rc;
+size_t chunk_size(slh_ctx* c, size_t count, bool fused, uint64_t budget) {
+  const Tuning& t = c->tune[ID];
+  const Plan<ID> one(1, fused, t, c->cus), big(1024, fused, t, c->cus);
+  const size_t per = (big.total - one.total) / 1023 + 1;
+  const size_t fixed = one.total > per ? one.total - per : 0;
+  size_t chunk = budget > fixed ? (budget - fixed) / per : 1;
+  chunk = std::max<size_t>(1, std::min(chunk, count));
+  return chunk;
+}
+
+template <int ID>
+int prepare_group(slh_ctx* c, size_t count, bool fused, uint64_t budget, size_t* chunk) {
+  *chunk = chunk_size<ID>(c, count, fused, budget);
+  const Plan<ID> pl(*chunk, fused, c->tune[ID], c->cus);
+  return ensure_ws(c, ID, pl.total);
+}
+
+template <int ID>
+int enqueue_group(slh_ctx* c, const DevItem* h_items, size_t count, size_t chunk, const uint8_t* msgs,
+                  uint8_t* sigs, hipStream_t s, bool fused, bool timing) {
   for (size_t off = 0; off < count; off += chunk) {
     const size_t cnt = std::min(chunk, count - off);
-    rc = launch_chunk<ID>(c, h_items + off, cnt, msgs, sigs, s);
+    const Plan<ID> pl(cnt, fused, c->tune[ID], c->cus);
+    const int rc = launch_chunk<ID>(c, pl, h_items + off, msgs, sigs, s, timing);
     if (rc) return rc;
+  }
+  return SLH_OK;
+}
+
+int enqueue_all(slh_ctx* c, const size_t per[4], const size_t start[4], const size_t chunk[4], const uint8_t* msgs,
+                uint8_t* sigs, hipStream_t s, bool fused, bool timing) {
+  int groups = 0;
+  for (int p = 1; p <= 3; p++) groups += per[p] ? 1 : 0;
+  const bool branches = fused && groups > 1;
+  if (branches) HIPCHK(c, hipEventRecord(c->fork, s));
+  for (int p = 1; p <= 3 ; p++) {
+    if (!per[p]) continue;
+    hipStream_t b = s;
+    if (branches) {
+      b = c->branch[p];
+      HIPCHK(c, hipStreamWaitEvent(b, c->fork, 0));
+    }
+    int rc = SLH_OK;
+    if (p == 1) rc = enqueue_group<1>(c, c->staging + start[1], per[1], chunk[1], msgs, sigs, b, fused, timing);
+    if (p == 2) rc = enqueue_group<2>(c, c->staging + start[2], per[2], chunk[2], msgs, sigs, b, fused, timing);
+    if (p == 3) rc = enqueue_group<3>(c, c->staging + start[3], per[3], chunk[3], msgs, sigs, b, fused, timing);
+    if (rc) return rc;
+    if (branches) {
+      HIPCHK(c, hipEventRecord(c->join[p], b));
+      HIPCHK(c, hipStreamWaitEvent(s, c->join[p], 0));
+    }
   }
   return SLH_OK;
 }
@@ -327,11 +486,20 @@ int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
   c->device = device;
   c->budget = hbm_budget ? hbm_budget : (uint64_t(8) << 30);
   e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  // all streams at the default priority
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  for (int p = 1; p <= 3 && e == hipSuccess; p++) {
+    e = hipStreamCreateWithFlags(&c->branch[p], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[p], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
-    delete c;
+    slh_ctx_destroy(c);
     return hip_fail(nullptr, e, "context set-up");
   }
+  for (int p = 1; p <= 3; p++) c->tune[p].fg = fg_default(uint32_t(p));
   *out = c;
   return SLH_OK;
 }
@@ -340,10 +508,18 @@ int slh_ctx_destroy(slh_ctx* c) {
   if (!c) return SLH_OK;
   (void)hipSetDevice(c->device);
   if (c->pending) (void)hipEventSynchronize(c->done);
-  if (c->ws) (void)hipFree(c->ws);
+  (void)hipDeviceSynchronize();
+  drop_graphs(c);
+  for (int p = 0; p < 4; p++) {
+    if (c->ws[p]) (void)hipFree(c->ws[p]);
+    if (c->branch[p]) (void)hipStreamDestroy(c->branch[p]);
+    if (c->join[p]) (void)hipEventDestroy(c->join[p]);
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->keys) (void)hipFree(c->keys);
   if (c->staging) (void)hipHostFree(c->staging);
   if (c->done) (void)hipEventDestroy(c->done);
+  if (c->fork) (void)hipEventDestroy(c->fork);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return SLH_OK;
@@ -423,7 +599,7 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (count == 0) return SLH_OK;
   if (!items || !sigs) return fail(c, SLH_EINVAL, "null items or signature buffer");
-  if (mode != SLH_MODE_PLAIN) return fail(c, SLH_EINVAL, "unknown mode");
+  if (mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH)) return fail(c, SLH_EINVAL, "unknown mode");
   if (reinterpret_cast<uintptr_t>(sigs) % 16) return fail(c, SLH_EINVAL, "signature buffer not 16-byte aligned");
   // validation, and grouping by parameter set
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
@@ -449,9 +625,11 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
     if (ranges[i].first < ranges[i - 1].second) return fail(c, SLH_EINVAL, "signature ranges overlap");
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool fused = (mode & SLH_MODE_FUSED) != 0, graph = (mode & SLH_MODE_GRAPH) != 0;
   // the pinned staging copy of the items may still be read by the previous call
   if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
   if (c->staging_cap < count) {
+    drop_graphs(c);
     if (c->staging) HIPCHK(c, hipHostFree(c->staging));
     c->staging = nullptr;
     c->staging_cap = 0;
@@ -468,16 +646,86 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
     d.param = it.param; d.key_slot = it.key_slot; d.msg_off = it.msg_off; d.msg_len = it.msg_len;
     d.sig_off = it.sig_off;
   }
+  // working memory: the budget is shared by the parameter sets present
+  int groups = 0;
+  for (int p = 1; p <= 3; p++) groups += per[p] ? 1 : 0;
+  const uint64_t share = c->budget / uint64_t(groups);
+  size_t chunk[4] = {0, 0, 0, 0};
   int rc = SLH_OK;
-  if (per[1] && !rc) rc = sign_group<1>(c, c->staging + start[1], per[1], msgs, sigs, s);
-  if (per[2] && !rc) rc = sign_group<2>(c, c->staging + start[2], per[2], msgs, sigs, s);
-  if (per[3] && !rc) rc = sign_group<3>(c, c->staging + start[3], per[3], msgs, sigs, s);
+  if (per[1] && !rc) rc = prepare_group<1>(c, per[1], fused, share, &chunk[1]);
+  if (per[2] && !rc) rc = prepare_group<2>(c, per[2], fused, share, &chunk[2]);
+  if (per[3] && !rc) rc = prepare_group<3>(c, per[3], fused, share, &chunk[3]);
   if (rc) return rc;
+  if (!graph) {
+    rc = enqueue_all(c, per, start, chunk, msgs, sigs, s, fused, true);
+    if (rc) return rc;
+  } else {
+    GraphKey key;
+    std::memset(&key, 0, sizeof key);
+    for (int p = 1; p <= 3; p++) {
+      key.n[p] = per[p];
+      key.ws[p] = c->ws[p];
+      key.ws_bytes[p] = c->ws_bytes[p];
+      key.fg[p] = c->tune[p].fg;
+      key.wpc[p] = c->tune[p].wgs_per_cu;
+      key.keep[p] = c->tune[p].keep;
+    }
+    key.n[0] = fused ? 1 : 0;
+    key.msgs = msgs;
+    key.sigs = sigs;
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : c->graphs)
+      if (g.first == key) exec = g.second;
+    if (!exec) {
+      HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_all(c, per, start, chunk, msgs, sigs, c->cap_stream, fused, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+      if (c->graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(c->graphs.front().second);
+        c->graphs.erase(c->graphs.begin());
+      }
+      c->graphs.emplace_back(key, exec);
+    }
+    HIPCHK(c, hipGraphLaunch(exec, s));
+  }
   HIPCHK(c, hipEventRecord(c->done, s));
   c->pending = true;
   return SLH_OK;
 }
 
+int slh_ctx_set_tuning(slh_ctx* c, uint32_t param, const slh_tuning* t) {
+  Sizes sz;
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (!t || !sizes_of(param, &sz)) return fail(c, SLH_EINVAL, "unknown parameter set or null tuning");
+  const uint32_t fg = t->fors_trees_per_group ? t->fors_trees_per_group : fg_default(param);
+  if (!fg_ok(param, fg)) return fail(c, SLH_EINVAL, "no compiled FORS variant with that many trees per group");
+  if (t->wgs_per_cu > 64) return fail(c, SLH_EINVAL, "wgs_per_cu above 64");
+  if (t->keep_chains > 1) return fail(c, SLH_EINVAL, "keep_chains must be 0 or 1");
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  drop_graphs(c);
+  c->tune[param].fg = fg;
+  c->tune[param].wgs_per_cu = t->wgs_per_cu;
+  c->tune[param].keep = t->keep_chains;
+  return SLH_OK;
+}
+
+int slh_ctx_get_tuning(const slh_ctx* c, uint32_t param, slh_tuning* t) {
+  Sizes sz;
+  if (!c || !t || !sizes_of(param, &sz)) return fail(nullptr, SLH_EINVAL, "null argument or unknown parameter set");
+  t->fors_trees_per_group = c->tune[param].fg;
+  t->wgs_per_cu = c->tune[param].wgs_per_cu;
+  t->keep_chains = c->tune[param].keep;
+  return SLH_OK;
+}
 
 int slh_keygen(uint32_t param, const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
   if (!seed || !pk || !sk) return fail(nullptr, SLH_EINVAL, "null pointer");

@@ -190,9 +190,10 @@ __device__ void split_digest(const uint32_t digest[16], uint16_t* indices, uint6
 template <int ID>
 __global__ void k_prelude(const DevKey* __restrict__ keys, const DevItem* __restrict__ items,
                           uint32_t count, const uint8_t* __restrict__ msgs, uint8_t* sigs,
-                          WorkRec* __restrict__ recs) {
+                          WorkRec* __restrict__ recs, uint32_t* queue) {
   constexpr int NW = P<ID>::NW;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && queue) *queue = 0u;  // work counter of the fused kernel of this batch
   if (i >= count) return;
   const DevItem it = items[i];
   const DevKey& K = keys[it.key_slot];
@@ -230,20 +231,21 @@ __global__ void k_prelude(const DevKey* __restrict__ keys, const DevItem* __rest
 // same reason: more independent nodes per synchronisation).
 template <int ID>
 struct ForsShape {
-  // trees per workgroup: 8 x 32 pairs (128f), 8 x 128 (192f), 4 x 256 (256f)
+  static constexpr int PAIRS = 1 << (P<ID>::a - 1);  // level-1 nodes per tree
+  // default trees per workgroup: 8 x 32 pairs (128f), 8 x 128 (192f), 4 x 256 (256f)
   static constexpr int FG = ID == 3 ? 4 : 8;
-  static constexpr int PAIRS = 1 << (P<ID>::a - 1);
 };
 
-template <int ID>
-__global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict__ keys,
-                                                       WorkRec* __restrict__ recs, uint32_t ntrees,
-                                                       uint8_t* sigs, uint32_t* __restrict__ roots) {
+// One group of FG trees (flat tree ids group*FG ...).  `node` is LDS of
+// FG * PAIRS * NW words.  All threads of the workgroup must call it.
+template <int ID, int FG>
+__device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, const WorkRec* __restrict__ recs,
+                           uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ roots, uint32_t group,
+                           uint32_t* node) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, A = Q::a, KT = Q::k;
-  constexpr int FG = ForsShape<ID>::FG, PAIRS = ForsShape<ID>::PAIRS;
-  __shared__ uint32_t node[FG * PAIRS * NW];
-  const uint32_t ft0 = blockIdx.x * FG;
+  constexpr int PAIRS = ForsShape<ID>::PAIRS;
+  const uint32_t ft0 = group * FG;
 
   // pair phase
   for (int q = threadIdx.x; q < FG * PAIRS; q += kForsThreads) {
@@ -315,6 +317,14 @@ __global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict_
   }
 }
 
+template <int ID, int FG>
+__global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict__ keys,
+                                                       const WorkRec* __restrict__ recs, uint32_t ntrees,
+                                                       uint8_t* sigs, uint32_t* __restrict__ roots) {
+  __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * P<ID>::NW];
+  fors_group<ID, FG>(keys, recs, ntrees, sigs, roots, blockIdx.x, node);
+}
+
 // FORS public key T_k(FORS_ROOTS address, roots) of each message, one lane
 // per message, from the roots the FORS kernel left in HBM.
 template <int ID>
@@ -364,7 +374,7 @@ __device__ __forceinline__ TreeJob sign_job(const DevKey* keys, WorkRec* recs, u
   }
   J.sig_xmss = sigs + W.sig_off + Q::ht_off + size_t(layer) * Q::xmss_bytes;
   J.root_out = (layer + 1 < uint32_t(Q::d)) ? W.roots[layer] : nullptr;
-  J.spill = spill + size_t(ftree) * Q::len * 16 * Q::NW;
+  J.spill = spill ? spill + size_t(ftree) * Q::len * 16 * Q::NW : nullptr;
   return J;
 }
 
@@ -389,20 +399,20 @@ __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t
   }
 }
 
-// KEYGEN = true: a single tree (layer d-1, tree 0) whose root is written to
-// root_out; otherwise trees are taken from the batch's work records.
+// One block of 64 leaves (TPB trees, flat tree ids block*TPB ...).  KEYGEN:
+// a single tree (layer d-1, tree 0) whose root goes to root_out; otherwise
+// trees come from the batch's work records.  `st` is this workgroup's
+// chain-end staging (len * 64 * NW words).  All threads must call it; wave 0
+// finishes the block (T_len and the XMSS levels) while the others return.
 template <int ID, bool KEYGEN>
-__global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict__ keys,
-                                                       WorkRec* __restrict__ recs, uint32_t ntrees,
-                                                       uint8_t* sigs, uint32_t* __restrict__ stage,
-                                                       uint32_t* __restrict__ spill,
-                                                       uint32_t key_slot, uint32_t* root_out) {
+__device__ __forceinline__ void tree_block(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t ntrees,
+                           uint8_t* sigs, uint32_t* __restrict__ st, uint32_t* __restrict__ spill,
+                           uint32_t key_slot, uint32_t* root_out, uint32_t block) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
   constexpr int TPB = kLeavesPerBlock / LV;  // trees per block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t tree0 = blockIdx.x * TPB;
-  uint32_t* st = stage + size_t(blockIdx.x) * LEN * kLeavesPerBlock * NW;
+  const uint32_t tree0 = block * TPB;
 
   auto job_of = [&](uint32_t lt) -> TreeJob {
     if constexpr (KEYGEN) {
@@ -479,6 +489,60 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
   if (valid && kp == 0 && J.root_out) store_words<NW>(J.root_out, v);
 }
 
+template <int ID, bool KEYGEN>
+__global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict__ keys,
+                                                       WorkRec* __restrict__ recs, uint32_t ntrees,
+                                                       uint8_t* sigs, uint32_t* __restrict__ stage,
+                                                       uint32_t* __restrict__ spill,
+                                                       uint32_t key_slot, uint32_t* root_out) {
+  uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
+  tree_block<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ fused
+// Persistent kernel of one parameter set: workgroups take work items from a
+// device counter until the list is exhausted.  Items [0, ntb) are TREE
+// blocks, items [ntb, ntb + nfg) FORS groups; the long TREE blocks go first
+// and the short FORS groups fill the tail.  Chain-end staging is indexed by
+// the workgroup, not the item, so it scales with the grid, not the batch.
+// The counter is zeroed by k_prelude of the same batch.  Every workgroup
+// leaves as soon as the counter passes the end of the list.
+// Waves per SIMD the fused kernel is compiled for (bounds its VGPRs): four
+// for 128f (at most 128 VGPRs, like the plain TREE kernel), three otherwise.
+template <int ID>
+struct FusedOcc {
+  static constexpr int waves = ID == 1 ? 4 : 3;
+};
+
+template <int ID, int FG>
+__global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(const DevKey* __restrict__ keys,
+                                                        WorkRec* __restrict__ recs, uint32_t nmsg,
+                                                        uint8_t* sigs, uint32_t* __restrict__ stage,
+                                                        uint32_t* __restrict__ spill,
+                                                        uint32_t* __restrict__ roots, uint32_t* queue,
+                                                        uint32_t ntb, uint32_t nfg) {
+  static_assert(kTreeThreads == kForsThreads, "one workgroup shape for both item kinds");
+  using Q = P<ID>;
+  __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * Q::NW];
+  __shared__ uint32_t item;
+  uint32_t* st = stage + size_t(blockIdx.x) * Q::len * kLeavesPerBlock * Q::NW;
+  const uint32_t total = ntb + nfg;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t it = item;
+    __syncthreads();  // everyone holds `it` before thread 0 may overwrite `item`
+    if (it >= total) break;
+    if (it < ntb) {
+      // waves 1..3 return from the block after phase 1 and wait at the next
+      // barrier while wave 0 finishes T_len and the XMSS levels
+      tree_block<ID, false>(keys, recs, nmsg * Q::d, sigs, st, spill, 0u, nullptr, it);
+    } else {
+      fors_group<ID, FG>(keys, recs, nmsg * Q::k, sigs, roots, it - ntb, node);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ WOTS
 // One lane per (message, layer, chain): digit of the layer's message
 // (FORS pk for layer 0, root of layer j-1 otherwise) with the checksum
@@ -509,6 +573,48 @@ __global__ void k_wots(const WorkRec* __restrict__ recs, uint32_t count, uint8_t
   uint32_t v[NW];
   load_words<NW>(src, v);
   store_be<NW>(sigs + W.sig_off + Q::ht_off + size_t(layer) * Q::xmss_bytes + c * Q::n, v);
+}
+
+// WOTS+ signatures recomputed instead of gathered (for contexts that do not
+// keep the chain values of the signing leaves): one lane per chain runs PRF
+// and then `digit` F steps (FIPS 205 Algorithm 7).
+template <int ID>
+__global__ void k_wots_recompute(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                 uint32_t count, uint8_t* sigs) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t total = count * Q::d * LEN;
+  if (gid >= total) return;
+  const uint32_t ftree = gid / LEN, c = gid - ftree * LEN;
+  const TreeJob J = sign_job<ID>(keys, recs, sigs, nullptr, ftree);
+  const uint32_t msg = ftree / Q::d, layer = ftree - msg * Q::d;
+  const WorkRec& W = recs[msg];
+  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
+  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
+  uint32_t digit;
+  if (c < uint32_t(Q::len1)) {
+    digit = nib(c);
+  } else {
+    uint32_t csum = 0;
+    for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
+    csum <<= 4;
+    digit = (csum >> (12 - 4 * (c - Q::len1))) & 15u;
+  }
+  uint32_t mid[8], sks[NW], x[NW];
+  load_words<8>(J.key->mid256, mid);
+  load_words<NW>(J.key->sk_seed, sks);
+  const uint32_t kp = uint32_t(J.sign_leaf);
+  thF<ID>(mid, make_adrs(layer, J.tree, A_WOTS_PRF, kp, c, 0), sks, x);
+  Adrs A = make_adrs(layer, J.tree, A_WOTS_HASH, kp, c, 0);
+  for (uint32_t st = 0; st < digit; st++) {
+    A.tail = st << 16;
+    uint32_t y[NW];
+    th256<NW, NW>(mid, A, x, y);
+#pragma unroll
+    for (int u = 0; u < NW; u++) x[u] = y[u];
+  }
+  store_be<NW>(J.sig_xmss + c * Q::n, x);
 }
 
 // ------------------------------------------------------------------ verify

@@ -17,10 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libslh.so")
 SHA2_128F, SHA2_192F, SHA2_256F = 1, 2, 3
 NAMES = {1: "128f", 2: "192f", 3: "256f"}
 IDS = {v: k for k, v in NAMES.items()}
-MODE_PLAIN = 0
+MODE_PLAIN, MODE_FUSED, MODE_GRAPH = 0, 1, 2
+MODES = {"plain": MODE_PLAIN, "fused": MODE_FUSED, "graph": MODE_GRAPH | MODE_FUSED,
+         "graph-plain": MODE_GRAPH}
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
-PHASES = ("prelude", "fors", "tree", "wots")
+PHASES = ("prelude", "fors", "tree", "wots", "fused")
+# compiled FORS group sizes per parameter set
+FORS_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8)}
 
 ITEM_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"),
                        ("msg_len", "<u8"), ("sig_off", "<u8")])
@@ -31,6 +35,11 @@ class SlhError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("slh error %d: %s" % (code, msg))
         self.code = code
+
+
+class slh_tuning(ctypes.Structure):
+    _fields_ = [("fors_trees_per_group", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
+                ("keep_chains", ctypes.c_uint32)]
 
 
 class slh_sizes(ctypes.Structure):
@@ -58,6 +67,8 @@ def _load():
     L.slh_sign_batch.argtypes = [vp, vp, u32, vp, u64, vp, u64, u32, vp]
     L.slh_verify.argtypes = [u32, ctypes.c_char_p, sz, ctypes.c_char_p, sz, ctypes.c_char_p]
     L.slh_ctx_profile.argtypes = [vp, ctypes.c_int]
+    L.slh_ctx_set_tuning.argtypes = [vp, u32, ctypes.POINTER(slh_tuning)]
+    L.slh_ctx_get_tuning.argtypes = [vp, u32, ctypes.POINTER(slh_tuning)]
     L.slh_ctx_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                       ctypes.POINTER(u64), ctypes.c_int]
     return L
@@ -138,6 +149,16 @@ class Context:
                self.h)
         self.key_params += [param] * (len(blob) // skb)
         return first.value
+
+    def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0,
+                   keep_chains: int = 1):
+        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains)
+        _check(lib.slh_ctx_set_tuning(self.h, int(param), ctypes.byref(t)), self.h)
+
+    def get_tuning(self, param: int) -> dict:
+        t = slh_tuning()
+        _check(lib.slh_ctx_get_tuning(self.h, int(param), ctypes.byref(t)), self.h)
+        return {f: getattr(t, f) for f, _ in t._fields_}
 
     def profile(self, enable: bool = True):
         """Record HIP events around every kernel of later sign_batch calls."""
