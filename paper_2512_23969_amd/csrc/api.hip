@@ -228,7 +228,8 @@ struct Plan {
     o_recs = 0;
     o_items = o_recs + up(n * sizeof(WorkRec));
     o_stage = o_items + up(n * sizeof(DevItem));
-    o_spill = o_stage + up(size_t(grid) * stage_per_block);
+    // the fused kernel double-buffers its staging per workgroup
+    o_spill = o_stage + up(size_t(grid) * stage_per_block * (fused ? 2 : 1));
     o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
     o_queue = o_roots + up(n * Q::k * Q::NW * 4);
     total = o_queue + kAlign;

@@ -399,63 +399,87 @@ __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t
   }
 }
 
-// One block of 64 leaves (TPB trees, flat tree ids block*TPB ...).  KEYGEN:
-// a single tree (layer d-1, tree 0) whose root goes to root_out; otherwise
-// trees come from the batch's work records.  `st` is this workgroup's
-// chain-end staging (len * 64 * NW words).  All threads must call it; wave 0
-// finishes the block (T_len and the XMSS levels) while the others return.
+// Chain chunks of wave 0 in a TREE block.  Wave 0 also runs T_len and the
+// XMSS levels of the block (10 + 3 SHA-256, 13 and 22 SHA-512 compressions,
+// about 13, 48 and 81 chain-step equivalents), so it takes fewer of the len
+// chunks of 16 compressions, and the other three waves share the rest.
+template <int ID>
+struct TreeSplit {
+  static constexpr int wave0 = ID == 1 ? 8 : (ID == 2 ? 10 : 13);
+};
+
+// Phase 1 of a block of 64 leaves (TPB trees, flat tree ids block*TPB ...):
+// the WOTS+ chains, one lane per chain, chain ends to `st` (len * 64 * NW
+// words).  KEYGEN: a single tree (layer d-1, tree 0); otherwise trees come
+// from the batch's work records.
 template <int ID, bool KEYGEN>
-__device__ __forceinline__ void tree_block(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t ntrees,
-                           uint8_t* sigs, uint32_t* __restrict__ st, uint32_t* __restrict__ spill,
-                           uint32_t key_slot, uint32_t* root_out, uint32_t block) {
+__device__ __forceinline__ TreeJob tree_job(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                            uint8_t* sigs, uint32_t* spill, uint32_t key_slot,
+                                            uint32_t* root_out, uint32_t ftree) {
+  if constexpr (KEYGEN) {
+    TreeJob J;
+    J.key = &keys[key_slot];
+    J.layer = P<ID>::d - 1;
+    J.tree = 0;
+    J.sign_leaf = -1;
+    J.sig_xmss = nullptr;
+    J.root_out = root_out;
+    J.spill = nullptr;
+    return J;
+  } else {
+    return sign_job<ID>(keys, recs, sigs, spill, ftree);
+  }
+}
+
+template <int ID, bool KEYGEN>
+__device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                            uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
+                                            uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
+                                            uint32_t block) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
-  constexpr int TPB = kLeavesPerBlock / LV;  // trees per block
+  constexpr int NW = Q::NW, LEN = Q::len, LV = Q::leaves;
+  constexpr int TPB = kLeavesPerBlock / LV;
+  constexpr int W0 = TreeSplit<ID>::wave0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tree0 = block * TPB;
-
-  auto job_of = [&](uint32_t lt) -> TreeJob {
-    if constexpr (KEYGEN) {
-      TreeJob J;
-      J.key = &keys[key_slot];
-      J.layer = Q::d - 1;
-      J.tree = 0;
-      J.sign_leaf = -1;
-      J.sig_xmss = nullptr;
-      J.root_out = root_out;
-      J.spill = nullptr;
-      return J;
-    } else {
-      return sign_job<ID>(keys, recs, sigs, spill, tree0 + lt);
-    }
-  };
-
-  // phase 1: chain c of leaf `lane` for c = wave, wave + 4, ...
-  {
-    const uint32_t lt = lane / LV, kp = lane % LV;
-    const bool valid = tree0 + lt < ntrees;
-    if (valid) {
-      const TreeJob J = job_of(lt);
-      uint32_t mid[8], sks[NW];
-      load_words<8>(J.key->mid256, mid);
-      load_words<NW>(J.key->sk_seed, sks);
-      const bool keepit = J.spill != nullptr && int32_t(kp) == J.sign_leaf;
-      for (int c = wave; c < LEN; c += kTreeThreads / 64) {
-        uint32_t x[NW];
-        wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keepit ? J.spill + c * 16 * NW : nullptr, x);
-        store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
-      }
-    }
+  const uint32_t lt = lane / LV, kp = lane % LV;
+  if (tree0 + lt >= ntrees) return;
+  const TreeJob J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, tree0 + lt);
+  uint32_t mid[8], sks[NW];
+  load_words<8>(J.key->mid256, mid);
+  load_words<NW>(J.key->sk_seed, sks);
+  const bool keepit = J.spill != nullptr && int32_t(kp) == J.sign_leaf;
+  // wave 0: chunks 0 .. W0-1; waves 1..3: chunks W0 + (wave - 1) + 3 i
+  const int c0 = wave == 0 ? 0 : W0 + wave - 1;
+  const int cend = wave == 0 ? W0 : LEN;
+  const int cstep = wave == 0 ? 1 : 3;
+  for (int c = c0; c < cend; c += cstep) {
+    uint32_t x[NW];
+    wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keepit ? J.spill + c * 16 * NW : nullptr, x);
+    store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
   }
-  __syncthreads();
-  if (wave != 0) return;
-  // phase 2: one lane per leaf computes T_len over its chain ends
+}
+
+// Phases 2 and 3 of a block, run by one wave: T_len of each leaf over its
+// chain ends, then the XMSS levels inside the wave (the node of level z lives
+// in the lanes with kp % 2^z == 0, its partner is 2^(z-1) lanes up); auth
+// nodes and the root are written where they are computed.
+template <int ID, bool KEYGEN>
+__device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                            uint32_t ntrees, uint8_t* sigs, const uint32_t* __restrict__ st,
+                                            uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
+                                            uint32_t block) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
+  constexpr int TPB = kLeavesPerBlock / LV;
+  const int lane = threadIdx.x & 63;
+  const uint32_t tree0 = block * TPB;
   const uint32_t lt = lane / LV, kp = lane % LV;
   const bool valid = tree0 + lt < ntrees;
   uint32_t v[NW];
   TreeJob J{};
   if (valid) {
-    J = job_of(lt);
+    J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, tree0 + lt);
     auto get = [&](int wi) -> uint32_t {
       const int c = wi / NW, u = wi - c * NW;
       return st[(c * kLeavesPerBlock + lane) * NW + u];
@@ -465,8 +489,6 @@ __device__ __forceinline__ void tree_block(const DevKey* __restrict__ keys, Work
 #pragma unroll
     for (int u = 0; u < NW; u++) v[u] = 0;
   }
-  // phase 3: XMSS levels inside the wave; node of level z lives in lanes
-  // with kp % 2^z == 0, its partner is 2^(z-1) lanes up.
 #pragma unroll 1
   for (int z = 1; z <= HP; z++) {
     const uint32_t span = 1u << (z - 1);
@@ -496,17 +518,24 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
                                                        uint32_t* __restrict__ spill,
                                                        uint32_t key_slot, uint32_t* root_out) {
   uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
-  tree_block<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x);
+  tree_chains<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x);
+  __syncthreads();
+  if ((threadIdx.x >> 6) == 0)
+    tree_finish<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ fused
 // Persistent kernel of one parameter set: workgroups take work items from a
 // device counter until the list is exhausted.  Items [0, ntb) are TREE
 // blocks, items [ntb, ntb + nfg) FORS groups; the long TREE blocks go first
-// and the short FORS groups fill the tail.  Chain-end staging is indexed by
-// the workgroup, not the item, so it scales with the grid, not the batch.
-// The counter is zeroed by k_prelude of the same batch.  Every workgroup
-// leaves as soon as the counter passes the end of the list.
+// and the short FORS groups fill the tail.  TREE blocks are software
+// pipelined: while all four waves run the chains of block i, wave 0 also
+// finishes block i-1 (T_len and the XMSS levels) from the other half of the
+// workgroup's double-buffered chain-end staging, so no wave waits for
+// another between blocks.  Staging is indexed by the workgroup, so it scales
+// with the grid, not the batch.  The counter is zeroed by k_prelude of the
+// same batch; every workgroup leaves once the counter passes the end.
+//
 // Waves per SIMD the fused kernel is compiled for (bounds its VGPRs): four
 // for 128f (at most 128 VGPRs, like the plain TREE kernel), three otherwise.
 template <int ID>
@@ -515,32 +544,41 @@ struct FusedOcc {
 };
 
 template <int ID, int FG>
-__global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(const DevKey* __restrict__ keys,
-                                                        WorkRec* __restrict__ recs, uint32_t nmsg,
-                                                        uint8_t* sigs, uint32_t* __restrict__ stage,
-                                                        uint32_t* __restrict__ spill,
-                                                        uint32_t* __restrict__ roots, uint32_t* queue,
-                                                        uint32_t ntb, uint32_t nfg) {
+__global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
+    const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg, uint8_t* sigs,
+    uint32_t* __restrict__ stage, uint32_t* __restrict__ spill, uint32_t* __restrict__ roots, uint32_t* queue,
+    uint32_t ntb, uint32_t nfg) {
   static_assert(kTreeThreads == kForsThreads, "one workgroup shape for both item kinds");
   using Q = P<ID>;
+  constexpr size_t SW = size_t(Q::len) * kLeavesPerBlock * Q::NW;  // words of one staging buffer
   __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * Q::NW];
   __shared__ uint32_t item;
-  uint32_t* st = stage + size_t(blockIdx.x) * Q::len * kLeavesPerBlock * Q::NW;
-  const uint32_t total = ntb + nfg;
+  uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * SW;
+  const uint32_t total = ntb + nfg, ntrees = nmsg * Q::d;
+  const bool w0 = (threadIdx.x >> 6) == 0;
+  uint32_t pend = 0xffffffffu;  // TREE block waiting for its finish (uniform)
+  uint32_t cur = 0;             // staging buffer of the next TREE block (uniform)
   for (;;) {
     if (threadIdx.x == 0) item = atomicAdd(queue, 1u);
     __syncthreads();
     const uint32_t it = item;
     __syncthreads();  // everyone holds `it` before thread 0 may overwrite `item`
     if (it >= total) break;
+    if (pend != 0xffffffffu) {
+      // finish the previous TREE block while the other waves start this item
+      if (w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u, nullptr, pend);
+      pend = 0xffffffffu;
+    }
     if (it < ntb) {
-      // waves 1..3 return from the block after phase 1 and wait at the next
-      // barrier while wave 0 finishes T_len and the XMSS levels
-      tree_block<ID, false>(keys, recs, nmsg * Q::d, sigs, st, spill, 0u, nullptr, it);
+      tree_chains<ID, false>(keys, recs, ntrees, sigs, st0 + cur * SW, spill, 0u, nullptr, it);
+      pend = it;
+      cur ^= 1;
     } else {
       fors_group<ID, FG>(keys, recs, nmsg * Q::k, sigs, roots, it - ntb, node);
     }
   }
+  if (pend != 0xffffffffu && w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u,
+                                                        nullptr, pend);
 }
 
 // ------------------------------------------------------------------ WOTS
