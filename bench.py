@@ -127,6 +127,65 @@ def cpu_baseline(name, workloads, seconds=15.0):
 TRAFFIC = {}  # (param, kernel) -> bytes per launch
 
 
+def serve_bench(slh, workloads, n, rates, log):
+    """Serving workload: n requests, parameter set 50/30/20 % 128f/192f/256f,
+    256 device-resident keys (128/77/51), log-normal message lengths (median
+    256 B, 32 B - 16 KiB), random bytes.  First all requests at time 0 (the
+    saturated rate), then Poisson arrivals at fractions of that rate.
+    Latency = completion - arrival, PCIe transfers included (messages in from
+    host memory, signatures out to host memory)."""
+    import numpy as np
+    import torch
+    keys_per_set = (128, 77, 51)
+    t0 = time.perf_counter()
+    reqs = workloads.serving_requests(n, keys_per_set=keys_per_set)
+    params = [p for p, _, _ in reqs]
+    kidx = [k for _, k, _ in reqs]
+    msgs = [m for _, _, m in reqs]
+    log("serve: %d requests generated in %.1f s" % (n, time.perf_counter() - t0))
+    srv = slh.Server(0, lanes=3, max_batch=4096, max_wait_us=2000, mode=slh.MODE_FUSED)
+    slots = {}
+    sks = {}
+    for p, cnt in zip((1, 2, 3), keys_per_set):
+        sks[p] = [slh.keygen(p, workloads.key_seed(p, 1000 + i))[1] for i in range(cnt)]
+        slots[p] = srv.add_keys(p, sks[p])
+    ks = [slots[p] + k for p, k in zip(params, kidx)]
+    out = {"requests": n, "mix": "50/30/20 % 128f/192f/256f", "keys": 256,
+           "msg_len": "log-normal, median 256 B, clipped to [32, 16384]", "lanes": 3, "max_batch": 4096,
+           "max_wait_us": 2000, "mode": "fused", "latency": "arrival to completion, host buffers (PCIe included)",
+           "points": []}
+    reqs0, blob = slh.trace(params, ks, msgs, [0.0] * n)
+    sigs, lat, st = srv.replay(reqs0, blob)
+    sat = st["sig_per_s"]
+    out["saturated_sig_per_s"] = round(sat, 1)
+    log("serve: saturated %.0f sig/s, %d launches" % (sat, st["launches"]))
+    # bit-exactness of the served signatures: every request against the same
+    # requests signed as one plain batch (alone vs in the mix)
+    with slh.Context(0) as ctx:
+        for p in (1, 2, 3):
+            ctx.add_keys(p, sks[p])
+        chk = list(range(0, n, max(1, n // 4000)))
+        ref = slh.sign_messages(ctx, [params[i] for i in chk], [ks[i] for i in chk], [msgs[i] for i in chk])
+    bad = 0
+    for j, i in enumerate(chk):
+        sb = slh.sizes(params[i])["sig_bytes"]
+        o = int(reqs0[i]["sig_off"])
+        bad += sigs[o:o + sb].tobytes() != ref[j]
+    out["checked_against_plain_batch"] = len(chk)
+    out["mismatches"] = int(bad)
+    for f in rates:
+        arr = workloads.poisson_arrivals(n, f * sat)
+        r, blob = slh.trace(params, ks, msgs, arr)
+        _, lat, st = srv.replay(r, blob, skip=min(1000, n // 10))
+        pt = {"load": f, "offered_sig_per_s": round(f * sat, 1), "sig_per_s": round(st["sig_per_s"], 1),
+              "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
+              "mean_batch": round(st["mean_batch"], 1)}
+        out["points"].append(pt)
+        log("serve: %s" % pt)
+    srv.close()
+    return out
+
+
 def roofline(param, res):
     """Roofline of the dominant kernel: k_fused (FORS + TREE) in the fused
     modes, k_tree in the plain mode.  Kernel time from the library's HIP
@@ -175,6 +234,8 @@ def main():
     ap.add_argument("--all", action="store_true", help="also time the 192f and 256f workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-n", type=int, default=100000, help="requests of the serving workload (0 = skip)")
+    ap.add_argument("--serve-rates", default="0.25,0.5,0.75,0.9,1.0,1.2")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
@@ -235,6 +296,10 @@ def main():
                         args.tune and mode == "plain" and name != args.workload, args.tune_out)
                 extra["%s/%s" % (name, mode)] = summary(acc, r, mode)
         line["extra"] = extra
+    if args.serve_n:
+        log("bench: serving")
+        line["serving"] = serve_bench(slh, workloads, args.serve_n,
+                                      [float(x) for x in args.serve_rates.split(",")], log)
     if not args.no_cpu:
         log("bench: cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args.workload, workloads, args.cpu_seconds)

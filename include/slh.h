@@ -201,6 +201,100 @@ int slh_ctx_profile(slh_ctx *ctx, int enable);
 int slh_ctx_phase_times(slh_ctx *ctx, double *ms, uint64_t *launches, uint64_t *messages,
                         int reset);
 
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of sign requests (this library's own; the   */
+/* paper signs fixed batches).                                              */
+/* ---------------------------------------------------------------------- */
+typedef struct slh_server slh_server;
+
+/* Server configuration (0 selects the default in brackets).
+ *   lanes        batches in flight at once, each with its own signing
+ *                context, stream and buffers, so that they overlap on the
+ *                GPU [3, at most 8]
+ *   max_batch    requests per launch [4096]
+ *   min_batch    launch as soon as this many wait and a lane is free
+ *                [0 = rule off]
+ *   max_wait_us  launch when the oldest waiting request is this old [2000]
+ *   msg_bytes    message buffer per lane; a batch takes requests in arrival
+ *                order while their messages fit (admission by memory)
+ *                [64 MiB]
+ *   hbm_budget   working memory of each lane's signing context [4 GiB]
+ *   mode         SLH_MODE_* of the launches [plain]
+ *   queue_limit  waiting requests before slh_serve_submit says SLH_EBUSY
+ *                [1 << 20]
+ * A batch is launched when it is full, when no lane is busy, when its
+ * oldest request has waited max_wait_us, or by the min_batch rule. */
+typedef struct {
+    uint32_t lanes;
+    uint32_t max_batch;
+    uint32_t min_batch;
+    uint32_t max_wait_us;
+    uint64_t msg_bytes;
+    uint64_t hbm_budget;
+    uint32_t mode;
+    uint32_t queue_limit;
+} slh_serve_config;
+
+/* One request of a replayed trace.  Offsets index the replay's host
+ * buffers; arrival_s is the arrival time in seconds after the replay
+ * starts (non-decreasing). */
+typedef struct {
+    uint32_t param;
+    uint32_t key_slot;
+    uint64_t msg_off;
+    uint64_t msg_len;
+    uint64_t sig_off;
+    double arrival_s;
+} slh_serve_request;
+
+/* Outcome of a replay.  Latency = completion - arrival, over the requests
+ * after the first `skip`. */
+typedef struct {
+    uint64_t completed;
+    uint64_t launches;
+    double wall_s;      /* replay start to last completion */
+    double sig_per_s;   /* completed / wall_s */
+    double p50_s, p99_s, mean_s, max_s;
+    double mean_batch;  /* requests per launch */
+} slh_serve_stats;
+
+/* Create / destroy a server on GPU `device`.  cfg may be null (defaults).
+ * Errors: SLH_EINVAL, SLH_ENOMEM, SLH_EDEVICE. */
+int slh_serve_create(int device, const slh_serve_config *cfg, slh_server **out);
+int slh_serve_destroy(slh_server *s);
+const char *slh_serve_last_error(const slh_server *s);
+
+/* Register secret keys (as slh_ctx_add_keys) on every lane; the slots are
+ * the same on all lanes.  Not while the online scheduler runs. */
+int slh_serve_add_keys(slh_server *s, uint32_t param, const uint8_t *sks, uint32_t count,
+                       uint32_t *first_slot);
+/* Tuning knobs (as slh_ctx_set_tuning) on every lane. */
+int slh_serve_set_tuning(slh_server *s, uint32_t param, const slh_tuning *t);
+
+/* Serve a trace on the calling thread: each request is released to the
+ * scheduler at its arrival time, signatures are written to sigs (host,
+ * sigs_bytes long) at sig_off, latencies (seconds) to latency_s[i] if not
+ * null, and the summary to *stats if not null.  Returns when every request
+ * has completed.  Errors: SLH_EINVAL (bad request; nothing is served),
+ * SLH_EBUSY (online scheduler running), SLH_EDEVICE. */
+int slh_serve_replay(slh_server *s, const slh_serve_request *reqs, uint64_t n, const uint8_t *msgs,
+                     uint64_t msgs_bytes, uint8_t *sigs, uint64_t sigs_bytes, double *latency_s,
+                     uint64_t skip, slh_serve_stats *stats);
+
+/* Online use: start a scheduler thread, submit requests as they arrive
+ * (the message is copied; `tag` identifies the result), poll completed
+ * results, stop (waits until every submitted request has completed).
+ * slh_serve_submit returns SLH_EBUSY when queue_limit requests wait.
+ * slh_serve_poll copies up to `max` results: tags[i], the signature at
+ * sigs + i * sig_stride (sig_stride >= 49856), latency_s[i] if not null;
+ * *n is the number copied.  Submit and poll may be called from any thread. */
+int slh_serve_start(slh_server *s);
+int slh_serve_submit(slh_server *s, uint32_t param, uint32_t key_slot, const uint8_t *msg,
+                     uint64_t len, uint64_t tag);
+int slh_serve_poll(slh_server *s, uint64_t *tags, uint8_t *sigs, uint64_t sig_stride,
+                   double *latency_s, uint32_t max, uint32_t *n);
+int slh_serve_stop(slh_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslh.so")
-SOURCES = [os.path.join(CSRC, "api.hip")]
+SOURCES = [os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "serve.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

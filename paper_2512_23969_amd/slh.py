@@ -42,6 +42,24 @@ class slh_tuning(ctypes.Structure):
                 ("keep_chains", ctypes.c_uint32)]
 
 
+class slh_serve_config(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("min_batch", ctypes.c_uint32),
+                ("max_wait_us", ctypes.c_uint32), ("msg_bytes", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
+                ("mode", ctypes.c_uint32), ("queue_limit", ctypes.c_uint32)]
+
+
+class slh_serve_stats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("wall_s", ctypes.c_double),
+                ("sig_per_s", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double), ("mean_batch", ctypes.c_double)]
+
+
+REQ_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
+                      ("sig_off", "<u8"), ("arrival_s", "<f8")])
+assert REQ_DTYPE.itemsize == 40
+MAX_SIG_BYTES = 49856
+
+
 class slh_sizes(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in
                 ("n", "h", "d", "hp", "a", "k", "len", "m", "seed_bytes", "pk_bytes", "sk_bytes",
@@ -71,6 +89,17 @@ def _load():
     L.slh_ctx_get_tuning.argtypes = [vp, u32, ctypes.POINTER(slh_tuning)]
     L.slh_ctx_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                       ctypes.POINTER(u64), ctypes.c_int]
+    L.slh_serve_create.argtypes = [ctypes.c_int, ctypes.POINTER(slh_serve_config), ctypes.POINTER(vp)]
+    L.slh_serve_destroy.argtypes = [vp]
+    L.slh_serve_last_error.argtypes = [vp]
+    L.slh_serve_last_error.restype = ctypes.c_char_p
+    L.slh_serve_add_keys.argtypes = [vp, u32, ctypes.c_char_p, u32, ctypes.POINTER(u32)]
+    L.slh_serve_set_tuning.argtypes = [vp, u32, ctypes.POINTER(slh_tuning)]
+    L.slh_serve_replay.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp, u64, ctypes.POINTER(slh_serve_stats)]
+    L.slh_serve_start.argtypes = [vp]
+    L.slh_serve_stop.argtypes = [vp]
+    L.slh_serve_submit.argtypes = [vp, u32, u32, ctypes.c_char_p, u64, u64]
+    L.slh_serve_poll.argtypes = [vp, vp, vp, u64, vp, u32, ctypes.POINTER(u32)]
     return L
 
 
@@ -224,3 +253,101 @@ def sign_messages(ctx: Context, params, slots, messages, mode: int = MODE_PLAIN)
     host = sigs.cpu().numpy().tobytes()
     return [host[int(it["sig_off"]):int(it["sig_off"]) + sizes(int(it["param"]))["sig_bytes"]]
             for it in items]
+
+
+class Server:
+    """Continuous-batching signing server (lanes of in-flight batches)."""
+
+    def __init__(self, device: int = 0, lanes: int = 0, max_batch: int = 0, min_batch: int = 0,
+                 max_wait_us: int = 0, msg_bytes: int = 0, hbm_budget: int = 0, mode: int = MODE_PLAIN,
+                 queue_limit: int = 0):
+        cfg = slh_serve_config(lanes, max_batch, min_batch, max_wait_us, msg_bytes, hbm_budget, mode,
+                               queue_limit)
+        h = ctypes.c_void_p()
+        rc = lib.slh_serve_create(int(device), ctypes.byref(cfg), ctypes.byref(h))
+        if rc < 0:
+            raise SlhError(rc, "slh_serve_create failed")
+        self.h = h
+
+    def _check(self, rc):
+        if rc < 0:
+            raise SlhError(rc, lib.slh_serve_last_error(self.h).decode(errors="replace"))
+        return rc
+
+    def close(self):
+        if self.h:
+            lib.slh_serve_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_keys(self, param: int, sks) -> int:
+        blob = b"".join(sks) if isinstance(sks, (list, tuple)) else bytes(sks)
+        skb = sizes(param)["sk_bytes"]
+        first = ctypes.c_uint32()
+        self._check(lib.slh_serve_add_keys(self.h, int(param), blob, len(blob) // skb, ctypes.byref(first)))
+        return first.value
+
+    def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0, keep_chains: int = 1):
+        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains)
+        self._check(lib.slh_serve_set_tuning(self.h, int(param), ctypes.byref(t)))
+
+    def replay(self, reqs: np.ndarray, msgs: bytes, skip: int = 0):
+        """Serve a trace (REQ_DTYPE array, msg offsets into `msgs`).
+        Returns (signature blob, latencies array, stats dict); each request's
+        signature sits at its sig_off."""
+        reqs = np.ascontiguousarray(reqs, dtype=REQ_DTYPE)
+        n = len(reqs)
+        total = int((reqs["sig_off"] + MAX_SIG_BYTES).max()) if n else 16
+        sigs = np.zeros(total, dtype=np.uint8)
+        lat = np.zeros(max(1, n), dtype=np.float64)
+        mbuf = np.frombuffer(msgs or b"\0", dtype=np.uint8)
+        st = slh_serve_stats()
+        self._check(lib.slh_serve_replay(self.h, reqs.ctypes.data, n, mbuf.ctypes.data, len(msgs),
+                                         sigs.ctypes.data, total, lat.ctypes.data, int(skip), ctypes.byref(st)))
+        return sigs, lat[:n], {f: getattr(st, f) for f, _ in st._fields_}
+
+    def start(self):
+        self._check(lib.slh_serve_start(self.h))
+
+    def stop(self):
+        self._check(lib.slh_serve_stop(self.h))
+
+    def submit(self, param: int, key_slot: int, msg: bytes, tag: int) -> int:
+        """0 if accepted, EBUSY if the queue is full."""
+        rc = lib.slh_serve_submit(self.h, int(param), int(key_slot), msg, len(msg), int(tag))
+        if rc == EBUSY:
+            return rc
+        return self._check(rc)
+
+    def poll(self, max_results: int = 256):
+        """List of (tag, signature bytes with trailing space, latency s)."""
+        tags = np.zeros(max_results, dtype=np.uint64)
+        sigs = np.zeros(max_results * MAX_SIG_BYTES, dtype=np.uint8)
+        lat = np.zeros(max_results, dtype=np.float64)
+        n = ctypes.c_uint32()
+        self._check(lib.slh_serve_poll(self.h, tags.ctypes.data, sigs.ctypes.data, MAX_SIG_BYTES,
+                                       lat.ctypes.data, max_results, ctypes.byref(n)))
+        return [(int(tags[i]), sigs[i * MAX_SIG_BYTES:(i + 1) * MAX_SIG_BYTES].tobytes(), float(lat[i]))
+                for i in range(n.value)]
+
+
+def trace(params, slots, messages, arrivals):
+    """Build a replay trace: (REQ_DTYPE array, message blob)."""
+    reqs = np.zeros(len(messages), dtype=REQ_DTYPE)
+    moff = soff = 0
+    for i, (p, k, m, a) in enumerate(zip(params, slots, messages, arrivals)):
+        reqs[i] = (p, k, moff, len(m), soff, a)
+        moff += len(m)
+        soff += (sizes(p)["sig_bytes"] + 15) // 16 * 16
+    return reqs, b"".join(messages)

@@ -1,0 +1,124 @@
+"""Serving parity: requests of mixed parameter sets, keys and lengths served
+by the continuous-batching scheduler (several batches in flight, arrivals
+while the GPU is busy) give exactly the signature that the same request
+signed alone gives, and the oracle's."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import NAMES, describe_diff, oracle_sign_many
+from paper_2512_23969_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slh():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2512_23969_amd import slh as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def keyset(slh):
+    keys = {}
+    for p in (1, 2, 3):
+        keys[p] = [slh.keygen(p, workloads.key_seed(p, 40 + i)) for i in range(3)]
+    return keys
+
+
+def _mix(n, seed=9):
+    reqs = workloads.serving_requests(n, seed=seed, keys_per_set=(3, 3, 3))
+    return [p for p, _, _ in reqs], [k for _, k, _ in reqs], [m for _, _, m in reqs]
+
+
+def test_replay_equals_alone_and_oracle(slh, keyset):
+    n = 600
+    params, kidx, msgs = _mix(n)
+    with slh.Server(0, lanes=3, max_batch=128, max_wait_us=500) as srv, slh.Context(0) as ctx:
+        slots = {}
+        for p in (1, 2, 3):
+            slots[p] = srv.add_keys(p, [sk for _, sk in keyset[p]])
+            assert ctx.add_keys(p, [sk for _, sk in keyset[p]]) == slots[p]
+        ks = [slots[p] + k for p, k in zip(params, kidx)]
+        # arrivals at ~ 4x a 128-batch every few ms: batches overlap
+        arr = np.cumsum(np.random.default_rng(3).exponential(2e-5, size=n))
+        reqs, blob = slh.trace(params, ks, msgs, arr)
+        sigs, lat, st = srv.replay(reqs, blob)
+        print("serve stats", st, flush=True)
+        assert st["completed"] == n and st["launches"] >= 5 and (lat > 0).all()
+        served = [sigs[int(r["sig_off"]):int(r["sig_off"]) + slh.sizes(int(r["param"]))["sig_bytes"]].tobytes()
+                  for r in reqs]
+        # the same requests in one plain batch, and a few truly alone
+        batch = slh.sign_messages(ctx, params, ks, msgs)
+        for i in range(n):
+            assert served[i] == batch[i], "req %d (%s, %d B): %s" % (
+                i, NAMES[params[i]], len(msgs[i]), describe_diff(params[i], served[i], batch[i]))
+        for i in (0, 1, 2, n // 2, n - 1):
+            alone = slh.sign_messages(ctx, [params[i]], [ks[i]], [msgs[i]])[0]
+            assert alone == served[i]
+    # the oracle on a sample
+    sample = list(range(0, n, 50))
+    want = oracle_sign_many([(params[i], keyset[params[i]][kidx[i]][1], msgs[i]) for i in sample])
+    for i, w in zip(sample, want):
+        assert served[i] == w, "req %d: %s" % (i, describe_diff(params[i], served[i], w))
+
+
+def test_online_submit_poll_two_threads(slh, keyset):
+    n = 300
+    params, kidx, msgs = _mix(n, seed=13)
+    with slh.Server(0, lanes=2, max_batch=64, max_wait_us=300, queue_limit=100000) as srv, \
+            slh.Context(0) as ctx:
+        slots = {p: srv.add_keys(p, [sk for _, sk in keyset[p]]) for p in (1, 2, 3)}
+        for p in (1, 2, 3):
+            ctx.add_keys(p, [sk for _, sk in keyset[p]])
+        ks = [slots[p] + k for p, k in zip(params, kidx)]
+        srv.start()
+        results = {}
+
+        def producer(lo, hi):
+            for i in range(lo, hi):
+                while srv.submit(params[i], ks[i], msgs[i], i) == slh.EBUSY:
+                    pass
+        th = [threading.Thread(target=producer, args=(0, n // 2)),
+              threading.Thread(target=producer, args=(n // 2, n))]
+        for t in th:
+            t.start()
+        import time
+        t0 = time.time()
+        while len(results) < n and time.time() - t0 < 60:
+            for tag, sig, lat in srv.poll(128):
+                results[tag] = sig[:slh.sizes(params[tag])["sig_bytes"]]
+            time.sleep(0.001)
+        for t in th:
+            t.join()
+        srv.stop()
+        for tag, sig, lat in srv.poll(1024):
+            results[tag] = sig[:slh.sizes(params[tag])["sig_bytes"]]
+        assert len(results) == n
+        batch = slh.sign_messages(ctx, params, ks, msgs)
+        for i in range(n):
+            assert results[i] == batch[i], "req %d" % i
+
+
+def test_replay_rejects_bad_requests(slh, keyset):
+    with slh.Server(0, lanes=1, max_batch=8) as srv:
+        slot = srv.add_keys(1, keyset[1][0][1])
+        reqs, blob = slh.trace([1, 1], [slot, slot], [b"a", b"b"], [0.0, 0.0])
+        bad = reqs.copy()
+        bad[1]["msg_off"] = 10 ** 9
+        with pytest.raises(slh.SlhError):
+            srv.replay(bad, blob)
+        bad = reqs.copy()
+        bad[0]["param"] = 9
+        with pytest.raises(slh.SlhError):
+            srv.replay(bad, blob)
+        bad = reqs.copy()
+        bad[1]["arrival_s"] = -1.0
+        with pytest.raises(slh.SlhError):
+            srv.replay(bad, blob)
+        sigs, lat, st = srv.replay(reqs, blob)  # still serves afterwards
+        assert st["completed"] == 2
