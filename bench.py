@@ -65,6 +65,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     if mode == "auto":
         mode = {"plain": "plain", "fused": "fused"}.get(tuned or "plain", "plain")
     m = slh.MODES[mode]
+    ctx.dedup_stats(reset=True)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
@@ -79,6 +80,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     t1 = time.perf_counter()
     ctx.profile(False)
     phases = ctx.phase_times(reset=True)
+    trees, distinct = ctx.dedup_stats(reset=True)
     ctx.close()
     elapsed = t1 - t0
     return {
@@ -90,6 +92,8 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         "steps": steps,
         "mode": mode,
         "tuning": best,
+        # (trees needed, distinct trees computed) per step, dedup modes only
+        "dedup": (trees // (warmup + steps), distinct // (warmup + steps)) if trees else None,
     }
 
 
@@ -143,7 +147,7 @@ def serve_bench(slh, workloads, n, rates, log):
     kidx = [k for _, k, _ in reqs]
     msgs = [m for _, _, m in reqs]
     log("serve: %d requests generated in %.1f s" % (n, time.perf_counter() - t0))
-    srv = slh.Server(0, lanes=3, max_batch=4096, max_wait_us=2000, mode=slh.MODE_FUSED)
+    srv = slh.Server(0, lanes=4, max_batch=4096, max_wait_us=2000, mode=slh.MODE_FUSED)
     slots = {}
     sks = {}
     for p, cnt in zip((1, 2, 3), keys_per_set):
@@ -151,7 +155,7 @@ def serve_bench(slh, workloads, n, rates, log):
         slots[p] = srv.add_keys(p, sks[p])
     ks = [slots[p] + k for p, k in zip(params, kidx)]
     out = {"requests": n, "mix": "50/30/20 % 128f/192f/256f", "keys": 256,
-           "msg_len": "log-normal, median 256 B, clipped to [32, 16384]", "lanes": 3, "max_batch": 4096,
+           "msg_len": "log-normal, median 256 B, clipped to [32, 16384]", "lanes": 4, "max_batch": 4096,
            "max_wait_us": 2000, "mode": "fused", "latency": "arrival to completion, host buffers (PCIe included)",
            "points": []}
     reqs0, blob = slh.trace(params, ks, msgs, [0.0] * n)
@@ -197,8 +201,10 @@ def roofline(param, res):
     if launches == 0:
         return None
     per_launch_msgs = msgs / launches
-    ops = sum(acc.ops_per_signature(param, p) for p in parts) * per_launch_msgs
-    tb = sum(acc.ops_per_signature(param, p, textbook=True) for p in parts) * per_launch_msgs
+    # with tree dedup only the distinct trees are computed
+    scale = {"tree": res["dedup"][1] / res["dedup"][0] if res.get("dedup") else 1.0}
+    ops = sum(acc.ops_per_signature(param, p) * scale.get(p, 1.0) for p in parts) * per_launch_msgs
+    tb = sum(acc.ops_per_signature(param, p, textbook=True) * scale.get(p, 1.0) for p in parts) * per_launch_msgs
     avg_s = ms / launches / 1000.0
     achieved = ops / avg_s / 1e12
     peak = acc.VALU_PEAK_OPS / 1e12
@@ -207,7 +213,7 @@ def roofline(param, res):
             "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
             "traffic": TRAFFIC.get((param, kernel)),
             "avg_launch_ms": round(ms / launches, 4),
-            "units_per_launch": {h: int(sum(c[h][p] for p in parts) * per_launch_msgs)
+            "units_per_launch": {h: int(sum(c[h][p] * scale.get(p, 1.0) for p in parts) * per_launch_msgs)
                                  for h in ("sha256", "sha512")},
             "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512},
             "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4)}
@@ -215,10 +221,17 @@ def roofline(param, res):
 
 def summary(acc, r, mode):
     prm = r["cfg"]["param"]
-    return {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3), "mode": mode,
-            "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
-            "roofline": roofline(prm, r) if mode != "graph" else None,
-            "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]}}
+    out = {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3), "mode": mode,
+           "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
+           "roofline": roofline(prm, r) if "graph" not in mode else None,
+           "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]}}
+    if r["dedup"]:
+        trees, distinct = r["dedup"]
+        out["dedup"] = {"trees_per_step": trees, "distinct_trees_per_step": distinct,
+                        "tree_work_saved": round(1.0 - distinct / trees, 4),
+                        "note": "identical signatures; work per signature below the paper's, "
+                                "so not the headline value"}
+    return out
 
 
 def main():
@@ -227,8 +240,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2_128f_4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="auto", choices=["auto", "plain", "fused", "graph"],
-                    help="execution mode; auto = the autotuned mode for the workload")
+    ap.add_argument("--mode", default="auto",
+                    choices=["auto", "plain", "fused", "graph", "dedup", "fused-dedup", "graph-dedup"],
+                    help="execution mode; auto = the autotuned mode for the workload (dedup modes: "
+                         "within-batch tree dedup)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner first and store its result")
     ap.add_argument("--tune-out", default=None, help="tuning cache file (default: the package's tuning.json)")
     ap.add_argument("--all", action="store_true", help="also time the 192f and 256f workloads")
@@ -288,7 +303,7 @@ def main():
         extra = {}
         steps_c = max(3, args.steps // 2)
         for name in ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64"):
-            for mode in ("plain", "fused", "graph"):
+            for mode in ("plain", "fused", "graph", "dedup", "fused-dedup"):
                 if name == args.workload and mode == res["mode"]:
                     continue
                 log("bench: workload", name, mode)

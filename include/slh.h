@@ -98,10 +98,21 @@ typedef struct slh_ctx slh_ctx;
  *                   (per batch shape, buffers and tuning) and replayed with a
  *                   single hipGraphLaunch; combine with SLH_MODE_FUSED for the
  *                   batched fused pipeline.  Per-phase timing is not recorded
- *                   inside graphs. */
+ *                   inside graphs.
+ *   SLH_MODE_DEDUP  within-batch dedup of XMSS trees (combines with the
+ *                   others): messages of one key whose hypertree paths share
+ *                   a tree at some layer (FIPS 205 Algorithm 12: the layer's
+ *                   tree address idx_tree >> (j h')) compute that tree once;
+ *                   the others take its authentication path and root from a
+ *                   node buffer and recompute only their WOTS+ chains.  Only
+ *                   layers whose tree address has at most 35 bits are
+ *                   matched (wider addresses practically never repeat within
+ *                   a batch).  Costs about (2^(h'+1) - 1) n + 24 bytes of
+ *                   working memory per tree. */
 #define SLH_MODE_PLAIN 0u
 #define SLH_MODE_FUSED 1u
 #define SLH_MODE_GRAPH 2u
+#define SLH_MODE_DEDUP 4u
 
 /* Fill *out with the sizes of parameter set `param`.
  * Errors: SLH_EINVAL for an unknown set or a null pointer. */
@@ -158,6 +169,27 @@ int slh_sign_batch(slh_ctx *ctx, const slh_item *items, uint32_t count, const ui
 int slh_verify(uint32_t param, const uint8_t *msg, size_t msg_len, const uint8_t *sig,
                size_t sig_len, const uint8_t *pk);
 
+/* One verification request of a batch (host memory, 40 bytes).  Offsets
+ * index the batch's device buffers of messages, signatures and public keys
+ * (pk = PK.seed | PK.root, 2n bytes). */
+typedef struct {
+    uint32_t param;
+    uint32_t pad;
+    uint64_t msg_off;
+    uint64_t msg_len;
+    uint64_t sig_off;
+    uint64_t pk_off;
+} slh_verify_item;
+
+/* Verify a batch (Algorithm 20 per item) on the context's GPU: one
+ * workgroup per signature.  results (device, count int32) receives 1 for a
+ * valid signature and 0 otherwise, in item order.  Asynchronous on `stream`
+ * like slh_sign_batch.  Errors: SLH_EINVAL (nothing launched), SLH_ENOMEM,
+ * SLH_EDEVICE. */
+int slh_verify_batch(slh_ctx *ctx, const slh_verify_item *items, uint32_t count, const uint8_t *msgs,
+                     uint64_t msgs_bytes, const uint8_t *sigs, uint64_t sigs_bytes, const uint8_t *pks,
+                     uint64_t pks_bytes, int32_t *results, void *stream);
+
 /* Kernel phases of the signing path, for per-phase timing. */
 #define SLH_PHASE_PRELUDE 0 /* PRF_msg, H_msg, index split                     */
 #define SLH_PHASE_FORS 1    /* FORS trees and auth paths (plain mode)          */
@@ -194,6 +226,13 @@ int slh_ctx_get_tuning(const slh_ctx *ctx, uint32_t param, slh_tuning *t);
  * in its Table 8; this is the same measurement).  Errors: SLH_EINVAL. */
 int slh_ctx_profile(slh_ctx *ctx, int enable);
 
+/* Trees of the hypertree that slh_sign_batch calls in SLH_MODE_DEDUP needed
+ * (messages x d) and the distinct ones they computed, summed since the last
+ * reset (FIPS 205 Algorithm 12 visits d trees per signature; the difference
+ * is the TREE work the dedup saved).  Waits for the context's pending work;
+ * reset != 0 clears the totals.  Errors: SLH_EINVAL, SLH_EDEVICE. */
+int slh_ctx_dedup_stats(slh_ctx *ctx, uint64_t *trees, uint64_t *distinct, int reset);
+
 /* Accumulated GPU time per phase since the last reset.  Host arrays of
  * SLH_NPHASES entries: ms[i] milliseconds, launches[i] kernel launches,
  * messages[i] messages processed.  Waits for the recorded events.  reset != 0
@@ -210,7 +249,7 @@ typedef struct slh_server slh_server;
 /* Server configuration (0 selects the default in brackets).
  *   lanes        batches in flight at once, each with its own signing
  *                context, stream and buffers, so that they overlap on the
- *                GPU [3, at most 8]
+ *                GPU [4, at most 8]
  *   max_batch    requests per launch [4096]
  *   min_batch    launch as soon as this many wait and a lane is free
  *                [0 = rule off]
@@ -223,7 +262,8 @@ typedef struct slh_server slh_server;
  *   queue_limit  waiting requests before slh_serve_submit says SLH_EBUSY
  *                [1 << 20]
  * A batch is launched when it is full, when no lane is busy, when its
- * oldest request has waited max_wait_us, or by the min_batch rule. */
+ * oldest request has waited max_wait_us times the number of busy lanes, or
+ * by the min_batch rule. */
 typedef struct {
     uint32_t lanes;
     uint32_t max_batch;

@@ -111,6 +111,10 @@ struct slh_ctx {
   Tuning tune[4];
   DevItem* staging = nullptr;  // pinned host copy of the items of a call
   size_t staging_cap = 0;
+  uint8_t* vbuf = nullptr;     // device copy of a verify batch's items
+  size_t vbuf_bytes = 0;
+  VerifyItem* vstage = nullptr;  // pinned host copy of a verify batch's items
+  size_t vstage_cap = 0;
   hipEvent_t done = nullptr;   // end of the last call's GPU work
   bool pending = false;
   hipStream_t cap_stream = nullptr;          // stream graphs are captured on
@@ -126,6 +130,7 @@ struct slh_ctx {
   double phase_ms[SLH_NPHASES] = {0};
   uint64_t phase_launches[SLH_NPHASES] = {0};
   uint64_t phase_units[SLH_NPHASES] = {0};
+  unsigned long long* dstats = nullptr;  // device: trees, distinct trees (dedup mode)
 };
 
 namespace {
@@ -210,11 +215,13 @@ template <int ID>
 struct Plan {
   using Q = P<ID>;
   size_t n = 0;
-  bool fused = false, keep = true;
-  uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0;
-  size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0, total = 0;
+  bool fused = false, dedup = false, keep = true;
+  uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0, table = 0;
+  size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
+  size_t o_table = 0, o_rep = 0, o_ulist = 0, o_nodes = 0, total = 0;
   static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
-  Plan(size_t n_, bool fused_, const Tuning& t, int cus) : n(n_), fused(fused_), keep(t.keep != 0) {
+  Plan(size_t n_, uint32_t mode, const Tuning& t, int cus)
+      : n(n_), fused((mode & SLH_MODE_FUSED) != 0), dedup((mode & SLH_MODE_DEDUP) != 0), keep(t.keep != 0) {
     fg = t.fg ? t.fg : fg_default(ID);
     const size_t trees = n * Q::d;
     ntb = uint32_t((trees + kLeavesPerBlock / Q::leaves - 1) / (kLeavesPerBlock / Q::leaves));
@@ -232,7 +239,20 @@ struct Plan {
     o_spill = o_stage + up(size_t(grid) * stage_per_block * (fused ? 2 : 1));
     o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
     o_queue = o_roots + up(n * Q::k * Q::NW * 4);
-    total = o_queue + kAlign;
+    // dedup: hash table (>= 2 slots per tree), representative per tree, list
+    // of representatives (its count is the word after the work counter), and
+    // every node of every tree
+    o_table = o_queue + kAlign;
+    if (dedup) {
+      table = 2;
+      while (table < 2 * trees) table <<= 1;
+      o_rep = o_table + up(size_t(table) * sizeof(DedupSlot));
+      o_ulist = o_rep + up(trees * 4);
+      o_nodes = o_ulist + up(trees * 4);
+      total = o_nodes + up(trees * TreeNodes<ID>::count * Q::NW * 4);
+    } else {
+      total = o_table;
+    }
   }
 };
 
@@ -259,11 +279,20 @@ void launch_fors(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, u
   hipLaunchKernelGGL((k_fors<ID, FG>), dim3(pl.nfg), dim3(kForsThreads), 0, s, c->keys, recs,
                      uint32_t(pl.n * P<ID>::k), sigs, roots);
 }
+// Dedup buffers of a chunk (all null without dedup).
+struct DedupBufs {
+  DedupSlot* table = nullptr;
+  uint32_t* rep = nullptr;
+  uint32_t* ulist = nullptr;
+  uint32_t* ucount = nullptr;
+  uint32_t* nodes = nullptr;
+};
+
 template <int ID, int FG>
 void launch_fused(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
-                  uint32_t* roots, uint32_t* queue, hipStream_t s) {
+                  uint32_t* roots, uint32_t* queue, const DedupBufs& db, hipStream_t s) {
   hipLaunchKernelGGL((k_fused<ID, FG>), dim3(pl.grid), dim3(kTreeThreads), 0, s, c->keys, recs, uint32_t(pl.n),
-                     sigs, stage, spill, roots, queue, pl.ntb, pl.nfg);
+                     sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist, db.ucount, db.nodes);
 }
 
 // Enqueue one chunk on stream s.  `timing` is false while a graph is captured.
@@ -278,23 +307,40 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
   uint32_t* spill = pl.keep ? reinterpret_cast<uint32_t*>(base + pl.o_spill) : nullptr;
   uint32_t* roots = reinterpret_cast<uint32_t*>(base + pl.o_roots);
   uint32_t* queue = reinterpret_cast<uint32_t*>(base + pl.o_queue);
+  DedupBufs db;
+  if (pl.dedup) {
+    db.table = reinterpret_cast<DedupSlot*>(base + pl.o_table);
+    db.rep = reinterpret_cast<uint32_t*>(base + pl.o_rep);
+    db.ulist = reinterpret_cast<uint32_t*>(base + pl.o_ulist);
+    db.ucount = queue + 1;
+    db.nodes = reinterpret_cast<uint32_t*>(base + pl.o_nodes);
+  }
   HIPCHK(c, hipMemcpyAsync(items, h_items, pl.n * sizeof(DevItem), hipMemcpyHostToDevice, s));
   const uint32_t n = uint32_t(pl.n);
+  const uint32_t trees = n * Q::d;
   {
     PhaseTimer t(c, s, SLH_PHASE_PRELUDE, n, timing);
     hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs, sigs, recs,
                        pl.fused ? queue : nullptr);
+    if (pl.dedup) {
+      hipLaunchKernelGGL(k_dedup_init, dim3((pl.table + 255) / 256), dim3(256), 0, s, db.table, pl.table, db.ucount);
+      hipLaunchKernelGGL((k_dedup_insert<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, recs, n, db.table,
+                         pl.table, db.rep);
+      hipLaunchKernelGGL((k_dedup_resolve<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, n, db.table, db.rep,
+                         db.ulist, db.ucount);
+      hipLaunchKernelGGL(k_dedup_stats, dim3(1), dim3(64), 0, s, trees, db.ucount, c->dstats);
+    }
   }
   if (pl.fused) {
     PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
     if constexpr (ID == 3) {
-      if (pl.fg == 2) launch_fused<ID, 2>(c, pl, sigs, recs, stage, spill, roots, queue, s);
-      else if (pl.fg == 8) launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, s);
-      else launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+      if (pl.fg == 2) launch_fused<ID, 2>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+      else if (pl.fg == 8) launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+      else launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
     } else {
-      if (pl.fg == 4) launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, s);
-      else if (pl.fg == 16) launch_fused<ID, 16>(c, pl, sigs, recs, stage, spill, roots, queue, s);
-      else launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, s);
+      if (pl.fg == 4) launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+      else if (pl.fg == 16) launch_fused<ID, 16>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+      else launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
     }
   } else {
     {
@@ -311,15 +357,21 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
     }
     {
       PhaseTimer t(c, s, SLH_PHASE_TREE, n, timing);
-      hipLaunchKernelGGL((k_tree<ID, false>), dim3(pl.ntb), dim3(kTreeThreads), 0, s, c->keys, recs,
-                         uint32_t(n * Q::d), sigs, stage, spill, 0u, nullptr);
+      hipLaunchKernelGGL((k_tree<ID, false>), dim3(pl.ntb), dim3(kTreeThreads), 0, s, c->keys, recs, trees, sigs,
+                         stage, spill, 0u, nullptr, db.ulist, db.ucount, db.nodes);
     }
   }
   {
     PhaseTimer t(c, s, SLH_PHASE_WOTS, n, timing);
+    if (pl.dedup)
+      hipLaunchKernelGGL((k_dedup_scatter<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs,
+                         db.rep, db.nodes);
     hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, roots);
     const uint32_t nw = n * Q::d * Q::len;
-    if (pl.keep)
+    if (pl.keep && pl.dedup)
+      hipLaunchKernelGGL((k_wots_dedup<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs, spill,
+                         db.rep);
+    else if (pl.keep)
       hipLaunchKernelGGL((k_wots<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, recs, n, sigs, spill);
     else
       hipLaunchKernelGGL((k_wots_recompute<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs);
@@ -330,29 +382,31 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
 
 // Messages per chunk for parameter set ID within `budget` bytes.
 template <int ID>
-size_t chunk_size(slh_ctx* c, size_t count, bool fused, uint64_t budget) {
+size_t chunk_size(slh_ctx* c, size_t count, uint32_t mode, uint64_t budget) {
   const Tuning& t = c->tune[ID];
-  const Plan<ID> one(1, fused, t, c->cus), big(1024, fused, t, c->cus);
+  const Plan<ID> one(1, mode, t, c->cus), big(1024, mode, t, c->cus);
   const size_t per = (big.total - one.total) / 1023 + 1;
   const size_t fixed = one.total > per ? one.total - per : 0;
   size_t chunk = budget > fixed ? (budget - fixed) / per : 1;
   chunk = std::max<size_t>(1, std::min(chunk, count));
+  // the dedup table is rounded up to a power of two: shrink until it fits
+  while (chunk > 1 && Plan<ID>(chunk, mode, t, c->cus).total > budget) chunk -= chunk / 64 + 1;
   return chunk;
 }
 
 template <int ID>
-int prepare_group(slh_ctx* c, size_t count, bool fused, uint64_t budget, size_t* chunk) {
-  *chunk = chunk_size<ID>(c, count, fused, budget);
-  const Plan<ID> pl(*chunk, fused, c->tune[ID], c->cus);
+int prepare_group(slh_ctx* c, size_t count, uint32_t mode, uint64_t budget, size_t* chunk) {
+  *chunk = chunk_size<ID>(c, count, mode, budget);
+  const Plan<ID> pl(*chunk, mode, c->tune[ID], c->cus);
   return ensure_ws(c, ID, pl.total);
 }
 
 template <int ID>
 int enqueue_group(slh_ctx* c, const DevItem* h_items, size_t count, size_t chunk, const uint8_t* msgs,
-                  uint8_t* sigs, hipStream_t s, bool fused, bool timing) {
+                  uint8_t* sigs, hipStream_t s, uint32_t mode, bool timing) {
   for (size_t off = 0; off < count; off += chunk) {
     const size_t cnt = std::min(chunk, count - off);
-    const Plan<ID> pl(cnt, fused, c->tune[ID], c->cus);
+    const Plan<ID> pl(cnt, mode, c->tune[ID], c->cus);
     const int rc = launch_chunk<ID>(c, pl, h_items + off, msgs, sigs, s, timing);
     if (rc) return rc;
   }
@@ -360,10 +414,10 @@ int enqueue_group(slh_ctx* c, const DevItem* h_items, size_t count, size_t chunk
 }
 
 int enqueue_all(slh_ctx* c, const size_t per[4], const size_t start[4], const size_t chunk[4], const uint8_t* msgs,
-                uint8_t* sigs, hipStream_t s, bool fused, bool timing) {
+                uint8_t* sigs, hipStream_t s, uint32_t mode, bool timing) {
   int groups = 0;
   for (int p = 1; p <= 3; p++) groups += per[p] ? 1 : 0;
-  const bool branches = fused && groups > 1;
+  const bool branches = (mode & SLH_MODE_FUSED) && groups > 1;
   if (branches) HIPCHK(c, hipEventRecord(c->fork, s));
   for (int p = 1; p <= 3 ; p++) {
     if (!per[p]) continue;
@@ -373,9 +427,9 @@ int enqueue_all(slh_ctx* c, const size_t per[4], const size_t start[4], const si
       HIPCHK(c, hipStreamWaitEvent(b, c->fork, 0));
     }
     int rc = SLH_OK;
-    if (p == 1) rc = enqueue_group<1>(c, c->staging + start[1], per[1], chunk[1], msgs, sigs, b, fused, timing);
-    if (p == 2) rc = enqueue_group<2>(c, c->staging + start[2], per[2], chunk[2], msgs, sigs, b, fused, timing);
-    if (p == 3) rc = enqueue_group<3>(c, c->staging + start[3], per[3], chunk[3], msgs, sigs, b, fused, timing);
+    if (p == 1) rc = enqueue_group<1>(c, c->staging + start[1], per[1], chunk[1], msgs, sigs, b, mode, timing);
+    if (p == 2) rc = enqueue_group<2>(c, c->staging + start[2], per[2], chunk[2], msgs, sigs, b, mode, timing);
+    if (p == 3) rc = enqueue_group<3>(c, c->staging + start[3], per[3], chunk[3], msgs, sigs, b, mode, timing);
     if (rc) return rc;
     if (branches) {
       HIPCHK(c, hipEventRecord(c->join[p], b));
@@ -411,7 +465,7 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_key_midstates, dim3(1), dim3(64), 0, 0, dk, 0u, 1u);
     hipLaunchKernelGGL((k_tree<ID, true>), dim3(1), dim3(kTreeThreads), 0, 0, dk, nullptr, 1u, nullptr,
-                       stage, nullptr, 0u, root);
+                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpy(hroot, root, Q::n, hipMemcpyDeviceToHost);
@@ -442,7 +496,7 @@ int verify_impl(const uint8_t* msg, size_t msg_len, const uint8_t* sig, const ui
     (void)hipGetLastError();
     return fail(nullptr, SLH_ENOMEM, "verify device allocation failed");
   }
-  VerifyItem it{0, msg_len, 0, 0};
+  VerifyItem it{0, msg_len, 0, 0, 0};
   uint8_t* d_items = buf;
   uint8_t* d_msg = d_items + up(sizeof(VerifyItem));
   uint8_t* d_sig = d_msg + up(mbytes);
@@ -490,6 +544,8 @@ int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMalloc(&c->dstats, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->dstats, 0, 2 * sizeof(unsigned long long));
   // all streams at the default priority
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   for (int p = 1; p <= 3 && e == hipSuccess; p++) {
@@ -518,7 +574,10 @@ int slh_ctx_destroy(slh_ctx* c) {
   }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->keys) (void)hipFree(c->keys);
+  if (c->dstats) (void)hipFree(c->dstats);
   if (c->staging) (void)hipHostFree(c->staging);
+  if (c->vbuf) (void)hipFree(c->vbuf);
+  if (c->vstage) (void)hipHostFree(c->vstage);
   if (c->done) (void)hipEventDestroy(c->done);
   if (c->fork) (void)hipEventDestroy(c->fork);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -553,6 +612,18 @@ int slh_ctx_phase_times(slh_ctx* c, double* ms, uint64_t* launches, uint64_t* me
     messages[i] = c->phase_units[i];
     if (reset) { c->phase_ms[i] = 0; c->phase_launches[i] = 0; c->phase_units[i] = 0; }
   }
+  return SLH_OK;
+}
+
+int slh_ctx_dedup_stats(slh_ctx* c, uint64_t* trees, uint64_t* distinct, int reset) {
+  if (!c || !trees || !distinct) return fail(c, SLH_EINVAL, "null argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  unsigned long long h[2] = {0, 0};
+  HIPCHK(c, hipMemcpy(h, c->dstats, sizeof h, hipMemcpyDeviceToHost));
+  *trees = h[0];
+  *distinct = h[1];
+  if (reset) HIPCHK(c, hipMemset(c->dstats, 0, sizeof h));
   return SLH_OK;
 }
 
@@ -600,7 +671,7 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (count == 0) return SLH_OK;
   if (!items || !sigs) return fail(c, SLH_EINVAL, "null items or signature buffer");
-  if (mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH)) return fail(c, SLH_EINVAL, "unknown mode");
+  if (mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH | SLH_MODE_DEDUP)) return fail(c, SLH_EINVAL, "unknown mode");
   if (reinterpret_cast<uintptr_t>(sigs) % 16) return fail(c, SLH_EINVAL, "signature buffer not 16-byte aligned");
   // validation, and grouping by parameter set
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
@@ -626,7 +697,7 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
     if (ranges[i].first < ranges[i - 1].second) return fail(c, SLH_EINVAL, "signature ranges overlap");
   HIPCHK(c, hipSetDevice(c->device));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const bool fused = (mode & SLH_MODE_FUSED) != 0, graph = (mode & SLH_MODE_GRAPH) != 0;
+  const bool graph = (mode & SLH_MODE_GRAPH) != 0;
   // the pinned staging copy of the items may still be read by the previous call
   if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
   if (c->staging_cap < count) {
@@ -653,12 +724,12 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
   const uint64_t share = c->budget / uint64_t(groups);
   size_t chunk[4] = {0, 0, 0, 0};
   int rc = SLH_OK;
-  if (per[1] && !rc) rc = prepare_group<1>(c, per[1], fused, share, &chunk[1]);
-  if (per[2] && !rc) rc = prepare_group<2>(c, per[2], fused, share, &chunk[2]);
-  if (per[3] && !rc) rc = prepare_group<3>(c, per[3], fused, share, &chunk[3]);
+  if (per[1] && !rc) rc = prepare_group<1>(c, per[1], mode, share, &chunk[1]);
+  if (per[2] && !rc) rc = prepare_group<2>(c, per[2], mode, share, &chunk[2]);
+  if (per[3] && !rc) rc = prepare_group<3>(c, per[3], mode, share, &chunk[3]);
   if (rc) return rc;
   if (!graph) {
-    rc = enqueue_all(c, per, start, chunk, msgs, sigs, s, fused, true);
+    rc = enqueue_all(c, per, start, chunk, msgs, sigs, s, mode, true);
     if (rc) return rc;
   } else {
     GraphKey key;
@@ -671,7 +742,7 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
       key.wpc[p] = c->tune[p].wgs_per_cu;
       key.keep[p] = c->tune[p].keep;
     }
-    key.n[0] = fused ? 1 : 0;
+    key.n[0] = mode & (SLH_MODE_FUSED | SLH_MODE_DEDUP);
     key.msgs = msgs;
     key.sigs = sigs;
     hipGraphExec_t exec = nullptr;
@@ -679,7 +750,7 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
       if (g.first == key) exec = g.second;
     if (!exec) {
       HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_all(c, per, start, chunk, msgs, sigs, c->cap_stream, fused, false);
+      rc = enqueue_all(c, per, start, chunk, msgs, sigs, c->cap_stream, mode, false);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
       if (rc) {
@@ -698,6 +769,71 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
     }
     HIPCHK(c, hipGraphLaunch(exec, s));
   }
+  HIPCHK(c, hipEventRecord(c->done, s));
+  c->pending = true;
+  return SLH_OK;
+}
+
+int slh_verify_batch(slh_ctx* c, const slh_verify_item* items, uint32_t count, const uint8_t* msgs,
+                     uint64_t msgs_bytes, const uint8_t* sigs, uint64_t sigs_bytes, const uint8_t* pks,
+                     uint64_t pks_bytes, int32_t* results, void* stream) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (count == 0) return SLH_OK;
+  if (!items || !sigs || !pks || !results) return fail(c, SLH_EINVAL, "null argument");
+  size_t per[4] = {0, 0, 0, 0};
+  for (uint32_t i = 0; i < count; i++) {
+    const slh_verify_item& it = items[i];
+    Sizes s;
+    if (!sizes_of(it.param, &s)) return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": unknown parameter set");
+    if (it.msg_len > msgs_bytes || it.msg_off > msgs_bytes - it.msg_len || (it.msg_len && !msgs))
+      return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": message outside the buffer");
+    if (s.sig > sigs_bytes || it.sig_off > sigs_bytes - s.sig)
+      return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": signature outside the buffer");
+    if (2 * s.n > pks_bytes || it.pk_off > pks_bytes - 2 * s.n)
+      return fail(c, SLH_EINVAL, "item " + std::to_string(i) + ": public key outside the buffer");
+    per[it.param]++;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->vstage_cap < count) {
+    if (c->vstage) HIPCHK(c, hipHostFree(c->vstage));
+    c->vstage = nullptr;
+    c->vstage_cap = 0;
+    if (hipHostMalloc(&c->vstage, size_t(count) * sizeof(VerifyItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "pinned staging allocation failed");
+    }
+    c->vstage_cap = count;
+  }
+  const size_t need = up(size_t(count) * sizeof(VerifyItem));
+  if (c->vbuf_bytes < need) {
+    if (c->vbuf) HIPCHK(c, hipFree(c->vbuf));
+    c->vbuf = nullptr;
+    c->vbuf_bytes = 0;
+    if (hipMalloc(&c->vbuf, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "hipMalloc of verify items failed");
+    }
+    c->vbuf_bytes = need;
+  }
+  size_t start[4] = {0, 0, per[1], per[1] + per[2]}, fill[4] = {0, 0, 0, 0};
+  for (uint32_t i = 0; i < count; i++) {
+    const slh_verify_item& it = items[i];
+    c->vstage[start[it.param] + fill[it.param]++] = VerifyItem{it.msg_off, it.msg_len, it.sig_off, it.pk_off, i};
+  }
+  VerifyItem* d = reinterpret_cast<VerifyItem*>(c->vbuf);
+  HIPCHK(c, hipMemcpyAsync(d, c->vstage, size_t(count) * sizeof(VerifyItem), hipMemcpyHostToDevice, s));
+  if (per[1])
+    hipLaunchKernelGGL((k_verify<1>), dim3(uint32_t(per[1])), dim3(kVerifyThreads), 0, s, d + start[1],
+                       uint32_t(per[1]), msgs, sigs, pks, results);
+  if (per[2])
+    hipLaunchKernelGGL((k_verify<2>), dim3(uint32_t(per[2])), dim3(kVerifyThreads), 0, s, d + start[2],
+                       uint32_t(per[2]), msgs, sigs, pks, results);
+  if (per[3])
+    hipLaunchKernelGGL((k_verify<3>), dim3(uint32_t(per[3])), dim3(kVerifyThreads), 0, s, d + start[3],
+                       uint32_t(per[3]), msgs, sigs, pks, results);
+  HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->done, s));
   c->pending = true;
   return SLH_OK;

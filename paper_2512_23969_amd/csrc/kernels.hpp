@@ -19,7 +19,9 @@
 //               WOTS+ signature of layer j (a function of the FORS public key
 //               or of root j-1) is a gather, with no hashing.
 // The paper launches FORS_Sign and TREE_Sign concurrently and then
-// WOTS+_Sign (Section III-F); here the same dependency holds.
+// WOTS+_Sign (Section III-F); here the same dependency holds.  The fused
+// persistent kernel runs FORS and TREE work from one work counter, and the
+// dedup kernels let messages that share an XMSS tree compute it once.
 #pragma once
 #include "slh_dev.hpp"
 
@@ -431,11 +433,21 @@ __device__ __forceinline__ TreeJob tree_job(const DevKey* __restrict__ keys, Wor
   }
 }
 
+// Trees of a batch, optionally restricted to a list of distinct trees
+// (within-batch dedup): tree slot i of the list is flat tree id ulist[i],
+// and there are *ucount of them; without a list, slot i is tree i of ntrees.
+struct TreeList {
+  const uint32_t* ulist;
+  const uint32_t* ucount;
+  __device__ __forceinline__ uint32_t count(uint32_t ntrees) const { return ucount ? *ucount : ntrees; }
+  __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : i; }
+};
+
 template <int ID, bool KEYGEN>
 __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
-                                            uint32_t block) {
+                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr}) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len, LV = Q::leaves;
   constexpr int TPB = kLeavesPerBlock / LV;
@@ -443,8 +455,8 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tree0 = block * TPB;
   const uint32_t lt = lane / LV, kp = lane % LV;
-  if (tree0 + lt >= ntrees) return;
-  const TreeJob J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, tree0 + lt);
+  if (tree0 + lt >= tl.count(ntrees)) return;
+  const TreeJob J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, tl.at(tree0 + lt));
   uint32_t mid[8], sks[NW];
   load_words<8>(J.key->mid256, mid);
   load_words<NW>(J.key->sk_seed, sks);
@@ -464,22 +476,35 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
 // chain ends, then the XMSS levels inside the wave (the node of level z lives
 // in the lanes with kp % 2^z == 0, its partner is 2^(z-1) lanes up); auth
 // nodes and the root are written where they are computed.
+// Number of nodes of one XMSS tree and the offset of level z in a node
+// buffer: level z (2^(h'-z) nodes) starts at 2^(h'+1) - 2^(h'-z+1).
+template <int ID>
+struct TreeNodes {
+  static constexpr int count = (2 << P<ID>::hp) - 1;
+  __device__ static constexpr int off(int z) { return (2 << P<ID>::hp) - (2 << (P<ID>::hp - z)); }
+};
+
+// `nodes` (optional): every node of the tree is stored at
+// nodes[(ft * TreeNodes::count + off(z) + i) * NW] for the dedup scatter.
 template <int ID, bool KEYGEN>
 __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, const uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
-                                            uint32_t block) {
+                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr},
+                                            uint32_t* __restrict__ nodes = nullptr) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
   constexpr int TPB = kLeavesPerBlock / LV;
   const int lane = threadIdx.x & 63;
   const uint32_t tree0 = block * TPB;
   const uint32_t lt = lane / LV, kp = lane % LV;
-  const bool valid = tree0 + lt < ntrees;
+  const bool valid = tree0 + lt < tl.count(ntrees);
+  const uint32_t ft = valid ? tl.at(tree0 + lt) : 0u;
+  uint32_t* tn = nodes ? nodes + size_t(ft) * TreeNodes<ID>::count * NW : nullptr;
   uint32_t v[NW];
   TreeJob J{};
   if (valid) {
-    J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, tree0 + lt);
+    J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, ft);
     auto get = [&](int wi) -> uint32_t {
       const int c = wi / NW, u = wi - c * NW;
       return st[(c * kLeavesPerBlock + lane) * NW + u];
@@ -498,6 +523,8 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
       if (i == ((uint32_t(J.sign_leaf) >> (z - 1)) ^ 1u))
         store_be<NW>(J.sig_xmss + (LEN + z - 1) * Q::n, v);
     }
+    if (valid && tn && (kp & (span - 1)) == 0)
+      store_words<NW>(tn + (TreeNodes<ID>::off(z - 1) + (kp >> (z - 1))) * NW, v);
     uint32_t lr[2 * NW];
 #pragma unroll
     for (int u = 0; u < NW; u++) {
@@ -509,6 +536,7 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
     }
   }
   if (valid && kp == 0 && J.root_out) store_words<NW>(J.root_out, v);
+  if (valid && kp == 0 && tn) store_words<NW>(tn + TreeNodes<ID>::off(HP) * NW, v);
 }
 
 template <int ID, bool KEYGEN>
@@ -516,12 +544,16 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
                                                        WorkRec* __restrict__ recs, uint32_t ntrees,
                                                        uint8_t* sigs, uint32_t* __restrict__ stage,
                                                        uint32_t* __restrict__ spill,
-                                                       uint32_t key_slot, uint32_t* root_out) {
+                                                       uint32_t key_slot, uint32_t* root_out,
+                                                       const uint32_t* ulist, const uint32_t* ucount,
+                                                       uint32_t* nodes) {
+  const TreeList tl{ulist, ucount};
+  if (blockIdx.x * (kLeavesPerBlock / P<ID>::leaves) >= tl.count(ntrees)) return;  // beyond the distinct trees
   uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
-  tree_chains<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x);
+  tree_chains<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl);
   __syncthreads();
   if ((threadIdx.x >> 6) == 0)
-    tree_finish<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x);
+    tree_finish<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
 }
 
 // ------------------------------------------------------------------ fused
@@ -547,14 +579,18 @@ template <int ID, int FG>
 __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg, uint8_t* sigs,
     uint32_t* __restrict__ stage, uint32_t* __restrict__ spill, uint32_t* __restrict__ roots, uint32_t* queue,
-    uint32_t ntb, uint32_t nfg) {
+    uint32_t ntb, uint32_t nfg, const uint32_t* ulist, const uint32_t* ucount, uint32_t* nodes) {
   static_assert(kTreeThreads == kForsThreads, "one workgroup shape for both item kinds");
   using Q = P<ID>;
   constexpr size_t SW = size_t(Q::len) * kLeavesPerBlock * Q::NW;  // words of one staging buffer
   __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * Q::NW];
   __shared__ uint32_t item;
   uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * SW;
-  const uint32_t total = ntb + nfg, ntrees = nmsg * Q::d;
+  const TreeList tl{ulist, ucount};
+  const uint32_t ntrees = nmsg * Q::d;
+  constexpr uint32_t TPB = kLeavesPerBlock / Q::leaves;
+  if (ucount) ntb = (*ucount + TPB - 1) / TPB;  // TREE blocks over the distinct trees only
+  const uint32_t total = ntb + nfg;
   const bool w0 = (threadIdx.x >> 6) == 0;
   uint32_t pend = 0xffffffffu;  // TREE block waiting for its finish (uniform)
   uint32_t cur = 0;             // staging buffer of the next TREE block (uniform)
@@ -566,11 +602,12 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     if (it >= total) break;
     if (pend != 0xffffffffu) {
       // finish the previous TREE block while the other waves start this item
-      if (w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u, nullptr, pend);
+      if (w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u, nullptr, pend, tl,
+                                     nodes);
       pend = 0xffffffffu;
     }
     if (it < ntb) {
-      tree_chains<ID, false>(keys, recs, ntrees, sigs, st0 + cur * SW, spill, 0u, nullptr, it);
+      tree_chains<ID, false>(keys, recs, ntrees, sigs, st0 + cur * SW, spill, 0u, nullptr, it, tl);
       pend = it;
       cur ^= 1;
     } else {
@@ -578,13 +615,46 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     }
   }
   if (pend != 0xffffffffu && w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u,
-                                                        nullptr, pend);
+                                                        nullptr, pend, tl, nodes);
 }
 
 // ------------------------------------------------------------------ WOTS
 // One lane per (message, layer, chain): digit of the layer's message
 // (FORS pk for layer 0, root of layer j-1 otherwise) with the checksum
-// digits appended (FIPS 205 Algorithm 7), then the kept chain value.
+// digits appended (FIPS 205 Algorithm 7), then the chain value at that digit.
+template <int ID>
+__device__ __forceinline__ uint32_t wots_digit(const WorkRec& W, uint32_t layer, uint32_t c) {
+  using Q = P<ID>;
+  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
+  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
+  if (c < uint32_t(Q::len1)) return nib(c);
+  uint32_t csum = 0;
+  for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
+  csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
+  return (csum >> (12 - 4 * (c - Q::len1))) & 15u;
+}
+
+// Chain c of the signing leaf of job J advanced `digit` steps from its PRF
+// secret (FIPS 205 Algorithms 5 and 7).
+template <int ID>
+__device__ __forceinline__ void wots_value(const TreeJob& J, uint32_t c, uint32_t digit, uint32_t x[P<ID>::NW]) {
+  constexpr int NW = P<ID>::NW;
+  uint32_t mid[8], sks[NW];
+  load_words<8>(J.key->mid256, mid);
+  load_words<NW>(J.key->sk_seed, sks);
+  const uint32_t kp = uint32_t(J.sign_leaf);
+  thF<ID>(mid, make_adrs(J.layer, J.tree, A_WOTS_PRF, kp, c, 0), sks, x);
+  Adrs A = make_adrs(J.layer, J.tree, A_WOTS_HASH, kp, c, 0);
+  for (uint32_t st = 0; st < digit; st++) {
+    A.tail = st << 16;
+    uint32_t y[NW];
+    th256<NW, NW>(mid, A, x, y);
+#pragma unroll
+    for (int u = 0; u < NW; u++) x[u] = y[u];
+  }
+}
+
+// Gather from the kept chain values of the signing leaves.
 template <int ID>
 __global__ void k_wots(const WorkRec* __restrict__ recs, uint32_t count, uint8_t* sigs,
                        const uint32_t* __restrict__ spill) {
@@ -596,17 +666,7 @@ __global__ void k_wots(const WorkRec* __restrict__ recs, uint32_t count, uint8_t
   const uint32_t ftree = gid / LEN, c = gid - ftree * LEN;
   const uint32_t msg = ftree / Q::d, layer = ftree - msg * Q::d;
   const WorkRec& W = recs[msg];
-  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
-  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
-  uint32_t digit;
-  if (c < uint32_t(Q::len1)) {
-    digit = nib(c);
-  } else {
-    uint32_t csum = 0;
-    for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
-    csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
-    digit = (csum >> (12 - 4 * (c - Q::len1))) & 15u;
-  }
+  const uint32_t digit = wots_digit<ID>(W, layer, c);
   const uint32_t* src = spill + ((size_t(ftree) * LEN + c) * 16 + digit) * NW;
   uint32_t v[NW];
   load_words<NW>(src, v);
@@ -615,7 +675,7 @@ __global__ void k_wots(const WorkRec* __restrict__ recs, uint32_t count, uint8_t
 
 // WOTS+ signatures recomputed instead of gathered (for contexts that do not
 // keep the chain values of the signing leaves): one lane per chain runs PRF
-// and then `digit` F steps (FIPS 205 Algorithm 7).
+// and then `digit` F steps.
 template <int ID>
 __global__ void k_wots_recompute(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                  uint32_t count, uint8_t* sigs) {
@@ -626,32 +686,143 @@ __global__ void k_wots_recompute(const DevKey* __restrict__ keys, WorkRec* __res
   if (gid >= total) return;
   const uint32_t ftree = gid / LEN, c = gid - ftree * LEN;
   const TreeJob J = sign_job<ID>(keys, recs, sigs, nullptr, ftree);
-  const uint32_t msg = ftree / Q::d, layer = ftree - msg * Q::d;
+  uint32_t x[NW];
+  wots_value<ID>(J, c, wots_digit<ID>(recs[ftree / Q::d], J.layer, c), x);
+  store_be<NW>(J.sig_xmss + c * Q::n, x);
+}
+
+// ------------------------------------------------------------------ dedup
+// Within-batch dedup of XMSS trees.  Two (message, layer) pairs whose key,
+// layer and tree address agree need the same tree; only the one with the
+// smallest flat tree id (the representative) computes it.  Layers whose tree
+// address has at most 35 bits are eligible, so that key slot (24 bits), layer
+// (5 bits) and tree address form one exact 64-bit key; a repeat of a wider
+// address within one batch has probability below 2^-10 per batch of 2^12.
+// The map is an open-addressing table of 2^k >= 2 entries per tree.
+struct DedupSlot {
+  unsigned long long key;
+  uint32_t owner;
+  uint32_t pad;
+};
+constexpr unsigned long long kDedupEmpty = ~0ull;
+
+__global__ void k_dedup_init(DedupSlot* table, uint32_t size, uint32_t* ucount) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < size) {
+    table[i].key = kDedupEmpty;
+    table[i].owner = 0xffffffffu;
+  }
+  if (i == 0) *ucount = 0;
+}
+
+__device__ __forceinline__ uint32_t dedup_hash(unsigned long long k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return uint32_t(k);
+}
+
+// rep[ft] <- table slot of its triple, or 0xffffffff when not eligible.
+template <int ID>
+__global__ void k_dedup_insert(const WorkRec* __restrict__ recs, uint32_t nmsg, DedupSlot* table, uint32_t size,
+                               uint32_t* rep) {
+  using Q = P<ID>;
+  const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ft >= nmsg * Q::d) return;
+  const uint32_t msg = ft / Q::d, layer = ft - msg * Q::d;
   const WorkRec& W = recs[msg];
-  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
-  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
-  uint32_t digit;
-  if (c < uint32_t(Q::len1)) {
-    digit = nib(c);
-  } else {
-    uint32_t csum = 0;
-    for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
-    csum <<= 4;
-    digit = (csum >> (12 - 4 * (c - Q::len1))) & 15u;
+  const int bits = Q::tree_bits - int(Q::hp * layer);  // bits of this layer's tree address
+  if (bits > 35 || W.key_slot >= (1u << 24)) {
+    rep[ft] = 0xffffffffu;
+    return;
   }
-  uint32_t mid[8], sks[NW], x[NW];
-  load_words<8>(J.key->mid256, mid);
-  load_words<NW>(J.key->sk_seed, sks);
-  const uint32_t kp = uint32_t(J.sign_leaf);
-  thF<ID>(mid, make_adrs(layer, J.tree, A_WOTS_PRF, kp, c, 0), sks, x);
-  Adrs A = make_adrs(layer, J.tree, A_WOTS_HASH, kp, c, 0);
-  for (uint32_t st = 0; st < digit; st++) {
-    A.tail = st << 16;
-    uint32_t y[NW];
-    th256<NW, NW>(mid, A, x, y);
-#pragma unroll
-    for (int u = 0; u < NW; u++) x[u] = y[u];
+  const uint32_t sh = Q::hp * layer;
+  const unsigned long long tree = sh >= 64 ? 0ull : (W.idx_tree >> sh);
+  const unsigned long long key = (unsigned long long)W.key_slot << 40 | (unsigned long long)layer << 35 | tree;
+  uint32_t h = dedup_hash(key) & (size - 1);
+  for (uint32_t probe = 0; probe < size; probe++) {
+    const unsigned long long prev = atomicCAS(&table[h].key, kDedupEmpty, key);
+    if (prev == kDedupEmpty || prev == key) {
+      atomicMin(&table[h].owner, ft);
+      rep[ft] = h;
+      return;
+    }
+    h = (h + 1) & (size - 1);
   }
+  rep[ft] = 0xffffffffu;  // table full (cannot happen at 2 entries per tree): compute it alone
+}
+
+// rep[ft] <- representative flat tree id; representatives are appended to
+// ulist (order irrelevant: every output position is fixed by the tree id).
+template <int ID>
+__global__ void k_dedup_resolve(uint32_t nmsg, const DedupSlot* table, uint32_t* rep, uint32_t* ulist,
+                                uint32_t* ucount) {
+  const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ft >= nmsg * P<ID>::d) return;
+  const uint32_t h = rep[ft];
+  const uint32_t r = h == 0xffffffffu ? ft : table[h].owner;
+  rep[ft] = r;
+  if (r == ft) ulist[atomicAdd(ucount, 1u)] = ft;
+}
+
+// Running totals of eligible-or-not trees and distinct trees computed (one
+// lane; stream order makes plain adds safe).
+__global__ void k_dedup_stats(uint32_t trees, const uint32_t* ucount, unsigned long long* stats) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    stats[0] += trees;
+    stats[1] += *ucount;
+  }
+}
+
+// Auth path and root of every non-representative (message, layer) from the
+// representative's node buffer; one lane per pair.
+template <int ID>
+__global__ void k_dedup_scatter(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg,
+                                uint8_t* sigs, const uint32_t* __restrict__ rep, const uint32_t* __restrict__ nodes) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW;
+  const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ft >= nmsg * Q::d) return;
+  const uint32_t r = rep[ft];
+  if (r == ft) return;
+  const TreeJob J = sign_job<ID>(keys, recs, sigs, nullptr, ft);
+  const uint32_t leaf = uint32_t(J.sign_leaf);
+  const uint32_t* tn = nodes + size_t(r) * TreeNodes<ID>::count * NW;
+  uint8_t* xs = J.sig_xmss + Q::len * Q::n;
+  for (int z = 0; z < Q::hp; z++) {
+    uint32_t v[NW];
+    load_words<NW>(tn + (TreeNodes<ID>::off(z) + ((leaf >> z) ^ 1u)) * NW, v);
+    store_be<NW>(xs + z * Q::n, v);
+  }
+  if (J.root_out) {
+    uint32_t v[NW];
+    load_words<NW>(tn + TreeNodes<ID>::off(Q::hp) * NW, v);
+    store_words<NW>(J.root_out, v);
+  }
+}
+
+// WOTS+ signatures with dedup.  The kept chain values of a tree's
+// representative serve every pair whose signing leaf is the representative's
+// (same key, tree and leaf: same chains, whatever the digits); the other
+// pairs recompute their chains.
+template <int ID>
+__global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t count,
+                             uint8_t* sigs, const uint32_t* __restrict__ spill, const uint32_t* __restrict__ rep) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len;
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= count * Q::d * LEN) return;
+  const uint32_t ftree = gid / LEN, c = gid - ftree * LEN;
+  const TreeJob J = sign_job<ID>(keys, recs, sigs, nullptr, ftree);
+  const uint32_t digit = wots_digit<ID>(recs[ftree / Q::d], J.layer, c);
+  const uint32_t r = rep[ftree];
+  uint32_t x[NW];
+  if (r == ftree || sign_job<ID>(keys, recs, sigs, nullptr, r).sign_leaf == J.sign_leaf)
+    load_words<NW>(spill + ((size_t(r) * LEN + c) * 16 + digit) * NW, x);
+  else
+    wots_value<ID>(J, c, digit, x);
   store_be<NW>(J.sig_xmss + c * Q::n, x);
 }
 
@@ -661,7 +832,7 @@ __global__ void k_wots_recompute(const DevKey* __restrict__ keys, WorkRec* __res
 // layer, WOTS+ pkFromSig with one lane per chain, T_len and the auth-path
 // climb on lane 0.  The result is 1 (valid) or 0.
 struct VerifyItem {
-  uint64_t msg_off, msg_len, sig_off, pk_off;
+  uint64_t msg_off, msg_len, sig_off, pk_off, res_idx;
 };
 constexpr int kVerifyThreads = 128;
 
@@ -809,7 +980,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     bool ok = true;
 #pragma unroll
     for (int u = 0; u < NW; u++) ok = ok && (cur[u] == pk_root[u]);
-    results[b] = ok ? 1 : 0;
+    results[it.res_idx] = ok ? 1 : 0;
   }
 }
 

@@ -93,7 +93,7 @@ struct slh_server {
   std::deque<Done> outbox;
   std::thread worker;
   // delivery of completed lanes (copies results out) off the scheduler thread
-  std::thread drainer;
+  std::thread drainer[2];
   std::mutex dmu;
   std::condition_variable dcv;
   std::deque<Lane*> drainq;
@@ -223,7 +223,10 @@ int step(slh_server* s, double t, double* lat, bool online) {
     if (L.busy || L.draining || s->pending.empty()) continue;
     const bool full = s->pending.size() >= s->cfg.max_batch;
     const bool idle = busy == 0;
-    const bool old = t - s->pending.front().arrival >= s->cfg.max_wait_us * 1e-6;
+    // with batches already in flight the GPU is fed; let the next one grow
+    // longer (max_wait per busy lane) so that batches stay efficient
+    const double wait = s->cfg.max_wait_us * 1e-6 * double(busy < 1 ? 1 : busy);
+    const bool old = t - s->pending.front().arrival >= wait;
     const bool enough = s->cfg.min_batch && s->pending.size() >= s->cfg.min_batch;
     if (!(full || idle || old || enough)) break;
     const int rc = launch(s, L);
@@ -291,14 +294,14 @@ int slh_serve_create(int device, const slh_serve_config* cfg_in, slh_server** ou
   *out = nullptr;
   slh_serve_config cfg{};
   if (cfg_in) cfg = *cfg_in;
-  if (cfg.lanes == 0) cfg.lanes = 3;
+  if (cfg.lanes == 0) cfg.lanes = 4;
   if (cfg.max_batch == 0) cfg.max_batch = 4096;
   if (cfg.max_wait_us == 0) cfg.max_wait_us = 2000;
   if (cfg.msg_bytes == 0) cfg.msg_bytes = uint64_t(64) << 20;
   if (cfg.hbm_budget == 0) cfg.hbm_budget = uint64_t(4) << 30;
   if (cfg.queue_limit == 0) cfg.queue_limit = 1u << 20;
   if (cfg.lanes > 8 || cfg.max_batch > (1u << 20) || cfg.min_batch > cfg.max_batch ||
-      (cfg.mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH)))
+      (cfg.mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH | SLH_MODE_DEDUP)))
     return SLH_EINVAL;
   slh_server* s = new slh_server();
   s->device = device;
@@ -326,7 +329,7 @@ int slh_serve_create(int device, const slh_serve_config* cfg_in, slh_server** ou
     delete s;
     return rc;
   }
-  s->drainer = std::thread(drain_main, s);
+  for (auto& t : s->drainer) t = std::thread(drain_main, s);
   *out = s;
   return SLH_OK;
 }
@@ -339,7 +342,8 @@ int slh_serve_destroy(slh_server* s) {
     s->drain_exit = true;
   }
   s->dcv.notify_all();
-  if (s->drainer.joinable()) s->drainer.join();
+  for (auto& t : s->drainer)
+    if (t.joinable()) t.join();
   for (Lane& L : s->lanes) free_lane(L);
   delete s;
   return SLH_OK;

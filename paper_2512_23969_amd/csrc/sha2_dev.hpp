@@ -174,40 +174,71 @@ __device__ __forceinline__ void sha512_iv(u64p s[8]) {
   s[6] = mk64(0x1f83d9abfb41bd6bull); s[7] = mk64(0x5be0cd19137e2179ull);
 }
 
-// Sixteen SHA-512 rounds r0 .. r0+15 with the message schedule extended in
-// place (SCHED: rounds >= 16).  Ring-buffer indices are compile-time
-// constants, so w[] stays in VGPRs; after sixteen rounds the working
-// variables are back in their original registers.
+// 64-bit helpers on native uint64_t values (kept in aligned register pairs,
+// which v_lshl_add_u64 needs; building results as pairs avoids the register
+// moves a (hi, lo) struct formulation costs).
+__device__ __forceinline__ uint64_t pair64(uint32_t hi, uint32_t lo) { return (uint64_t(hi) << 32) | lo; }
+template <int R>
+__device__ __forceinline__ uint64_t rot64(uint64_t x) {
+  const uint32_t hi = uint32_t(x >> 32), lo = uint32_t(x);
+  if constexpr (R < 32) {
+    return pair64(__builtin_amdgcn_alignbit(lo, hi, R), __builtin_amdgcn_alignbit(hi, lo, R));
+  } else if constexpr (R == 32) {
+    return pair64(lo, hi);
+  } else {
+    return pair64(__builtin_amdgcn_alignbit(hi, lo, R - 32), __builtin_amdgcn_alignbit(lo, hi, R - 32));
+  }
+}
+__device__ __forceinline__ uint64_t xor3_u64(uint64_t a, uint64_t b, uint64_t c) {
+  return pair64(xor3(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32)),
+                xor3(uint32_t(a), uint32_t(b), uint32_t(c)));
+}
+__device__ __forceinline__ uint64_t ch_u64(uint64_t e, uint64_t f, uint64_t g) {
+  return pair64(ch32(uint32_t(e >> 32), uint32_t(f >> 32), uint32_t(g >> 32)), ch32(uint32_t(e), uint32_t(f), uint32_t(g)));
+}
+__device__ __forceinline__ uint64_t maj_u64(uint64_t a, uint64_t b, uint64_t c) {
+  return pair64(maj32(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32)), maj32(uint32_t(a), uint32_t(b), uint32_t(c)));
+}
+
+// Sixteen SHA-512 rounds with the message schedule extended in place (SCHED:
+// rounds >= 16).  Ring-buffer indices are compile-time constants, so w[]
+// stays in VGPRs; after sixteen rounds the working variables are back in
+// their original registers.  kr: the sixteen round constants.
 template <bool SCHED>
-__device__ __forceinline__ void sha512_16rounds(u64p& a, u64p& b, u64p& c, u64p& d, u64p& e, u64p& f,
-                                                u64p& g, u64p& h, u64p w[16], const uint64_t* kr) {
+__device__ __forceinline__ void sha512_16rounds(uint64_t& a, uint64_t& b, uint64_t& c, uint64_t& d, uint64_t& e,
+                                                uint64_t& f, uint64_t& g, uint64_t& h, uint64_t w[16],
+                                                const uint64_t* kr) {
 #pragma unroll
   for (int i = 0; i < 16; i++) {
     if (SCHED) {
-      u64p x15 = w[(i + 1) & 15], x2 = w[(i + 14) & 15];
-      u64p s0 = xor3_64(rotr64<1>(x15), rotr64<8>(x15), shr64<7>(x15));
-      u64p s1 = xor3_64(rotr64<19>(x2), rotr64<61>(x2), shr64<6>(x2));
-      w[i] = mk64(to64(w[i]) + to64(s0) + to64(w[(i + 9) & 15]) + to64(s1));
+      const uint64_t x15 = w[(i + 1) & 15], x2 = w[(i + 14) & 15];
+      const uint64_t s0 = xor3_u64(rot64<1>(x15), rot64<8>(x15), x15 >> 7);
+      const uint64_t s1 = xor3_u64(rot64<19>(x2), rot64<61>(x2), x2 >> 6);
+      w[i] = w[i] + s0 + w[(i + 9) & 15] + s1;
     }
-    u64p S1 = xor3_64(rotr64<14>(e), rotr64<18>(e), rotr64<41>(e));
-    u64p S0 = xor3_64(rotr64<28>(a), rotr64<34>(a), rotr64<39>(a));
-    uint64_t t1 = to64(h) + (kr[i] + to64(w[i])) + to64(S1) + to64(ch64(e, f, g));
-    uint64_t t2 = to64(S0) + to64(maj64(a, b, c));
-    h = g; g = f; f = e; e = mk64(to64(d) + t1); d = c; c = b; b = a; a = mk64(t1 + t2);
+    const uint64_t S1 = xor3_u64(rot64<14>(e), rot64<18>(e), rot64<41>(e));
+    const uint64_t S0 = xor3_u64(rot64<28>(a), rot64<34>(a), rot64<39>(a));
+    const uint64_t t1 = h + (kr[i] + w[i]) + S1 + ch_u64(e, f, g);
+    const uint64_t t2 = S0 + maj_u64(a, b, c);
+    h = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = t1 + t2;
   }
 }
 
 // One SHA-512 compression: st <- st + rounds(st, w).  w[] is overwritten.
 // Rounds 0-15 are peeled; rounds 16-79 run as a loop of four 16-round
 // blocks, which keeps the code at two copies of sixteen rounds.
-__device__ __forceinline__ void sha512_compress(u64p st[8], u64p w[16]) {
-  u64p a = st[0], b = st[1], c = st[2], d = st[3], e = st[4], f = st[5], g = st[6], h = st[7];
+__device__ __forceinline__ void sha512_compress(u64p st[8], u64p w16[16]) {
+  uint64_t w[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) w[i] = to64(w16[i]);
+  uint64_t a = to64(st[0]), b = to64(st[1]), c = to64(st[2]), d = to64(st[3]);
+  uint64_t e = to64(st[4]), f = to64(st[5]), g = to64(st[6]), h = to64(st[7]);
   sha512_16rounds<false>(a, b, c, d, e, f, g, h, w, kK512);
 #pragma unroll 1
   for (int r = 16; r < 80; r += 16) sha512_16rounds<true>(a, b, c, d, e, f, g, h, w, kK512 + r);
-  st[0] = add64(st[0], a); st[1] = add64(st[1], b); st[2] = add64(st[2], c);
-  st[3] = add64(st[3], d); st[4] = add64(st[4], e); st[5] = add64(st[5], f);
-  st[6] = add64(st[6], g); st[7] = add64(st[7], h);
+  st[0] = mk64(to64(st[0]) + a); st[1] = mk64(to64(st[1]) + b); st[2] = mk64(to64(st[2]) + c);
+  st[3] = mk64(to64(st[3]) + d); st[4] = mk64(to64(st[4]) + e); st[5] = mk64(to64(st[5]) + f);
+  st[6] = mk64(to64(st[6]) + g); st[7] = mk64(to64(st[7]) + h);
 }
 
 }  // namespace slh

@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(_HERE, "libslh.so")
 SHA2_128F, SHA2_192F, SHA2_256F = 1, 2, 3
 NAMES = {1: "128f", 2: "192f", 3: "256f"}
 IDS = {v: k for k, v in NAMES.items()}
-MODE_PLAIN, MODE_FUSED, MODE_GRAPH = 0, 1, 2
+MODE_PLAIN, MODE_FUSED, MODE_GRAPH, MODE_DEDUP = 0, 1, 2, 4
 MODES = {"plain": MODE_PLAIN, "fused": MODE_FUSED, "graph": MODE_GRAPH | MODE_FUSED,
-         "graph-plain": MODE_GRAPH}
+         "graph-plain": MODE_GRAPH, "dedup": MODE_DEDUP, "fused-dedup": MODE_FUSED | MODE_DEDUP,
+         "graph-dedup": MODE_GRAPH | MODE_FUSED | MODE_DEDUP}
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
 PHASES = ("prelude", "fors", "tree", "wots", "fused")
@@ -53,6 +54,10 @@ class slh_serve_stats(ctypes.Structure):
                 ("sig_per_s", ctypes.c_double), ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
                 ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double), ("mean_batch", ctypes.c_double)]
 
+
+VERIFY_DTYPE = np.dtype([("param", "<u4"), ("pad", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
+                         ("sig_off", "<u8"), ("pk_off", "<u8")])
+assert VERIFY_DTYPE.itemsize == 40
 
 REQ_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
                       ("sig_off", "<u8"), ("arrival_s", "<f8")])
@@ -89,6 +94,8 @@ def _load():
     L.slh_ctx_get_tuning.argtypes = [vp, u32, ctypes.POINTER(slh_tuning)]
     L.slh_ctx_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
                                       ctypes.POINTER(u64), ctypes.c_int]
+    L.slh_verify_batch.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, u64, vp, vp]
+    L.slh_ctx_dedup_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.c_int]
     L.slh_serve_create.argtypes = [ctypes.c_int, ctypes.POINTER(slh_serve_config), ctypes.POINTER(vp)]
     L.slh_serve_destroy.argtypes = [vp]
     L.slh_serve_last_error.argtypes = [vp]
@@ -201,6 +208,23 @@ class Context:
         me = (ctypes.c_uint64 * n)()
         _check(lib.slh_ctx_phase_times(self.h, ms, la, me, 1 if reset else 0), self.h)
         return {p: (ms[i], la[i], me[i]) for i, p in enumerate(PHASES)}
+
+    def dedup_stats(self, reset: bool = True) -> tuple:
+        """(trees needed, distinct trees computed) of the dedup-mode calls."""
+        t, d = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib.slh_ctx_dedup_stats(self.h, ctypes.byref(t), ctypes.byref(d), 1 if reset else 0), self.h)
+        return t.value, d.value
+
+    def verify_batch(self, items: np.ndarray, msgs, sigs, pks, results, stream=None):
+        """Enqueue verification of `items` (VERIFY_DTYPE); results is an int32
+        CUDA tensor receiving 1 (valid) / 0 per item."""
+        items = np.ascontiguousarray(items, dtype=VERIFY_DTYPE)
+        mp, mb = _ptr(msgs)
+        sp, sb = _ptr(sigs)
+        pp, pb = _ptr(pks)
+        rp, _ = _ptr(results)
+        _check(lib.slh_verify_batch(self.h, items.ctypes.data, len(items), mp, mb, sp, sb, pp, pb, rp,
+                                    _stream_handle(stream)), self.h)
 
     def sign_batch(self, items: np.ndarray, msgs, sigs, mode: int = MODE_PLAIN, stream=None):
         """Enqueue signing of `items` (ITEM_DTYPE array) on `stream`.

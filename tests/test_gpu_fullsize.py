@@ -1,0 +1,80 @@
+"""Full-size parity in the launch configurations the benchmark times: each
+batch-4096 workload (128f 1 key, 192f 1 key, 256f 64 keys) signed in its
+autotuned mode and in the other modes (within-batch tree dedup included)
+gives identical bytes; 64 sampled
+signatures (plus the first and last) equal the oracle's; and every one of
+the 4096 signatures verifies on the GPU (a property that holds at any size),
+while corrupted copies do not."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import NAMES, describe_diff, oracle_sign_many
+from paper_2512_23969_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def slh():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2512_23969_amd import slh as m
+    return m
+
+
+@pytest.mark.parametrize("name", ["c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64"])
+def test_full_batch(slh, name):
+    import torch
+    from paper_2512_23969_amd import autotune
+    cfg = workloads.CONFIGS[name]
+    param, batch = cfg["param"], cfg["batch"]
+    keys = [slh.keygen(param, workloads.key_seed(param, i)) for i in range(cfg["keys"])]
+    kidx = workloads.key_assignment(cfg["cfg"], batch, cfg["keys"]) if cfg["keys"] > 1 else [0] * batch
+    msgs = workloads.messages(cfg["cfg"], batch, cfg["length"])
+    with slh.Context(0) as ctx:
+        first = ctx.add_keys(param, [sk for _, sk in keys])
+        slots = [first + k for k in kidx]
+        items, blob, total = slh.pack_batch([param] * batch, slots, msgs)
+        d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+        outs = {}
+        tuned = autotune.lookup(param, batch)
+        if tuned:
+            autotune.apply(ctx, param, tuned["best"])
+        for mode in ("plain", "fused", "graph", "dedup", "graph-dedup"):
+            d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
+            print(name, mode, flush=True)
+            ctx.sign_batch(items, d_m, d_s, mode=slh.MODES[mode])
+            torch.cuda.synchronize()
+            outs[mode] = d_s
+        for mode in ("fused", "graph", "dedup", "graph-dedup"):
+            assert torch.equal(outs[mode], outs["plain"]), mode
+        host = outs["plain"].cpu().numpy().tobytes()
+        sb = slh.sizes(param)["sig_bytes"]
+        sig = lambda i: host[int(items[i]["sig_off"]):int(items[i]["sig_off"]) + sb]  # noqa: E731
+        # sampled oracle comparison
+        sample = workloads.sample_indices(cfg["cfg"], batch, 64)
+        want = oracle_sign_many([(param, keys[kidx[i]][1], msgs[i]) for i in sample])
+        for i, w in zip(sample, want):
+            assert sig(i) == w, "%s item %d: %s" % (name, i, describe_diff(param, sig(i), w))
+        # every signature verifies on the GPU; flipped copies of a few do not
+        pks = b"".join(pk for pk, _ in keys)
+        d_pk = torch.frombuffer(bytearray(pks), dtype=torch.uint8).cuda()
+        npk = 2 * slh.sizes(param)["n"]
+        vit = np.zeros(batch + 8, dtype=slh.VERIFY_DTYPE)
+        for i in range(batch):
+            vit[i] = (param, 0, items[i]["msg_off"], items[i]["msg_len"], items[i]["sig_off"], kidx[i] * npk)
+        bad_sigs = d_s_bad = outs["plain"].clone()
+        for j in range(8):
+            i = sample[j]
+            off = int(items[i]["sig_off"]) + (j * 997) % sb
+            bad_sigs[off] ^= 1
+            vit[batch + j] = vit[i]
+        res = torch.zeros(batch + 8, dtype=torch.int32, device="cuda")
+        ctx.verify_batch(vit[:batch], d_m, outs["plain"], d_pk, res)
+        torch.cuda.synchronize()
+        assert int(res[:batch].sum()) == batch
+        res2 = torch.zeros(8, dtype=torch.int32, device="cuda")
+        ctx.verify_batch(vit[batch:], d_m, d_s_bad, d_pk, res2)
+        torch.cuda.synchronize()
+        assert int(res2.sum()) == 0
