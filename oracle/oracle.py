@@ -81,6 +81,10 @@ def lib():
             L.or_keygen.argtypes = [P, u8p, u8p, u8p, ctypes.c_void_p, ctypes.c_void_p]
             L.or_sign.argtypes = [P, u8p, sz, u8p, ctypes.c_char_p, ctypes.c_void_p]
             L.or_verify.argtypes = [P, u8p, sz, u8p, sz, u8p]
+            L.or_encode_ext.argtypes = [u8p, sz, u8p, sz, ctypes.c_int, ctypes.c_void_p]
+            L.or_encode_ext.restype = ctypes.c_long
+            L.or_sign_ext.argtypes = [P, u8p, sz, u8p, sz, ctypes.c_int, u8p, ctypes.c_char_p, ctypes.c_void_p]
+            L.or_verify_ext.argtypes = [P, u8p, sz, u8p, sz, ctypes.c_int, u8p, sz, u8p]
             L.or_counters_get.argtypes = [ctypes.c_void_p]
             _lib = L
     return _lib
@@ -275,6 +279,36 @@ def verify(p, msg: bytes, sig: bytes, pk: bytes) -> bool:
     rc = lib().or_verify(ctypes.byref(p), msg, len(msg), sig, len(sig), pk)
     if rc < 0:
         raise ValueError("or_verify failed")
+    return rc == 1
+
+
+# message encodings of the external interface (FIPS 205 Section 10)
+PURE, PH_SHA256, PH_SHA512 = 0, 1, 2
+
+
+def encode_ext(msg: bytes, ctx: bytes = b"", ph: int = PURE) -> bytes:
+    """M' of slh_sign / hash_slh_sign (Algorithms 22 and 23)."""
+    out = ctypes.create_string_buffer(2 + len(ctx) + max(len(msg), 75))
+    n = lib().or_encode_ext(msg, len(msg), ctx, len(ctx), ph, out)
+    if n < 0:
+        raise ValueError("or_encode_ext: bad arguments")
+    return out.raw[:n]
+
+
+def sign_ext(p, msg: bytes, sk: bytes, ctx: bytes = b"", ph: int = PURE, addrnd: bytes | None = None) -> bytes:
+    """slh_sign (ph = PURE) or hash_slh_sign (Algorithms 22 / 23)."""
+    p = p if isinstance(p, or_params) else params(p)
+    out = ctypes.create_string_buffer(sig_bytes(p))
+    if lib().or_sign_ext(ctypes.byref(p), msg, len(msg), ctx, len(ctx), ph, sk, addrnd, out) != 0:
+        raise ValueError("or_sign_ext failed")
+    return out.raw
+
+
+def verify_ext(p, msg: bytes, sig: bytes, pk: bytes, ctx: bytes = b"", ph: int = PURE) -> bool:
+    p = p if isinstance(p, or_params) else params(p)
+    rc = lib().or_verify_ext(ctypes.byref(p), msg, len(msg), ctx, len(ctx), ph, sig, len(sig), pk)
+    if rc < 0:
+        raise ValueError("or_verify_ext failed")
     return rc == 1
 
 

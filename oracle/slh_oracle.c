@@ -14,6 +14,7 @@
  */
 #include "slh_oracle.h"
 
+#include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------------ */
@@ -906,4 +907,77 @@ int or_verify(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t
     or_fors_pk_from_sig(p, sig_fors, md, pk_seed, A, pk_fors);
     const uint8_t *sig_ht = sig_fors + (size_t)p->k * (p->a + 1) * p->n;
     return ht_verify(p, pk_fors, sig_ht, pk_seed, idx_tree, idx_leaf, pk_root);
+}
+
+
+/* ---------------------------------------------------------------------- */
+/* External interface (FIPS 205 Section 10).                               */
+
+/* DER encodings of the hash function identifiers (FIPS 205 Section 10.2.2):
+ * id-sha256 = 2.16.840.1.101.3.4.2.1 and id-sha512 = 2.16.840.1.101.3.4.2.3,
+ * each as tag 06, length 09 and the nine content octets. */
+static const uint8_t OID_SHA256[11] = {0x06, 0x09, 0x60, 0x86, 0x48, 0x01, 0x65, 0x03, 0x04, 0x02, 0x01};
+static const uint8_t OID_SHA512[11] = {0x06, 0x09, 0x60, 0x86, 0x48, 0x01, 0x65, 0x03, 0x04, 0x02, 0x03};
+
+long or_encode_ext(const uint8_t *msg, size_t mlen, const uint8_t *ctx, size_t ctxlen, int ph,
+                   uint8_t *out)
+{
+    if (ctxlen > 255 || (ph != OR_PURE && ph != OR_PH_SHA256 && ph != OR_PH_SHA512)) return -1;
+    size_t o = 0;
+    out[o++] = (uint8_t)(ph == OR_PURE ? 0 : 1);      /* toByte(0 or 1, 1) */
+    out[o++] = (uint8_t)ctxlen;                       /* toByte(|ctx|, 1) */
+    if (ctxlen) memcpy(out + o, ctx, ctxlen);
+    o += ctxlen;
+    if (ph == OR_PURE) {
+        if (mlen) memcpy(out + o, msg, mlen);
+        o += mlen;
+    } else if (ph == OR_PH_SHA256) {
+        memcpy(out + o, OID_SHA256, 11);
+        o += 11;
+        or_sha256(msg, mlen, out + o);
+        o += 32;
+    } else {
+        memcpy(out + o, OID_SHA512, 11);
+        o += 11;
+        or_sha512(msg, mlen, out + o);
+        o += 64;
+    }
+    return (long)o;
+}
+
+static uint8_t *encode_alloc(const uint8_t *msg, size_t mlen, const uint8_t *ctx, size_t ctxlen, int ph,
+                             long *len)
+{
+    uint8_t *buf = (uint8_t *)malloc(2 + ctxlen + (mlen > 75 ? mlen : 75));
+    if (!buf) return NULL;
+    *len = or_encode_ext(msg, mlen, ctx, ctxlen, ph, buf);
+    if (*len < 0) {
+        free(buf);
+        return NULL;
+    }
+    return buf;
+}
+
+/* slh_sign (Algorithm 22) and hash_slh_sign (Algorithm 23). */
+int or_sign_ext(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t *ctx,
+                size_t ctxlen, int ph, const uint8_t *sk, const uint8_t *addrnd, uint8_t *sig)
+{
+    long len;
+    uint8_t *mp = encode_alloc(msg, mlen, ctx, ctxlen, ph, &len);
+    if (!mp) return -1;
+    int rc = or_sign(p, mp, (size_t)len, sk, addrnd, sig);
+    free(mp);
+    return rc;
+}
+
+/* slh_verify (Algorithm 24) and hash_slh_verify (Algorithm 25). */
+int or_verify_ext(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t *ctx,
+                  size_t ctxlen, int ph, const uint8_t *sig, size_t siglen, const uint8_t *pk)
+{
+    long len;
+    uint8_t *mp = encode_alloc(msg, mlen, ctx, ctxlen, ph, &len);
+    if (!mp) return -1;
+    int rc = or_verify(p, mp, (size_t)len, sig, siglen, pk);
+    free(mp);
+    return rc;
 }

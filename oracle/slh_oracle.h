@@ -28,9 +28,9 @@
  *
  * Precision: every value is an exact byte string; there is no floating point.
  *
- * Memory: every buffer belongs to the caller.  No function allocates on the
- * heap except or_sign / or_verify / or_keygen, which use bounded stack arrays
- * sized by the compile-time limits below.  Functions return 0 on success and
+ * Memory: every buffer belongs to the caller.  Only or_sign_ext and
+ * or_verify_ext allocate (the encoded message M'); or_sign / or_verify /
+ * or_keygen use bounded stack arrays sized by the compile-time limits below.  Functions return 0 on success and
  * a negative value on a bad argument (unknown parameters, sizes beyond the
  * limits); verify returns 1 (valid) or 0 (invalid).
  */
@@ -136,6 +136,23 @@ int or_sign(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t *
 /* Verification (Algorithm 20): 1 valid, 0 invalid, negative on bad params. */
 int or_verify(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t *sig,
               size_t siglen, const uint8_t *pk);
+
+/* External interface of FIPS 205 (Section 10).  ph selects the message
+ * encoding: OR_PURE (Algorithms 22 / 24: M' = 0 | len(ctx) | ctx | M) or
+ * OR_PH_SHA256 / OR_PH_SHA512 (Algorithms 23 / 25: M' = 1 | len(ctx) | ctx |
+ * OID(PH) | PH(M)).  ctxlen <= 255.  or_encode_ext writes M' to out (room for
+ * 2 + ctxlen + max(mlen, 75) bytes) and returns its length, or -1 on bad
+ * arguments.  or_sign_ext / or_verify_ext sign / verify M' with the internal
+ * functions (addrnd NULL: deterministic); they allocate M' on the heap. */
+#define OR_PURE 0
+#define OR_PH_SHA256 1
+#define OR_PH_SHA512 2
+long or_encode_ext(const uint8_t *msg, size_t mlen, const uint8_t *ctx, size_t ctxlen, int ph,
+                   uint8_t *out);
+int or_sign_ext(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t *ctx,
+                size_t ctxlen, int ph, const uint8_t *sk, const uint8_t *addrnd, uint8_t *sig);
+int or_verify_ext(const or_params *p, const uint8_t *msg, size_t mlen, const uint8_t *ctx,
+                  size_t ctxlen, int ph, const uint8_t *sig, size_t siglen, const uint8_t *pk);
 
 /* Per-thread call counters (reset / read).  Index: 0 F, 1 PRF, 2 H, 3 T_l,
  * 4 SHA-256 compressions, 5 SHA-512 compressions, 6 PRF_msg, 7 H_msg. */
