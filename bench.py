@@ -36,9 +36,11 @@ def setup(slh, workloads, name):
     param, batch = cfg["param"], cfg["batch"]
     ctx = slh.Context(0)
     slots = []
+    ctx.pks = []
     for i in range(cfg["keys"]):
         pk, sk = slh.keygen(param, workloads.key_seed(param, i))
         slots.append(ctx.add_keys(param, sk))
+        ctx.pks.append(pk)
     if cfg["keys"] > 1:
         kidx = workloads.key_assignment(cfg["cfg"], batch, cfg["keys"])
     else:
@@ -50,7 +52,33 @@ def setup(slh, workloads, name):
     return ctx, items, d_m, d_s, cfg, msgs, kidx
 
 
-def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None):
+def verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps):
+    """Batched GPU verification of the batch just signed: every signature
+    must verify; throughput over `steps` launches."""
+    import numpy as np
+    import torch
+    param, batch = cfg["param"], cfg["batch"]
+    npk = 2 * slh.sizes(param)["n"]
+    d_pk = torch.frombuffer(bytearray(b"".join(ctx.pks)), dtype=torch.uint8).cuda()
+    vit = np.zeros(batch, dtype=slh.VERIFY_DTYPE)
+    vit["param"] = param
+    vit["msg_off"] = items["msg_off"]
+    vit["msg_len"] = items["msg_len"]
+    vit["sig_off"] = items["sig_off"]
+    vit["pk_off"] = np.asarray(kidx, dtype=np.uint64) * npk
+    res = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    ctx.verify_batch(vit, d_m, d_s, d_pk, res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.verify_batch(vit, d_m, d_s, d_pk, res)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"value": round(batch * steps / el, 1), "unit": "verifications/s",
+            "ms_per_batch": round(1e3 * el / steps, 3), "all_valid": int(res.sum()) == batch}
+
+
+def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None, verify=False):
     import torch
     from paper_2512_23969_amd import autotune
     ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
@@ -81,6 +109,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     ctx.profile(False)
     phases = ctx.phase_times(reset=True)
     trees, distinct = ctx.dedup_stats(reset=True)
+    ver = verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps) if verify else None
     ctx.close()
     elapsed = t1 - t0
     return {
@@ -94,6 +123,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         "tuning": best,
         # (trees needed, distinct trees computed) per step, dedup modes only
         "dedup": (trees // (warmup + steps), distinct // (warmup + steps)) if trees else None,
+        "verify": ver,
     }
 
 
@@ -131,7 +161,7 @@ def cpu_baseline(name, workloads, seconds=15.0):
 TRAFFIC = {}  # (param, kernel) -> bytes per launch
 
 
-def serve_bench(slh, workloads, n, rates, log):
+def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0):
     """Serving workload: n requests, parameter set 50/30/20 % 128f/192f/256f,
     256 device-resident keys (128/77/51), log-normal message lengths (median
     256 B, 32 B - 16 KiB), random bytes.  First all requests at time 0 (the
@@ -147,7 +177,8 @@ def serve_bench(slh, workloads, n, rates, log):
     kidx = [k for _, k, _ in reqs]
     msgs = [m for _, _, m in reqs]
     log("serve: %d requests generated in %.1f s" % (n, time.perf_counter() - t0))
-    srv = slh.Server(0, lanes=4, max_batch=4096, max_wait_us=2000, mode=slh.MODE_FUSED)
+    srv = slh.Server(0, lanes=4, max_batch=4096, max_wait_us=2000, mode=slh.MODES[mode],
+                     cache_layers=cache_layers)
     slots = {}
     sks = {}
     for p, cnt in zip((1, 2, 3), keys_per_set):
@@ -156,7 +187,8 @@ def serve_bench(slh, workloads, n, rates, log):
     ks = [slots[p] + k for p, k in zip(params, kidx)]
     out = {"requests": n, "mix": "50/30/20 % 128f/192f/256f", "keys": 256,
            "msg_len": "log-normal, median 256 B, clipped to [32, 16384]", "lanes": 4, "max_batch": 4096,
-           "max_wait_us": 2000, "mode": "fused", "latency": "arrival to completion, host buffers (PCIe included)",
+           "max_wait_us": 2000, "mode": mode, "cache_layers": cache_layers,
+           "latency": "arrival to completion, host buffers (PCIe included)",
            "points": []}
     reqs0, blob = slh.trace(params, ks, msgs, [0.0] * n)
     sigs, lat, st = srv.replay(reqs0, blob)
@@ -251,6 +283,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-n", type=int, default=100000, help="requests of the serving workload (0 = skip)")
     ap.add_argument("--serve-rates", default="0.25,0.5,0.75,0.9,1.0,1.2")
+    ap.add_argument("--serve-mode", default="fused", choices=["plain", "fused", "dedup", "fused-dedup"])
+    ap.add_argument("--serve-cache-layers", type=int, default=0,
+                    help="upper hypertree layers cached per key on the server's lanes (dedup modes)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
@@ -272,7 +307,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log("bench: workload", args.workload)
-    res = run(slh, workloads, args.workload, args.steps, args.warmup, args.mode, args.tune, args.tune_out)
+    res = run(slh, workloads, args.workload, args.steps, args.warmup, args.mode, args.tune, args.tune_out,
+              verify=True)
     param = res["cfg"]["param"]
     c256, c512 = acc.compressions_per_signature(param)
     line = {
@@ -296,7 +332,10 @@ def main():
         "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param) / acc.VALU_PEAK_OPS, 4),
         "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items() if v[1]},
         "roofline": roofline(param, res),
+        "verify": res["verify"],
     }
+    if res["dedup"]:
+        line["dedup"] = {"trees_per_step": res["dedup"][0], "distinct_trees_per_step": res["dedup"][1]}
     if args.all:
         # every batch-4096 workload in the plain per-phase path and in the
         # batched modes (fused persistent kernel; hipGraph-captured pipeline)
@@ -308,13 +347,17 @@ def main():
                     continue
                 log("bench: workload", name, mode)
                 r = run(slh, workloads, name, steps_c, args.warmup, mode,
-                        args.tune and mode == "plain" and name != args.workload, args.tune_out)
+                        args.tune and mode == "plain" and name != args.workload, args.tune_out,
+                        verify=mode == "plain")
                 extra["%s/%s" % (name, mode)] = summary(acc, r, mode)
+                if r["verify"]:
+                    extra["%s/verify" % name] = r["verify"]
         line["extra"] = extra
     if args.serve_n:
         log("bench: serving")
         line["serving"] = serve_bench(slh, workloads, args.serve_n,
-                                      [float(x) for x in args.serve_rates.split(",")], log)
+                                      [float(x) for x in args.serve_rates.split(",")], log,
+                                      args.serve_mode, args.serve_cache_layers)
     if not args.no_cpu:
         log("bench: cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args.workload, workloads, args.cpu_seconds)

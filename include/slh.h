@@ -104,11 +104,12 @@ typedef struct slh_ctx slh_ctx;
  *                   a tree at some layer (FIPS 205 Algorithm 12: the layer's
  *                   tree address idx_tree >> (j h')) compute that tree once;
  *                   the others take its authentication path and root from a
- *                   node buffer and recompute only their WOTS+ chains.  Only
- *                   layers whose tree address has at most 35 bits are
+ *                   node buffer, and the chains of every leaf that some
+ *                   message signs with are kept, so WOTS+ stays a gather.
+ *                   Only layers whose tree address has at most 35 bits are
  *                   matched (wider addresses practically never repeat within
- *                   a batch).  Costs about (2^(h'+1) - 1) n + 24 bytes of
- *                   working memory per tree. */
+ *                   a batch).  Costs (2^(h'+1) - 1) n + 4 * 2^h' + 40 bytes
+ *                   of working memory per tree or less. */
 #define SLH_MODE_PLAIN 0u
 #define SLH_MODE_FUSED 1u
 #define SLH_MODE_GRAPH 2u
@@ -148,6 +149,19 @@ int slh_keygen(uint32_t param, const uint8_t *seed, uint8_t *pk, uint8_t *sk);
 int slh_ctx_add_keys(slh_ctx *ctx, uint32_t param, const uint8_t *sks, uint32_t count,
                      uint32_t *first_slot);
 
+/* Keep on the device every node of the XMSS trees of the top `layers`
+ * hypertree layers of keys first_slot .. first_slot + count - 1 (one
+ * parameter set).  These trees depend only on the key: layer d-1-u has
+ * 2^(h' u) of them, addressed by the tree index of FIPS 205 Algorithm 12.
+ * slh_sign_batch in SLH_MODE_DEDUP then takes the authentication path and
+ * root of those layers from the cache and only recomputes their WOTS+
+ * chains (Algorithm 10 with the cached nodes).  Memory per key:
+ * (2^(h' layers) - 1) / (2^h' - 1) trees of (2^(h'+1) - 1) n bytes, outside
+ * the context's HBM budget.  layers: 1..6 (128f, 192f), 1..4 (256f).
+ * Synchronous.  Errors: SLH_EINVAL (range outside the table, mixed sets, a
+ * key cached already, layers out of range), SLH_ENOMEM, SLH_EDEVICE. */
+int slh_ctx_cache_keys(slh_ctx *ctx, uint32_t first_slot, uint32_t count, uint32_t layers);
+
 /* Sign a batch (Algorithm 19 per request, deterministic).
  *   items       host array of `count` requests (any mix of parameter sets)
  *   msgs        device buffer holding the messages, msgs_bytes long
@@ -162,6 +176,44 @@ int slh_ctx_add_keys(slh_ctx *ctx, uint32_t param, const uint8_t *sks, uint32_t 
 int slh_sign_batch(slh_ctx *ctx, const slh_item *items, uint32_t count, const uint8_t *msgs,
                    uint64_t msgs_bytes, uint8_t *sigs, uint64_t sigs_bytes, uint32_t mode,
                    void *stream);
+
+/* One request of the external interface (FIPS 205 Section 10; host memory,
+ * 56 bytes).  Offsets index the batch's device message buffer.
+ *   param, key_slot, msg_off, msg_len, sig_off   as in slh_item
+ *   ctx_off, ctx_len  context string, 0..255 bytes
+ *   rnd_off    n bytes of fresh randomness for hedged signing (opt_rand of
+ *              Algorithm 19), or SLH_RND_NONE for the deterministic variant
+ *              (opt_rand = PK.seed)
+ *   prehash    SLH_PREHASH_NONE: pure SLH-DSA, Algorithm 22, signs
+ *              M' = 0 | len(ctx) | ctx | M;
+ *              SLH_PREHASH_SHA256 / _SHA512: HashSLH-DSA, Algorithm 23,
+ *              signs M' = 1 | len(ctx) | ctx | OID | SHA-256(M) / SHA-512(M) */
+typedef struct {
+    uint32_t param;
+    uint32_t key_slot;
+    uint64_t msg_off;
+    uint64_t msg_len;
+    uint64_t sig_off;
+    uint64_t ctx_off;
+    uint64_t rnd_off;
+    uint32_t ctx_len;
+    uint32_t prehash;
+} slh_item_ext;
+
+#define SLH_RND_NONE (~(uint64_t)0)
+#define SLH_PREHASH_NONE 0u
+#define SLH_PREHASH_SHA256 1u
+#define SLH_PREHASH_SHA512 2u
+
+/* Sign a batch through the external interface (Algorithms 22 and 23).  The
+ * library encodes every M' on the GPU (one workgroup per request; the
+ * pre-hash runs on one lane) into a buffer it owns, then signs as
+ * slh_sign_batch does; arguments, modes and errors as there, plus
+ * SLH_EINVAL for a context string over 255 bytes, an unknown pre-hash or an
+ * opt_rand range outside the message buffer. */
+int slh_sign_batch_ext(slh_ctx *ctx, const slh_item_ext *items, uint32_t count,
+                       const uint8_t *msgs, uint64_t msgs_bytes, uint8_t *sigs,
+                       uint64_t sigs_bytes, uint32_t mode, void *stream);
 
 /* Verify one signature (Algorithm 20) on the current GPU.  Host pointers.
  * Returns 1 if valid, 0 if not (including a wrong sig_len), negative on
@@ -189,6 +241,30 @@ typedef struct {
 int slh_verify_batch(slh_ctx *ctx, const slh_verify_item *items, uint32_t count, const uint8_t *msgs,
                      uint64_t msgs_bytes, const uint8_t *sigs, uint64_t sigs_bytes, const uint8_t *pks,
                      uint64_t pks_bytes, int32_t *results, void *stream);
+
+/* One verification request of the external interface (host memory, 56
+ * bytes): slh_verify_item plus the context string (ctx_off, ctx_len <= 255)
+ * and the encoding (prehash, as in slh_item_ext). */
+typedef struct {
+    uint32_t param;
+    uint32_t prehash;
+    uint64_t msg_off;
+    uint64_t msg_len;
+    uint64_t sig_off;
+    uint64_t pk_off;
+    uint64_t ctx_off;
+    uint32_t ctx_len;
+    uint32_t pad;
+} slh_verify_item_ext;
+
+/* Verify a batch through the external interface (slh_verify, Algorithm 24,
+ * and hash_slh_verify, Algorithm 25): M' is encoded on the GPU as for
+ * slh_sign_batch_ext, then verified as slh_verify_batch does; arguments and
+ * errors as there. */
+int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_t count,
+                         const uint8_t *msgs, uint64_t msgs_bytes, const uint8_t *sigs,
+                         uint64_t sigs_bytes, const uint8_t *pks, uint64_t pks_bytes,
+                         int32_t *results, void *stream);
 
 /* Kernel phases of the signing path, for per-phase timing. */
 #define SLH_PHASE_PRELUDE 0 /* PRF_msg, H_msg, index split                     */
@@ -261,6 +337,9 @@ typedef struct slh_server slh_server;
  *   mode         SLH_MODE_* of the launches [plain]
  *   queue_limit  waiting requests before slh_serve_submit says SLH_EBUSY
  *                [1 << 20]
+ *   cache_layers upper hypertree layers cached per key on every lane by
+ *                slh_serve_add_keys (slh_ctx_cache_keys; used in
+ *                SLH_MODE_DEDUP), clamped to the set's limit [0 = none]
  * A batch is launched when it is full, when no lane is busy, when its
  * oldest request has waited max_wait_us times the number of busy lanes, or
  * by the min_batch rule. */
@@ -273,6 +352,8 @@ typedef struct {
     uint64_t hbm_budget;
     uint32_t mode;
     uint32_t queue_limit;
+    uint32_t cache_layers;
+    uint32_t reserved;
 } slh_serve_config;
 
 /* One request of a replayed trace.  Offsets index the replay's host

@@ -131,6 +131,13 @@ struct slh_ctx {
   uint64_t phase_launches[SLH_NPHASES] = {0};
   uint64_t phase_units[SLH_NPHASES] = {0};
   unsigned long long* dstats = nullptr;  // device: trees, distinct trees (dedup mode)
+  uint8_t* cache = nullptr;              // device: cached upper-layer trees of keys
+  size_t cache_bytes = 0, cache_used = 0;
+  std::vector<uint32_t> key_cached;      // per key slot: cached layers
+  uint8_t* xbuf = nullptr;               // device: encoded messages of slh_sign_batch_ext
+  size_t xbuf_bytes = 0;
+  ExtJob* xjobs = nullptr;               // pinned host copy of their encode jobs
+  size_t xjobs_cap = 0;
 };
 
 namespace {
@@ -218,7 +225,7 @@ struct Plan {
   bool fused = false, dedup = false, keep = true;
   uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0, table = 0;
   size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
-  size_t o_table = 0, o_rep = 0, o_ulist = 0, o_nodes = 0, total = 0;
+  size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, total = 0;
   static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
   Plan(size_t n_, uint32_t mode, const Tuning& t, int cus)
       : n(n_), fused((mode & SLH_MODE_FUSED) != 0), dedup((mode & SLH_MODE_DEDUP) != 0), keep(t.keep != 0) {
@@ -240,15 +247,16 @@ struct Plan {
     o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
     o_queue = o_roots + up(n * Q::k * Q::NW * 4);
     // dedup: hash table (>= 2 slots per tree), representative per tree, list
-    // of representatives (its count is the word after the work counter), and
-    // every node of every tree
+    // of representatives (its count is the word after the work counter), the
+    // owner of every leaf of every tree, and every node of every tree
     o_table = o_queue + kAlign;
     if (dedup) {
       table = 2;
       while (table < 2 * trees) table <<= 1;
       o_rep = o_table + up(size_t(table) * sizeof(DedupSlot));
       o_ulist = o_rep + up(trees * 4);
-      o_nodes = o_ulist + up(trees * 4);
+      o_lown = o_ulist + up(trees * 4);
+      o_nodes = o_lown + up(trees * Q::leaves * 4);
       total = o_nodes + up(trees * TreeNodes<ID>::count * Q::NW * 4);
     } else {
       total = o_table;
@@ -285,6 +293,7 @@ struct DedupBufs {
   uint32_t* rep = nullptr;
   uint32_t* ulist = nullptr;
   uint32_t* ucount = nullptr;
+  uint32_t* lown = nullptr;
   uint32_t* nodes = nullptr;
 };
 
@@ -292,7 +301,7 @@ template <int ID, int FG>
 void launch_fused(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
                   uint32_t* roots, uint32_t* queue, const DedupBufs& db, hipStream_t s) {
   hipLaunchKernelGGL((k_fused<ID, FG>), dim3(pl.grid), dim3(kTreeThreads), 0, s, c->keys, recs, uint32_t(pl.n),
-                     sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist, db.ucount, db.nodes);
+                     sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist, db.ucount, db.lown, db.nodes);
 }
 
 // Enqueue one chunk on stream s.  `timing` is false while a graph is captured.
@@ -313,6 +322,7 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
     db.rep = reinterpret_cast<uint32_t*>(base + pl.o_rep);
     db.ulist = reinterpret_cast<uint32_t*>(base + pl.o_ulist);
     db.ucount = queue + 1;
+    db.lown = reinterpret_cast<uint32_t*>(base + pl.o_lown);
     db.nodes = reinterpret_cast<uint32_t*>(base + pl.o_nodes);
   }
   HIPCHK(c, hipMemcpyAsync(items, h_items, pl.n * sizeof(DevItem), hipMemcpyHostToDevice, s));
@@ -323,11 +333,13 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
     hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs, sigs, recs,
                        pl.fused ? queue : nullptr);
     if (pl.dedup) {
-      hipLaunchKernelGGL(k_dedup_init, dim3((pl.table + 255) / 256), dim3(256), 0, s, db.table, pl.table, db.ucount);
-      hipLaunchKernelGGL((k_dedup_insert<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, recs, n, db.table,
-                         pl.table, db.rep);
-      hipLaunchKernelGGL((k_dedup_resolve<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, n, db.table, db.rep,
-                         db.ulist, db.ucount);
+      const uint32_t nlown = trees * Q::leaves;
+      hipLaunchKernelGGL(k_dedup_init, dim3((std::max(pl.table, nlown) + 255) / 256), dim3(256), 0, s, db.table,
+                         pl.table, db.lown, nlown, db.ucount);
+      hipLaunchKernelGGL((k_dedup_insert<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, c->keys, recs, n,
+                         db.table, pl.table, db.rep);
+      hipLaunchKernelGGL((k_dedup_resolve<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, recs, n, db.table,
+                         db.rep, db.ulist, db.ucount, db.lown);
       hipLaunchKernelGGL(k_dedup_stats, dim3(1), dim3(64), 0, s, trees, db.ucount, c->dstats);
     }
   }
@@ -357,20 +369,20 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
     }
     {
       PhaseTimer t(c, s, SLH_PHASE_TREE, n, timing);
-      hipLaunchKernelGGL((k_tree<ID, false>), dim3(pl.ntb), dim3(kTreeThreads), 0, s, c->keys, recs, trees, sigs,
-                         stage, spill, 0u, nullptr, db.ulist, db.ucount, db.nodes);
+      hipLaunchKernelGGL((k_tree<ID, kSignTrees>), dim3(pl.ntb), dim3(kTreeThreads), 0, s, c->keys, recs, trees, sigs,
+                         stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, 0u);
     }
   }
   {
     PhaseTimer t(c, s, SLH_PHASE_WOTS, n, timing);
     if (pl.dedup)
       hipLaunchKernelGGL((k_dedup_scatter<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs,
-                         db.rep, db.nodes);
+                         db.rep, db.nodes, c->cache);
     hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, roots);
     const uint32_t nw = n * Q::d * Q::len;
     if (pl.keep && pl.dedup)
       hipLaunchKernelGGL((k_wots_dedup<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs, spill,
-                         db.rep);
+                         db.rep, db.lown);
     else if (pl.keep)
       hipLaunchKernelGGL((k_wots<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, recs, n, sigs, spill);
     else
@@ -464,8 +476,8 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
   e = hipMemcpy(dk, &hk, sizeof hk, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_key_midstates, dim3(1), dim3(64), 0, 0, dk, 0u, 1u);
-    hipLaunchKernelGGL((k_tree<ID, true>), dim3(1), dim3(kTreeThreads), 0, 0, dk, nullptr, 1u, nullptr,
-                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_tree<ID, kKeygenTree>), dim3(1), dim3(kTreeThreads), 0, 0, dk, nullptr, 1u, nullptr,
+                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr, nullptr, 0u);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpy(hroot, root, Q::n, hipMemcpyDeviceToHost);
@@ -482,6 +494,62 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
     }
   }
   std::memcpy(pk, seed + 2 * n, n);
+  return SLH_OK;
+}
+
+// Most cached layers per parameter set: at most 2^16 trees per key.
+uint32_t max_cache_layers(uint32_t param) { return param == 3 ? 4u : 6u; }
+
+// Build the cached upper layers of keys [first, first + count) (all of set ID).
+template <int ID>
+int cache_impl(slh_ctx* c, uint32_t first, uint32_t count, uint32_t layers) {
+  using Q = P<ID>;
+  const uint64_t per = CacheShape<ID>::trees(layers);
+  const uint64_t per_bytes = per * TreeNodes<ID>::count * Q::NW * 4;
+  const uint64_t need = per_bytes * count;
+  if (uint64_t(count) * per >= (1ull << 31)) return fail(c, SLH_EINVAL, "too many cached trees in one call");
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->cache_used + need > c->cache_bytes) {
+    // grow: the captured graphs hold the old address
+    const size_t nb = std::max<size_t>(c->cache_used + need, c->cache_bytes * 2);
+    uint8_t* nc = nullptr;
+    if (hipMalloc(&nc, nb) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "hipMalloc of the tree cache failed");
+    }
+    if (c->cache_used) HIPCHK(c, hipMemcpy(nc, c->cache, c->cache_used, hipMemcpyDeviceToDevice));
+    if (c->cache) HIPCHK(c, hipFree(c->cache));
+    c->cache = nc;
+    c->cache_bytes = nb;
+    drop_graphs(c);
+  }
+  const uint64_t off0 = c->cache_used;
+  hipLaunchKernelGGL(k_set_cache, dim3((count + 63) / 64), dim3(64), 0, 0, c->keys, first, count, layers, off0,
+                     per_bytes);
+  HIPCHK(c, hipGetLastError());
+  // all trees of the range, in launches of at most 1024 TREE blocks
+  constexpr uint32_t TPB = kLeavesPerBlock / Q::leaves;
+  constexpr uint32_t kMaxBlocks = 1024;
+  const size_t stage_bytes = size_t(kMaxBlocks) * Q::len * kLeavesPerBlock * Q::NW * 4;
+  uint32_t* stage = nullptr;
+  if (hipMalloc(&stage, stage_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SLH_ENOMEM, "hipMalloc of cache staging failed");
+  }
+  const uint32_t total = uint32_t(count * per);
+  uint32_t* nodes = reinterpret_cast<uint32_t*>(c->cache + off0);
+  hipError_t e = hipSuccess;
+  for (uint32_t t0 = 0; t0 < total && e == hipSuccess; t0 += kMaxBlocks * TPB) {
+    const uint32_t n = std::min<uint32_t>(kMaxBlocks * TPB, total - t0);
+    hipLaunchKernelGGL((k_tree<ID, kCacheTrees>), dim3((n + TPB - 1) / TPB), dim3(kTreeThreads), 0, 0, c->keys,
+                       nullptr, n, nullptr, stage, nullptr, first, nullptr, nullptr, nullptr, nullptr, nodes, t0);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  (void)hipFree(stage);
+  if (e != hipSuccess) return hip_fail(c, e, "tree cache build");
+  c->cache_used += need;
+  for (uint32_t i = 0; i < count; i++) c->key_cached[first + i] = layers;
   return SLH_OK;
 }
 
@@ -575,6 +643,9 @@ int slh_ctx_destroy(slh_ctx* c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->keys) (void)hipFree(c->keys);
   if (c->dstats) (void)hipFree(c->dstats);
+  if (c->cache) (void)hipFree(c->cache);
+  if (c->xbuf) (void)hipFree(c->xbuf);
+  if (c->xjobs) (void)hipHostFree(c->xjobs);
   if (c->staging) (void)hipHostFree(c->staging);
   if (c->vbuf) (void)hipFree(c->vbuf);
   if (c->vstage) (void)hipHostFree(c->vstage);
@@ -627,6 +698,24 @@ int slh_ctx_dedup_stats(slh_ctx* c, uint64_t* trees, uint64_t* distinct, int res
   return SLH_OK;
 }
 
+int slh_ctx_cache_keys(slh_ctx* c, uint32_t first_slot, uint32_t count, uint32_t layers) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (count == 0 || uint64_t(first_slot) + count > c->nkeys) return fail(c, SLH_EINVAL, "key range outside the table");
+  const uint32_t param = c->key_param[first_slot];
+  if (layers == 0 || layers > max_cache_layers(param))
+    return fail(c, SLH_EINVAL, "cached layers must be 1.." + std::to_string(max_cache_layers(param)));
+  for (uint32_t i = first_slot; i < first_slot + count; i++) {
+    if (c->key_param[i] != param) return fail(c, SLH_EINVAL, "keys of different parameter sets");
+    if (c->key_cached[i]) return fail(c, SLH_EINVAL, "key " + std::to_string(i) + " is cached already");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  switch (param) {
+    case 1: return cache_impl<1>(c, first_slot, count, layers);
+    case 2: return cache_impl<2>(c, first_slot, count, layers);
+    default: return cache_impl<3>(c, first_slot, count, layers);
+  }
+}
+
 int slh_ctx_add_keys(slh_ctx* c, uint32_t param, const uint8_t* sks, uint32_t count, uint32_t* first_slot) {
   Sizes s;
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
@@ -663,11 +752,17 @@ int slh_ctx_add_keys(slh_ctx* c, uint32_t param, const uint8_t* sks, uint32_t co
   *first_slot = c->nkeys;
   c->nkeys += count;
   c->key_param.resize(c->nkeys, param);
+  c->key_cached.resize(c->nkeys, 0);
   return SLH_OK;
 }
 
-int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint8_t* msgs, uint64_t msgs_bytes,
-                   uint8_t* sigs, uint64_t sigs_bytes, uint32_t mode, void* stream) {
+}  // extern "C"
+
+namespace {
+// slh_sign_batch with an optional opt_rand location per item (rnd[i] =
+// kNoRnd: deterministic).
+int sign_impl(slh_ctx* c, const slh_item* items, const uint64_t* rnd, uint32_t count, const uint8_t* msgs,
+              uint64_t msgs_bytes, uint8_t* sigs, uint64_t sigs_bytes, uint32_t mode, void* stream) {
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (count == 0) return SLH_OK;
   if (!items || !sigs) return fail(c, SLH_EINVAL, "null items or signature buffer");
@@ -717,6 +812,7 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
     DevItem& d = c->staging[start[it.param] + fill[it.param]++];
     d.param = it.param; d.key_slot = it.key_slot; d.msg_off = it.msg_off; d.msg_len = it.msg_len;
     d.sig_off = it.sig_off;
+    d.rnd_off = rnd ? rnd[i] : kNoRnd;
   }
   // working memory: the budget is shared by the parameter sets present
   int groups = 0;
@@ -772,6 +868,152 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
   HIPCHK(c, hipEventRecord(c->done, s));
   c->pending = true;
   return SLH_OK;
+}
+
+// One request of the external interface, as the encoder needs it.
+struct ExtReq {
+  uint32_t param, prehash, ctx_len;
+  uint64_t msg_off, msg_len, ctx_off, rnd_off;
+};
+
+// Validate external requests and lay out the encode buffer: the job table,
+// then per request opt_rand (if given) and M' (FIPS 205 Algorithms 22-25),
+// each 16-byte aligned.  *total: bytes of the buffer.
+int plan_ext(slh_ctx* c, const std::vector<ExtReq>& reqs, const uint8_t* msgs, uint64_t msgs_bytes,
+             std::vector<ExtJob>* jobs, uint64_t* total) {
+  const size_t count = reqs.size();
+  jobs->assign(count, ExtJob{});
+  uint64_t cur = up(uint64_t(count) * sizeof(ExtJob));
+  auto a16 = [](uint64_t x) { return (x + 15) / 16 * 16; };
+  for (size_t i = 0; i < count; i++) {
+    const ExtReq& r = reqs[i];
+    Sizes sz;
+    const std::string at = "item " + std::to_string(i) + ": ";
+    if (!sizes_of(r.param, &sz)) return fail(c, SLH_EINVAL, at + "unknown parameter set");
+    if (r.msg_len > msgs_bytes || r.msg_off > msgs_bytes - r.msg_len)
+      return fail(c, SLH_EINVAL, at + "message outside the message buffer");
+    if (r.ctx_len > 255) return fail(c, SLH_EINVAL, at + "context string longer than 255 bytes");
+    if (r.ctx_len > msgs_bytes || r.ctx_off > msgs_bytes - r.ctx_len)
+      return fail(c, SLH_EINVAL, at + "context string outside the message buffer");
+    if (r.prehash > SLH_PREHASH_SHA512) return fail(c, SLH_EINVAL, at + "unknown pre-hash");
+    if (r.rnd_off != SLH_RND_NONE && (sz.n > msgs_bytes || r.rnd_off > msgs_bytes - sz.n))
+      return fail(c, SLH_EINVAL, at + "opt_rand outside the message buffer");
+    if (!msgs && (r.msg_len || r.ctx_len || r.rnd_off != SLH_RND_NONE))
+      return fail(c, SLH_EINVAL, "null message buffer");
+    ExtJob& J = (*jobs)[i];
+    J.msg_off = r.msg_off;
+    J.msg_len = r.msg_len;
+    J.ctx_off = r.ctx_off;
+    J.ctx_len = r.ctx_len;
+    J.prehash = r.prehash;
+    J.n = sz.n;
+    J.rnd_in = r.rnd_off == SLH_RND_NONE ? kNoRnd : r.rnd_off;
+    if (J.rnd_in != kNoRnd) {
+      J.rnd_out = cur;
+      cur = a16(cur + sz.n);
+    }
+    const uint64_t body =
+        r.prehash == SLH_PREHASH_NONE ? r.msg_len : 11 + (r.prehash == SLH_PREHASH_SHA256 ? 32 : 64);
+    J.out_off = cur;
+    J.out_len = 2 + r.ctx_len + body;
+    cur = a16(cur + J.out_len);
+  }
+  *total = cur;
+  return SLH_OK;
+}
+
+// Encode the planned messages into the context's encode buffer on `stream`.
+int launch_encode(slh_ctx* c, const std::vector<ExtJob>& jobs, uint64_t total, const uint8_t* msgs, void* stream) {
+  const size_t count = jobs.size();
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // the encode buffer and its pinned job table may still be read by the last call
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->xbuf_bytes < total) {
+    drop_graphs(c);
+    if (c->xbuf) HIPCHK(c, hipFree(c->xbuf));
+    c->xbuf = nullptr;
+    c->xbuf_bytes = 0;
+    if (hipMalloc(&c->xbuf, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "hipMalloc of the encode buffer failed");
+    }
+    c->xbuf_bytes = total;
+  }
+  if (c->xjobs_cap < count) {
+    if (c->xjobs) HIPCHK(c, hipHostFree(c->xjobs));
+    c->xjobs = nullptr;
+    c->xjobs_cap = 0;
+    if (hipHostMalloc(&c->xjobs, count * sizeof(ExtJob)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "pinned job table allocation failed");
+    }
+    c->xjobs_cap = count;
+  }
+  std::memcpy(c->xjobs, jobs.data(), count * sizeof(ExtJob));
+  HIPCHK(c, hipMemcpyAsync(c->xbuf, c->xjobs, count * sizeof(ExtJob), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_encode_ext, dim3(uint32_t(count)), dim3(kEncodeThreads), 0, s,
+                     reinterpret_cast<const ExtJob*>(c->xbuf), msgs, c->xbuf);
+  HIPCHK(c, hipGetLastError());
+  return SLH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint8_t* msgs, uint64_t msgs_bytes,
+                   uint8_t* sigs, uint64_t sigs_bytes, uint32_t mode, void* stream) {
+  return sign_impl(c, items, nullptr, count, msgs, msgs_bytes, sigs, sigs_bytes, mode, stream);
+}
+
+int slh_sign_batch_ext(slh_ctx* c, const slh_item_ext* items, uint32_t count, const uint8_t* msgs,
+                       uint64_t msgs_bytes, uint8_t* sigs, uint64_t sigs_bytes, uint32_t mode, void* stream) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (count == 0) return SLH_OK;
+  if (!items || !sigs) return fail(c, SLH_EINVAL, "null items or signature buffer");
+  std::vector<ExtReq> reqs(count);
+  for (uint32_t i = 0; i < count; i++) {
+    const slh_item_ext& it = items[i];
+    reqs[i] = ExtReq{it.param, it.prehash, it.ctx_len, it.msg_off, it.msg_len, it.ctx_off, it.rnd_off};
+  }
+  std::vector<ExtJob> jobs;
+  uint64_t total = 0;
+  int rc = plan_ext(c, reqs, msgs, msgs_bytes, &jobs, &total);
+  if (rc) return rc;
+  std::vector<slh_item> inner(count);
+  std::vector<uint64_t> rnd(count);
+  for (uint32_t i = 0; i < count; i++) {
+    inner[i] = slh_item{items[i].param, items[i].key_slot, jobs[i].out_off, jobs[i].out_len, items[i].sig_off};
+    rnd[i] = jobs[i].rnd_in == kNoRnd ? kNoRnd : jobs[i].rnd_out;
+  }
+  rc = launch_encode(c, jobs, total, msgs, stream);
+  if (rc) return rc;
+  return sign_impl(c, inner.data(), rnd.data(), count, c->xbuf, total, sigs, sigs_bytes, mode, stream);
+}
+
+int slh_verify_batch_ext(slh_ctx* c, const slh_verify_item_ext* items, uint32_t count, const uint8_t* msgs,
+                         uint64_t msgs_bytes, const uint8_t* sigs, uint64_t sigs_bytes, const uint8_t* pks,
+                         uint64_t pks_bytes, int32_t* results, void* stream) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (count == 0) return SLH_OK;
+  if (!items) return fail(c, SLH_EINVAL, "null items");
+  std::vector<ExtReq> reqs(count);
+  for (uint32_t i = 0; i < count; i++) {
+    const slh_verify_item_ext& it = items[i];
+    reqs[i] = ExtReq{it.param, it.prehash, it.ctx_len, it.msg_off, it.msg_len, it.ctx_off, SLH_RND_NONE};
+  }
+  std::vector<ExtJob> jobs;
+  uint64_t total = 0;
+  int rc = plan_ext(c, reqs, msgs, msgs_bytes, &jobs, &total);
+  if (rc) return rc;
+  std::vector<slh_verify_item> inner(count);
+  for (uint32_t i = 0; i < count; i++)
+    inner[i] = slh_verify_item{items[i].param, 0, jobs[i].out_off, jobs[i].out_len, items[i].sig_off, items[i].pk_off};
+  rc = launch_encode(c, jobs, total, msgs, stream);
+  if (rc) return rc;
+  return slh_verify_batch(c, inner.data(), count, c->xbuf, total, sigs, sigs_bytes, pks, pks_bytes, results,
+                          stream);
 }
 
 int slh_verify_batch(slh_ctx* c, const slh_verify_item* items, uint32_t count, const uint8_t* msgs,

@@ -62,15 +62,81 @@ __global__ void k_key_midstates(DevKey* keys, uint32_t first, uint32_t count) {
   }
 }
 
+// Cache placement of keys first .. first+count-1: `layers` cached layers,
+// key i's trees at byte offset off0 + i * per_key.
+__global__ void k_set_cache(DevKey* keys, uint32_t first, uint32_t count, uint32_t layers, uint64_t off0,
+                            uint64_t per_key) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  keys[first + i].cache_layers = layers;
+  keys[first + i].cache_off = off0 + uint64_t(i) * per_key;
+}
+
+// ------------------------------------------------------------------ external interface
+// Message encodings of FIPS 205 Section 10: pure SLH-DSA (Algorithm 22:
+// M' = 0 | len(ctx) | ctx | M) and HashSLH-DSA (Algorithm 23: M' = 1 |
+// len(ctx) | ctx | OID | PH(M), PH = SHA-256 or SHA-512).  One workgroup per
+// request; the lanes copy bytes, lane 0 computes the pre-hash.  opt_rand (n
+// bytes) is copied next to M' when given.
+struct ExtJob {
+  uint64_t msg_off, msg_len;  // M in the caller's buffer
+  uint64_t ctx_off;           // ctx in the caller's buffer
+  uint64_t rnd_in;            // opt_rand in the caller's buffer, or kNoRnd
+  uint64_t out_off, out_len;  // M' in the encode buffer
+  uint64_t rnd_out;           // opt_rand in the encode buffer
+  uint32_t ctx_len, prehash, n, pad;
+};
+constexpr int kEncodeThreads = 256;
+
+__global__ __launch_bounds__(kEncodeThreads) void k_encode_ext(const ExtJob* __restrict__ jobs,
+                                                               const uint8_t* __restrict__ in,
+                                                               uint8_t* __restrict__ out) {
+  const ExtJob J = jobs[blockIdx.x];
+  const uint32_t t = threadIdx.x;
+  uint8_t* o = out + J.out_off;
+  if (t == 0) {
+    o[0] = J.prehash ? 1 : 0;
+    o[1] = uint8_t(J.ctx_len);
+  }
+  for (uint32_t b = t; b < J.ctx_len; b += kEncodeThreads) o[2 + b] = in[J.ctx_off + b];
+  if (J.rnd_in != kNoRnd)
+    for (uint32_t b = t; b < J.n; b += kEncodeThreads) out[J.rnd_out + b] = in[J.rnd_in + b];
+  uint8_t* body = o + 2 + J.ctx_len;
+  if (J.prehash == 0) {
+    for (uint64_t b = t; b < J.msg_len; b += kEncodeThreads) body[b] = in[J.msg_off + b];
+    return;
+  }
+  if (t != 0) return;
+  // DER encodings of id-sha256 (2.16.840.1.101.3.4.2.1) and id-sha512 (...2.3)
+  const uint8_t oid[11] = {0x06, 0x09, 0x60, 0x86, 0x48, 0x01, 0x65, 0x03, 0x04, 0x02,
+                           uint8_t(J.prehash == 1 ? 0x01 : 0x03)};
+  for (int b = 0; b < 11; b++) body[b] = oid[b];
+  uint8_t* d = body + 11;
+  if (J.prehash == 1) {
+    uint32_t st[8];
+    sha256_iv(st);
+    sha256_stream<0>(st, nullptr, in + J.msg_off, J.msg_len, 0);
+    for (int w = 0; w < 8; w++)
+      for (int b = 0; b < 4; b++) d[4 * w + b] = uint8_t(st[w] >> (24 - 8 * b));
+  } else {
+    u64p st[8];
+    sha512_iv(st);
+    sha512_stream<0>(st, nullptr, in + J.msg_off, J.msg_len, 0);
+    for (int w = 0; w < 8; w++)
+      for (int b = 0; b < 8; b++) d[8 * w + b] = uint8_t((b < 4 ? st[w].hi : st[w].lo) >> (24 - 8 * (b & 3)));
+  }
+}
+
 // ------------------------------------------------------------------ prelude
 // Per-key values the message hashes need (a DevKey, or a verifier's copy).
 struct KeyView {
   const uint32_t* sk_prf;
   const uint32_t* pk_seed;
   const uint32_t* pk_root;
+  const uint32_t* opt_rand;  // PK.seed for deterministic signing
 };
 
-// R = PRF_msg(SK.prf, opt_rand = PK.seed, M) = Trunc_n(HMAC-SHA-X(SK.prf, PK.seed | M))
+// R = PRF_msg(SK.prf, opt_rand, M) = Trunc_n(HMAC-SHA-X(SK.prf, opt_rand | M))
 template <int ID>
 __device__ void prf_msg(const KeyView& K, const uint8_t* msg, uint64_t mlen, uint32_t* R) {
   constexpr int NW = P<ID>::NW;
@@ -80,7 +146,7 @@ __device__ void prf_msg(const KeyView& K, const uint8_t* msg, uint64_t mlen, uin
 #pragma unroll
     for (int j = 0; j < 16; j++) blk[j] = (j < NW ? K.sk_prf[j] : 0u) ^ 0x36363636u;
     sha256_compress(st, blk);
-    sha256_stream<NW>(st, K.pk_seed, msg, mlen, 64);
+    sha256_stream<NW>(st, K.opt_rand, msg, mlen, 64);
     uint32_t inner[8];
 #pragma unroll
     for (int j = 0; j < 8; j++) inner[j] = st[j];
@@ -99,7 +165,7 @@ __device__ void prf_msg(const KeyView& K, const uint8_t* msg, uint64_t mlen, uin
       w[j] = u64p{(2 * j < NW ? K.sk_prf[2 * j] : 0u) ^ 0x36363636u,
                   (2 * j + 1 < NW ? K.sk_prf[2 * j + 1] : 0u) ^ 0x36363636u};
     sha512_compress(st, w);
-    sha512_stream<NW>(st, K.pk_seed, msg, mlen, 128);
+    sha512_stream<NW>(st, K.opt_rand, msg, mlen, 128);
     uint32_t inner[16];
 #pragma unroll
     for (int j = 0; j < 8; j++) { inner[2 * j] = st[j].hi; inner[2 * j + 1] = st[j].lo; }
@@ -199,7 +265,12 @@ __global__ void k_prelude(const DevKey* __restrict__ keys, const DevItem* __rest
   if (i >= count) return;
   const DevItem it = items[i];
   const DevKey& K = keys[it.key_slot];
-  const KeyView kv{K.sk_prf, K.pk_seed, K.pk_root};
+  uint32_t rnd[NW];
+  if (it.rnd_off != kNoRnd) {
+#pragma unroll
+    for (int j = 0; j < NW; j++) rnd[j] = msg_word(msgs + it.rnd_off, 4 * NW, 4 * j);
+  }
+  const KeyView kv{K.sk_prf, K.pk_seed, K.pk_root, it.rnd_off != kNoRnd ? rnd : K.pk_seed};
   const uint8_t* msg = msgs + it.msg_off;
   uint32_t R[NW], digest[16];
   prf_msg<ID>(kv, msg, it.msg_len, R);
@@ -410,72 +481,20 @@ struct TreeSplit {
   static constexpr int wave0 = ID == 1 ? 8 : (ID == 2 ? 10 : 13);
 };
 
-// Phase 1 of a block of 64 leaves (TPB trees, flat tree ids block*TPB ...):
-// the WOTS+ chains, one lane per chain, chain ends to `st` (len * 64 * NW
-// words).  KEYGEN: a single tree (layer d-1, tree 0); otherwise trees come
-// from the batch's work records.
-template <int ID, bool KEYGEN>
-__device__ __forceinline__ TreeJob tree_job(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
-                                            uint8_t* sigs, uint32_t* spill, uint32_t key_slot,
-                                            uint32_t* root_out, uint32_t ftree) {
-  if constexpr (KEYGEN) {
-    TreeJob J;
-    J.key = &keys[key_slot];
-    J.layer = P<ID>::d - 1;
-    J.tree = 0;
-    J.sign_leaf = -1;
-    J.sig_xmss = nullptr;
-    J.root_out = root_out;
-    J.spill = nullptr;
-    return J;
-  } else {
-    return sign_job<ID>(keys, recs, sigs, spill, ftree);
-  }
-}
+// What a TREE block works on: the trees of a batch's signatures, the top tree
+// of a new key, or the cached upper layers of keys.
+enum TreeKind : int { kSignTrees = 0, kKeygenTree = 1, kCacheTrees = 2 };
 
-// Trees of a batch, optionally restricted to a list of distinct trees
-// (within-batch dedup): tree slot i of the list is flat tree id ulist[i],
-// and there are *ucount of them; without a list, slot i is tree i of ntrees.
-struct TreeList {
-  const uint32_t* ulist;
-  const uint32_t* ucount;
-  __device__ __forceinline__ uint32_t count(uint32_t ntrees) const { return ucount ? *ucount : ntrees; }
-  __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : i; }
+// Cached upper layers of a key: layer d-1-u (u = 0 .. L-1) has 2^(h' u) trees,
+// stored top layer first, so its trees start at (2^(h' u) - 1) / (2^h' - 1).
+template <int ID>
+struct CacheShape {
+  __host__ __device__ static constexpr uint64_t layer_first(uint32_t u) {
+    return ((uint64_t(1) << (P<ID>::hp * u)) - 1) / ((uint64_t(1) << P<ID>::hp) - 1);
+  }
+  __host__ __device__ static constexpr uint64_t trees(uint32_t layers) { return layer_first(layers); }
 };
 
-template <int ID, bool KEYGEN>
-__device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
-                                            uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
-                                            uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
-                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr}) {
-  using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, LV = Q::leaves;
-  constexpr int TPB = kLeavesPerBlock / LV;
-  constexpr int W0 = TreeSplit<ID>::wave0;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t tree0 = block * TPB;
-  const uint32_t lt = lane / LV, kp = lane % LV;
-  if (tree0 + lt >= tl.count(ntrees)) return;
-  const TreeJob J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, tl.at(tree0 + lt));
-  uint32_t mid[8], sks[NW];
-  load_words<8>(J.key->mid256, mid);
-  load_words<NW>(J.key->sk_seed, sks);
-  const bool keepit = J.spill != nullptr && int32_t(kp) == J.sign_leaf;
-  // wave 0: chunks 0 .. W0-1; waves 1..3: chunks W0 + (wave - 1) + 3 i
-  const int c0 = wave == 0 ? 0 : W0 + wave - 1;
-  const int cend = wave == 0 ? W0 : LEN;
-  const int cstep = wave == 0 ? 1 : 3;
-  for (int c = c0; c < cend; c += cstep) {
-    uint32_t x[NW];
-    wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keepit ? J.spill + c * 16 * NW : nullptr, x);
-    store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
-  }
-}
-
-// Phases 2 and 3 of a block, run by one wave: T_len of each leaf over its
-// chain ends, then the XMSS levels inside the wave (the node of level z lives
-// in the lanes with kp % 2^z == 0, its partner is 2^(z-1) lanes up); auth
-// nodes and the root are written where they are computed.
 // Number of nodes of one XMSS tree and the offset of level z in a node
 // buffer: level z (2^(h'-z) nodes) starts at 2^(h'+1) - 2^(h'-z+1).
 template <int ID>
@@ -484,13 +503,107 @@ struct TreeNodes {
   __device__ static constexpr int off(int z) { return (2 << P<ID>::hp) - (2 << (P<ID>::hp - z)); }
 };
 
+// Phase 1 of a block of 64 leaves (TPB trees, flat tree ids block*TPB ...):
+// the WOTS+ chains, one lane per chain, chain ends to `st` (len * 64 * NW
+// words).  kKeygenTree: a single tree (layer d-1, tree 0) of key `key_slot`;
+// kCacheTrees: tree i of the cached layers of keys key_slot, key_slot + 1,
+// ... (all with the same cache_layers); kSignTrees: trees from the batch's
+// work records.
+template <int ID, int KIND>
+__device__ __forceinline__ TreeJob tree_job(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                            uint8_t* sigs, uint32_t* spill, uint32_t key_slot,
+                                            uint32_t* root_out, uint32_t ftree) {
+  if constexpr (KIND == kSignTrees) {
+    return sign_job<ID>(keys, recs, sigs, spill, ftree);
+  } else {
+    TreeJob J;
+    J.sign_leaf = -1;
+    J.sig_xmss = nullptr;
+    J.spill = nullptr;
+    if constexpr (KIND == kKeygenTree) {
+      J.key = &keys[key_slot];
+      J.layer = P<ID>::d - 1;
+      J.tree = 0;
+      J.root_out = root_out;
+    } else {
+      const uint32_t L = keys[key_slot].cache_layers;
+      const uint64_t per = CacheShape<ID>::trees(L);
+      const uint32_t k = uint32_t(ftree / per);
+      const uint64_t local = ftree - uint64_t(k) * per;
+      uint32_t u = 0;
+      while (u + 1 < L && local >= CacheShape<ID>::layer_first(u + 1)) u++;
+      J.key = &keys[key_slot + k];
+      J.layer = P<ID>::d - 1 - u;
+      J.tree = local - CacheShape<ID>::layer_first(u);
+      J.root_out = nullptr;
+    }
+    return J;
+  }
+}
+
+// Trees of a batch, optionally restricted to a list of distinct trees
+// (within-batch dedup): tree slot i of the list is flat tree id ulist[i],
+// and there are *ucount of them; without a list, slot i is tree i of ntrees.
+// With dedup, lown[ft * leaves + leaf] names the (message, layer) pair whose
+// kept-chain area receives the chains of that leaf of tree ft (~0: no pair
+// signs with that leaf).
+// Without a list, slot i is tree first + i.
+struct TreeList {
+  const uint32_t* ulist;
+  const uint32_t* ucount;
+  const uint32_t* lown;
+  uint32_t first;
+  __device__ __forceinline__ uint32_t count(uint32_t ntrees) const { return ucount ? *ucount : ntrees; }
+  __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : first + i; }
+};
+
+template <int ID, int KIND>
+__device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                            uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
+                                            uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
+                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr, nullptr, 0u}) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len, LV = Q::leaves;
+  constexpr int TPB = kLeavesPerBlock / LV;
+  constexpr int W0 = TreeSplit<ID>::wave0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t tree0 = block * TPB;
+  const uint32_t lt = lane / LV, kp = lane % LV;
+  if (tree0 + lt >= tl.count(ntrees)) return;
+  const uint32_t ft = tl.at(tree0 + lt);
+  const TreeJob J = tree_job<ID, KIND>(keys, recs, sigs, spill, key_slot, root_out, ft);
+  uint32_t mid[8], sks[NW];
+  load_words<8>(J.key->mid256, mid);
+  load_words<NW>(J.key->sk_seed, sks);
+  uint32_t* keep = nullptr;
+  if (tl.lown) {
+    const uint32_t o = tl.lown[size_t(ft) * LV + kp];
+    if (spill && o != 0xffffffffu) keep = spill + size_t(o) * LEN * 16 * NW;
+  } else if (J.spill && int32_t(kp) == J.sign_leaf) {
+    keep = J.spill;
+  }
+  // wave 0: chunks 0 .. W0-1; waves 1..3: chunks W0 + (wave - 1) + 3 i
+  const int c0 = wave == 0 ? 0 : W0 + wave - 1;
+  const int cend = wave == 0 ? W0 : LEN;
+  const int cstep = wave == 0 ? 1 : 3;
+  for (int c = c0; c < cend; c += cstep) {
+    uint32_t x[NW];
+    wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keep ? keep + c * 16 * NW : nullptr, x);
+    store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
+  }
+}
+
+// Phases 2 and 3 of a block, run by one wave: T_len of each leaf over its
+// chain ends, then the XMSS levels inside the wave (the node of level z lives
+// in the lanes with kp % 2^z == 0, its partner is 2^(z-1) lanes up); auth
+// nodes and the root are written where they are computed.
 // `nodes` (optional): every node of the tree is stored at
 // nodes[(ft * TreeNodes::count + off(z) + i) * NW] for the dedup scatter.
-template <int ID, bool KEYGEN>
+template <int ID, int KIND>
 __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, const uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
-                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr},
+                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr, nullptr, 0u},
                                             uint32_t* __restrict__ nodes = nullptr) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
@@ -504,7 +617,7 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
   uint32_t v[NW];
   TreeJob J{};
   if (valid) {
-    J = tree_job<ID, KEYGEN>(keys, recs, sigs, spill, key_slot, root_out, ft);
+    J = tree_job<ID, KIND>(keys, recs, sigs, spill, key_slot, root_out, ft);
     auto get = [&](int wi) -> uint32_t {
       const int c = wi / NW, u = wi - c * NW;
       return st[(c * kLeavesPerBlock + lane) * NW + u];
@@ -539,21 +652,21 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
   if (valid && kp == 0 && tn) store_words<NW>(tn + TreeNodes<ID>::off(HP) * NW, v);
 }
 
-template <int ID, bool KEYGEN>
+template <int ID, int KIND>
 __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict__ keys,
                                                        WorkRec* __restrict__ recs, uint32_t ntrees,
                                                        uint8_t* sigs, uint32_t* __restrict__ stage,
                                                        uint32_t* __restrict__ spill,
                                                        uint32_t key_slot, uint32_t* root_out,
                                                        const uint32_t* ulist, const uint32_t* ucount,
-                                                       uint32_t* nodes) {
-  const TreeList tl{ulist, ucount};
+                                                       const uint32_t* lown, uint32_t* nodes, uint32_t first) {
+  const TreeList tl{ulist, ucount, lown, first};
   if (blockIdx.x * (kLeavesPerBlock / P<ID>::leaves) >= tl.count(ntrees)) return;  // beyond the distinct trees
   uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
-  tree_chains<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl);
+  tree_chains<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl);
   __syncthreads();
   if ((threadIdx.x >> 6) == 0)
-    tree_finish<ID, KEYGEN>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
+    tree_finish<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
 }
 
 // ------------------------------------------------------------------ fused
@@ -572,21 +685,22 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
 // for 128f (at most 128 VGPRs, like the plain TREE kernel), three otherwise.
 template <int ID>
 struct FusedOcc {
-  static constexpr int waves = ID == 1 ? 4 : 3;
+  static constexpr int waves = 3;
 };
 
 template <int ID, int FG>
 __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg, uint8_t* sigs,
     uint32_t* __restrict__ stage, uint32_t* __restrict__ spill, uint32_t* __restrict__ roots, uint32_t* queue,
-    uint32_t ntb, uint32_t nfg, const uint32_t* ulist, const uint32_t* ucount, uint32_t* nodes) {
+    uint32_t ntb, uint32_t nfg, const uint32_t* ulist, const uint32_t* ucount, const uint32_t* lown,
+    uint32_t* nodes) {
   static_assert(kTreeThreads == kForsThreads, "one workgroup shape for both item kinds");
   using Q = P<ID>;
   constexpr size_t SW = size_t(Q::len) * kLeavesPerBlock * Q::NW;  // words of one staging buffer
   __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * Q::NW];
   __shared__ uint32_t item;
   uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * SW;
-  const TreeList tl{ulist, ucount};
+  const TreeList tl{ulist, ucount, lown, 0u};
   const uint32_t ntrees = nmsg * Q::d;
   constexpr uint32_t TPB = kLeavesPerBlock / Q::leaves;
   if (ucount) ntb = (*ucount + TPB - 1) / TPB;  // TREE blocks over the distinct trees only
@@ -602,19 +716,19 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     if (it >= total) break;
     if (pend != 0xffffffffu) {
       // finish the previous TREE block while the other waves start this item
-      if (w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u, nullptr, pend, tl,
+      if (w0) tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u, nullptr, pend, tl,
                                      nodes);
       pend = 0xffffffffu;
     }
     if (it < ntb) {
-      tree_chains<ID, false>(keys, recs, ntrees, sigs, st0 + cur * SW, spill, 0u, nullptr, it, tl);
+      tree_chains<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + cur * SW, spill, 0u, nullptr, it, tl);
       pend = it;
       cur ^= 1;
     } else {
       fors_group<ID, FG>(keys, recs, nmsg * Q::k, sigs, roots, it - ntb, node);
     }
   }
-  if (pend != 0xffffffffu && w0) tree_finish<ID, false>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u,
+  if (pend != 0xffffffffu && w0) tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u,
                                                         nullptr, pend, tl, nodes);
 }
 
@@ -706,12 +820,13 @@ struct DedupSlot {
 };
 constexpr unsigned long long kDedupEmpty = ~0ull;
 
-__global__ void k_dedup_init(DedupSlot* table, uint32_t size, uint32_t* ucount) {
+__global__ void k_dedup_init(DedupSlot* table, uint32_t size, uint32_t* lown, uint32_t nlown, uint32_t* ucount) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < size) {
     table[i].key = kDedupEmpty;
     table[i].owner = 0xffffffffu;
   }
+  if (i < nlown) lown[i] = 0xffffffffu;
   if (i == 0) *ucount = 0;
 }
 
@@ -724,15 +839,23 @@ __device__ __forceinline__ uint32_t dedup_hash(unsigned long long k) {
   return uint32_t(k);
 }
 
-// rep[ft] <- table slot of its triple, or 0xffffffff when not eligible.
+// Marks a (message, layer) pair whose tree sits in its key's tree cache.
+constexpr uint32_t kCachedTree = 0xfffffffeu;
+
+// rep[ft] <- table slot of its triple, 0xffffffff when not eligible, or
+// kCachedTree when the key caches the layer.
 template <int ID>
-__global__ void k_dedup_insert(const WorkRec* __restrict__ recs, uint32_t nmsg, DedupSlot* table, uint32_t size,
-                               uint32_t* rep) {
+__global__ void k_dedup_insert(const DevKey* __restrict__ keys, const WorkRec* __restrict__ recs, uint32_t nmsg,
+                               DedupSlot* table, uint32_t size, uint32_t* rep) {
   using Q = P<ID>;
   const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
   if (ft >= nmsg * Q::d) return;
   const uint32_t msg = ft / Q::d, layer = ft - msg * Q::d;
   const WorkRec& W = recs[msg];
+  if (layer + keys[W.key_slot].cache_layers >= uint32_t(Q::d)) {
+    rep[ft] = kCachedTree;
+    return;
+  }
   const int bits = Q::tree_bits - int(Q::hp * layer);  // bits of this layer's tree address
   if (bits > 35 || W.key_slot >= (1u << 24)) {
     rep[ft] = 0xffffffffu;
@@ -755,16 +878,25 @@ __global__ void k_dedup_insert(const WorkRec* __restrict__ recs, uint32_t nmsg, 
 }
 
 // rep[ft] <- representative flat tree id; representatives are appended to
-// ulist (order irrelevant: every output position is fixed by the tree id).
+// ulist (order irrelevant: every output position is fixed by the tree id);
+// the smallest pair signing with each leaf of a representative becomes that
+// leaf's owner in lown.
 template <int ID>
-__global__ void k_dedup_resolve(uint32_t nmsg, const DedupSlot* table, uint32_t* rep, uint32_t* ulist,
-                                uint32_t* ucount) {
+__global__ void k_dedup_resolve(const WorkRec* __restrict__ recs, uint32_t nmsg, const DedupSlot* table,
+                                uint32_t* rep, uint32_t* ulist, uint32_t* ucount, uint32_t* lown) {
+  using Q = P<ID>;
   const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ft >= nmsg * P<ID>::d) return;
+  if (ft >= nmsg * Q::d) return;
   const uint32_t h = rep[ft];
+  if (h == kCachedTree) return;
   const uint32_t r = h == 0xffffffffu ? ft : table[h].owner;
   rep[ft] = r;
   if (r == ft) ulist[atomicAdd(ucount, 1u)] = ft;
+  const uint32_t msg = ft / Q::d, layer = ft - msg * Q::d;
+  const WorkRec& W = recs[msg];
+  const uint32_t leaf = layer == 0 ? W.idx_leaf
+                                   : uint32_t((W.idx_tree >> (Q::hp * (layer - 1))) & ((1u << Q::hp) - 1));
+  atomicMin(&lown[size_t(r) * Q::leaves + leaf], ft);
 }
 
 // Running totals of eligible-or-not trees and distinct trees computed (one
@@ -778,9 +910,11 @@ __global__ void k_dedup_stats(uint32_t trees, const uint32_t* ucount, unsigned l
 
 // Auth path and root of every non-representative (message, layer) from the
 // representative's node buffer; one lane per pair.
+// Cached pairs read the key's tree cache instead.
 template <int ID>
 __global__ void k_dedup_scatter(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg,
-                                uint8_t* sigs, const uint32_t* __restrict__ rep, const uint32_t* __restrict__ nodes) {
+                                uint8_t* sigs, const uint32_t* __restrict__ rep, const uint32_t* __restrict__ nodes,
+                                const uint8_t* __restrict__ cache) {
   using Q = P<ID>;
   constexpr int NW = Q::NW;
   const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
@@ -789,7 +923,13 @@ __global__ void k_dedup_scatter(const DevKey* __restrict__ keys, WorkRec* __rest
   if (r == ft) return;
   const TreeJob J = sign_job<ID>(keys, recs, sigs, nullptr, ft);
   const uint32_t leaf = uint32_t(J.sign_leaf);
-  const uint32_t* tn = nodes + size_t(r) * TreeNodes<ID>::count * NW;
+  const uint32_t* tn;
+  if (r == kCachedTree) {
+    const uint64_t t = CacheShape<ID>::layer_first(Q::d - 1 - J.layer) + J.tree;
+    tn = reinterpret_cast<const uint32_t*>(cache + J.key->cache_off) + t * TreeNodes<ID>::count * NW;
+  } else {
+    tn = nodes + size_t(r) * TreeNodes<ID>::count * NW;
+  }
   uint8_t* xs = J.sig_xmss + Q::len * Q::n;
   for (int z = 0; z < Q::hp; z++) {
     uint32_t v[NW];
@@ -803,13 +943,13 @@ __global__ void k_dedup_scatter(const DevKey* __restrict__ keys, WorkRec* __rest
   }
 }
 
-// WOTS+ signatures with dedup.  The kept chain values of a tree's
-// representative serve every pair whose signing leaf is the representative's
-// (same key, tree and leaf: same chains, whatever the digits); the other
-// pairs recompute their chains.
+// WOTS+ signatures with dedup: the chains of every leaf some pair signs with
+// were kept (in the area of that leaf's owner), so every computed pair
+// gathers; pairs of cached layers recompute their chains.
 template <int ID>
 __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t count,
-                             uint8_t* sigs, const uint32_t* __restrict__ spill, const uint32_t* __restrict__ rep) {
+                             uint8_t* sigs, const uint32_t* __restrict__ spill, const uint32_t* __restrict__ rep,
+                             const uint32_t* __restrict__ lown) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len;
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -819,10 +959,12 @@ __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restric
   const uint32_t digit = wots_digit<ID>(recs[ftree / Q::d], J.layer, c);
   const uint32_t r = rep[ftree];
   uint32_t x[NW];
-  if (r == ftree || sign_job<ID>(keys, recs, sigs, nullptr, r).sign_leaf == J.sign_leaf)
-    load_words<NW>(spill + ((size_t(r) * LEN + c) * 16 + digit) * NW, x);
-  else
+  if (r == kCachedTree) {
     wots_value<ID>(J, c, digit, x);
+  } else {
+    const uint32_t o = lown[size_t(r) * Q::leaves + uint32_t(J.sign_leaf)];
+    load_words<NW>(spill + ((size_t(o) * LEN + c) * 16 + digit) * NW, x);
+  }
   store_be<NW>(J.sig_xmss + c * Q::n, x);
 }
 
@@ -885,7 +1027,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     for (int j = 0; j < 8; j++) { mid512[2 * j] = s5[j].hi; mid512[2 * j + 1] = s5[j].lo; }
     uint32_t R[NW], digest[16];
     load_be<NW>(sig, R);
-    const KeyView kv{nullptr, pk_seed, pk_root};
+    const KeyView kv{nullptr, pk_seed, pk_root, nullptr};
     h_msg<ID>(kv, R, msg, it.msg_len, digest);
     uint64_t tree;
     uint32_t leaf;

@@ -357,10 +357,15 @@ int slh_serve_add_keys(slh_server* s, uint32_t param, const uint8_t* sks, uint32
   uint32_t first = 0;
   for (size_t i = 0; i < s->lanes.size(); i++) {
     uint32_t f = 0;
-    const int rc = slh_ctx_add_keys(s->lanes[i].ctx, param, sks, count, &f);
+    int rc = slh_ctx_add_keys(s->lanes[i].ctx, param, sks, count, &f);
     if (rc) return lane_error(s, s->lanes[i], rc);
     if (i == 0) first = f;
     else if (f != first) return sfail(s, SLH_EDEVICE, "lane key tables diverged");
+    if (s->cfg.cache_layers) {
+      const uint32_t lim = param == SLH_SHA2_256F ? 4u : 6u;
+      rc = slh_ctx_cache_keys(s->lanes[i].ctx, f, count, std::min(s->cfg.cache_layers, lim));
+      if (rc) return lane_error(s, s->lanes[i], rc);
+    }
   }
   *first_slot = first;
   return SLH_OK;

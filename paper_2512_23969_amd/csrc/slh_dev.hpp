@@ -65,26 +65,32 @@ enum : uint32_t { A_WOTS_HASH = 0, A_WOTS_PK = 1, A_TREE = 2, A_FORS_TREE = 3, A
 // ---------------------------------------------------------------- tables in HBM
 // Per-key record in the device key table (256 bytes).  All values are BE words.
 struct DevKey {
-  uint32_t param, n, pad0, pad1;
+  uint32_t param, n;
+  uint32_t cache_layers;  // top hypertree layers whose tree nodes are cached (0: none)
+  uint32_t pad1;
   uint32_t sk_seed[8];
   uint32_t sk_prf[8];
   uint32_t pk_seed[8];
   uint32_t pk_root[8];
   uint32_t mid256[8];   // SHA-256 chaining value after PK.seed || 0^(64-n)
   uint32_t mid512[16];  // SHA-512 chaining value after PK.seed || 0^(128-n), (hi, lo) pairs
-  uint32_t pad2[4];
+  uint64_t cache_off;   // byte offset of this key's trees in the context's tree cache
+  uint32_t pad2[2];
 };
 static_assert(sizeof(DevKey) == 256, "DevKey layout");
 
-// One sign request as handed to the library (mirrors slh_item of slh.h).
+// One sign request as handed to the library (slh_item of slh.h plus the
+// location of opt_rand for hedged signing).
 struct DevItem {
   uint32_t param;
   uint32_t key_slot;
   uint64_t msg_off;
   uint64_t msg_len;
   uint64_t sig_off;
+  uint64_t rnd_off;  // n bytes of opt_rand in the message buffer, or kNoRnd (opt_rand = PK.seed)
 };
-static_assert(sizeof(DevItem) == 32, "DevItem layout");
+static_assert(sizeof(DevItem) == 40, "DevItem layout");
+constexpr uint64_t kNoRnd = ~uint64_t(0);
 
 // Per-message state shared by the kernels of one batch (1 KiB).
 struct WorkRec {

@@ -46,7 +46,8 @@ class slh_tuning(ctypes.Structure):
 class slh_serve_config(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("min_batch", ctypes.c_uint32),
                 ("max_wait_us", ctypes.c_uint32), ("msg_bytes", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
-                ("mode", ctypes.c_uint32), ("queue_limit", ctypes.c_uint32)]
+                ("mode", ctypes.c_uint32), ("queue_limit", ctypes.c_uint32), ("cache_layers", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class slh_serve_stats(ctypes.Structure):
@@ -55,9 +56,21 @@ class slh_serve_stats(ctypes.Structure):
                 ("mean_s", ctypes.c_double), ("max_s", ctypes.c_double), ("mean_batch", ctypes.c_double)]
 
 
+# slh_item_ext: the external interface (pure / pre-hash, context string, hedged)
+ITEM_EXT_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
+                           ("sig_off", "<u8"), ("ctx_off", "<u8"), ("rnd_off", "<u8"), ("ctx_len", "<u4"),
+                           ("prehash", "<u4")])
+assert ITEM_EXT_DTYPE.itemsize == 56
+RND_NONE = 0xFFFFFFFFFFFFFFFF
+PREHASH_NONE, PREHASH_SHA256, PREHASH_SHA512 = 0, 1, 2
+
 VERIFY_DTYPE = np.dtype([("param", "<u4"), ("pad", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
                          ("sig_off", "<u8"), ("pk_off", "<u8")])
 assert VERIFY_DTYPE.itemsize == 40
+VERIFY_EXT_DTYPE = np.dtype([("param", "<u4"), ("prehash", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
+                             ("sig_off", "<u8"), ("pk_off", "<u8"), ("ctx_off", "<u8"), ("ctx_len", "<u4"),
+                             ("pad", "<u4")])
+assert VERIFY_EXT_DTYPE.itemsize == 56
 
 REQ_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
                       ("sig_off", "<u8"), ("arrival_s", "<f8")])
@@ -96,6 +109,9 @@ def _load():
                                       ctypes.POINTER(u64), ctypes.c_int]
     L.slh_verify_batch.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, u64, vp, vp]
     L.slh_ctx_dedup_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.c_int]
+    L.slh_ctx_cache_keys.argtypes = [vp, u32, u32, u32]
+    L.slh_sign_batch_ext.argtypes = [vp, vp, u32, vp, u64, vp, u64, u32, vp]
+    L.slh_verify_batch_ext.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, u64, vp, vp]
     L.slh_serve_create.argtypes = [ctypes.c_int, ctypes.POINTER(slh_serve_config), ctypes.POINTER(vp)]
     L.slh_serve_destroy.argtypes = [vp]
     L.slh_serve_last_error.argtypes = [vp]
@@ -186,6 +202,11 @@ class Context:
         self.key_params += [param] * (len(blob) // skb)
         return first.value
 
+    def cache_keys(self, first_slot: int, count: int, layers: int):
+        """Cache the top `layers` hypertree layers of keys first_slot .. first_slot + count - 1
+        (used by the dedup modes)."""
+        _check(lib.slh_ctx_cache_keys(self.h, int(first_slot), int(count), int(layers)), self.h)
+
     def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0,
                    keep_chains: int = 1):
         t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains)
@@ -238,6 +259,25 @@ class Context:
                self.h)
 
 
+    def verify_batch_ext(self, items: np.ndarray, msgs, sigs, pks, results, stream=None):
+        """Enqueue verification through the external interface (VERIFY_EXT_DTYPE items)."""
+        items = np.ascontiguousarray(items, dtype=VERIFY_EXT_DTYPE)
+        mp, mb = _ptr(msgs)
+        sp, sb = _ptr(sigs)
+        pp, pb = _ptr(pks)
+        rp, _ = _ptr(results)
+        _check(lib.slh_verify_batch_ext(self.h, items.ctypes.data, len(items), mp, mb, sp, sb, pp, pb, rp,
+                                        _stream_handle(stream)), self.h)
+
+    def sign_batch_ext(self, items: np.ndarray, msgs, sigs, mode: int = MODE_PLAIN, stream=None):
+        """Enqueue signing through the external interface (ITEM_EXT_DTYPE items)."""
+        items = np.ascontiguousarray(items, dtype=ITEM_EXT_DTYPE)
+        mp, mb = _ptr(msgs)
+        sp, sb = _ptr(sigs)
+        _check(lib.slh_sign_batch_ext(self.h, items.ctypes.data, len(items), mp, mb, sp, sb, int(mode),
+                                      _stream_handle(stream)), self.h)
+
+
 def _ptr(t):
     if isinstance(t, tuple):
         return ctypes.c_void_p(int(t[0])), int(t[1])
@@ -265,6 +305,38 @@ def pack_batch(params, slots, messages, align: int = 16):
     return items, b"".join(messages), soff
 
 
+def sign_messages_ext(ctx: Context, params, slots, messages, contexts=None, prehash=None, rnds=None,
+                      mode: int = MODE_PLAIN):
+    """Sign through the external interface; contexts / prehash / rnds are
+    per-message lists (None: empty context, pure, deterministic)."""
+    import torch
+    n = len(messages)
+    contexts = contexts or [b""] * n
+    prehash = prehash or [PREHASH_NONE] * n
+    rnds = rnds or [None] * n
+    items = np.zeros(n, dtype=ITEM_EXT_DTYPE)
+    blob = bytearray()
+    soff = 0
+    for i in range(n):
+        mo = len(blob)
+        blob += messages[i]
+        co = len(blob)
+        blob += contexts[i]
+        ro = RND_NONE
+        if rnds[i] is not None:
+            ro = len(blob)
+            blob += rnds[i]
+        items[i] = (params[i], slots[i], mo, len(messages[i]), soff, co, ro, len(contexts[i]), prehash[i])
+        soff += (sizes(params[i])["sig_bytes"] + 15) // 16 * 16
+    dev = torch.device("cuda", ctx.device)
+    msgs = torch.frombuffer(bytearray(blob or b"\0"), dtype=torch.uint8).to(dev)
+    sigs = torch.zeros(max(soff, 16), dtype=torch.uint8, device=dev)
+    ctx.sign_batch_ext(items, (msgs.data_ptr(), len(blob)), sigs, mode)
+    torch.cuda.synchronize(dev)
+    host = sigs.cpu().numpy().tobytes()
+    return [host[int(it["sig_off"]):int(it["sig_off"]) + sizes(int(it["param"]))["sig_bytes"]] for it in items]
+
+
 def sign_messages(ctx: Context, params, slots, messages, mode: int = MODE_PLAIN):
     """Sign a list of messages synchronously; returns a list of signatures (bytes)."""
     import torch
@@ -284,9 +356,9 @@ class Server:
 
     def __init__(self, device: int = 0, lanes: int = 0, max_batch: int = 0, min_batch: int = 0,
                  max_wait_us: int = 0, msg_bytes: int = 0, hbm_budget: int = 0, mode: int = MODE_PLAIN,
-                 queue_limit: int = 0):
+                 queue_limit: int = 0, cache_layers: int = 0):
         cfg = slh_serve_config(lanes, max_batch, min_batch, max_wait_us, msg_bytes, hbm_budget, mode,
-                               queue_limit)
+                               queue_limit, cache_layers, 0)
         h = ctypes.c_void_p()
         rc = lib.slh_serve_create(int(device), ctypes.byref(cfg), ctypes.byref(h))
         if rc < 0:
