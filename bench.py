@@ -251,12 +251,44 @@ def roofline(param, res):
             "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4)}
 
 
+def phase_rooflines(param, res, msg_bytes=32):
+    """Each timed phase against its bound: the hashing phases against the
+    VALU issue rate (units x per-unit instructions), the WOTS+ gather against
+    HBM bandwidth (bytes it must move).  The prelude runs one lane per
+    message (latency-bound at batch 4096); its fraction shows that."""
+    from paper_2512_23969_amd import accounting as acc
+    c = acc.per_signature(param)
+    peak_ops = acc.VALU_PEAK_OPS
+    out = {}
+    scale = {"tree": res["dedup"][1] / res["dedup"][0] if res.get("dedup") else 1.0}
+    for ph, (ms, launches, msgs) in res["phases"].items():
+        if not launches or ms <= 0:
+            continue
+        s = ms / 1e3
+        if ph in ("fors", "tree", "fused"):
+            parts = ("fors", "tree") if ph == "fused" else (ph,)
+            ops = sum(acc.ops_per_signature(param, p) * scale.get(p, 1.0) for p in parts) * msgs
+            out[ph] = {"bound": "alu", "achieved": round(ops / s / 1e12, 3), "unit": "TOP/s",
+                       "frac": round(ops / s / peak_ops, 4)}
+        elif ph == "prelude":
+            c256, c512 = acc.prelude_compressions(param, msg_bytes)
+            ops = (c256 * acc.TEXTBOOK_SHA256 + c512 * acc.TEXTBOOK_SHA512) * msgs
+            out[ph] = {"bound": "alu (one lane per message)", "achieved": round(ops / s / 1e12, 4),
+                       "unit": "TOP/s", "frac": round(ops / s / peak_ops, 5)}
+        elif ph == "wots":
+            b = acc.wots_gather_bytes(param) * msgs
+            out[ph] = {"bound": "hbm", "achieved": round(b / s / 1e9, 1), "unit": "GB/s",
+                       "frac": round(b / s / 8e12, 4)}
+    return out
+
+
 def summary(acc, r, mode):
     prm = r["cfg"]["param"]
     out = {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3), "mode": mode,
            "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
            "roofline": roofline(prm, r) if "graph" not in mode else None,
-           "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]}}
+           "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]},
+           "phase_roofline": phase_rooflines(prm, r)}
     if r["dedup"]:
         trees, distinct = r["dedup"]
         out["dedup"] = {"trees_per_step": trees, "distinct_trees_per_step": distinct,
@@ -332,6 +364,7 @@ def main():
         "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param) / acc.VALU_PEAK_OPS, 4),
         "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items() if v[1]},
         "roofline": roofline(param, res),
+        "phase_roofline": phase_rooflines(param, res),
         "verify": res["verify"],
     }
     if res["dedup"]:

@@ -95,6 +95,33 @@ def per_signature(param: int) -> dict:
     return {"sha256": c256, "sha512": c512}
 
 
+def prelude_compressions(param: int, mlen: int) -> tuple[int, int]:
+    """(SHA-256, SHA-512) compressions of the prelude of one message of mlen
+    bytes: R = PRF_msg = HMAC(SK.prf, opt_rand | M) (the inner hash over
+    the key block, opt_rand and M; the outer over the key block and the
+    inner digest) and H_msg = MGF1(R | PK.seed | Hash(R | PK.seed | PK.root
+    | M), m)."""
+    p = PARAMS[param]
+    m = {1: 34, 2: 42, 3: 49}[param]
+    if not p.wide:
+        blk = lambda b: (b + 9 + 63) // 64  # noqa: E731
+        prf = blk(64 + p.n + mlen) + blk(64 + 32)
+        hm = blk(3 * p.n + mlen) + -(-m // 32) * blk(2 * p.n + 32 + 4)
+        return prf + hm, 0
+    blk = lambda b: (b + 17 + 127) // 128  # noqa: E731
+    prf = blk(128 + p.n + mlen) + blk(128 + 64)
+    hm = blk(3 * p.n + mlen) + -(-m // 64) * blk(2 * p.n + 64 + 4)
+    return 0, prf + hm
+
+
+def wots_gather_bytes(param: int) -> int:
+    """HBM bytes of the WOTS+ phase per signature when the chain values are
+    kept: one n-byte value read and one written per chain of every layer,
+    plus the k FORS roots read and the FORS pk written."""
+    p = PARAMS[param]
+    return 2 * p.d * p.len * p.n + (p.k + 1) * p.n
+
+
 def ops_per_signature(param: int, phase: str | None = None, textbook: bool = False) -> int:
     """VALU lane-operations per signature (ISA counts, or the textbook counts)."""
     c = per_signature(param)

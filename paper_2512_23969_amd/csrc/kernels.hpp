@@ -474,11 +474,12 @@ __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t
 
 // Chain chunks of wave 0 in a TREE block.  Wave 0 also runs T_len and the
 // XMSS levels of the block (10 + 3 SHA-256, 13 and 22 SHA-512 compressions,
-// about 13, 48 and 81 chain-step equivalents), so it takes fewer of the len
-// chunks of 16 compressions, and the other three waves share the rest.
+// about 13, 37 and 62 chain-step equivalents at 2.8 SHA-256 per SHA-512), so
+// it takes fewer of the len chunks of 16 compressions: w0 + extra / 16 =
+// (len - w0) / 3 gives 8, 11 and 14.
 template <int ID>
 struct TreeSplit {
-  static constexpr int wave0 = ID == 1 ? 8 : (ID == 2 ? 10 : 13);
+  static constexpr int wave0 = ID == 1 ? 8 : (ID == 2 ? 11 : 14);
 };
 
 // What a TREE block works on: the trees of a batch's signatures, the top tree

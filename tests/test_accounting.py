@@ -43,3 +43,17 @@ def test_isa_costs_below_textbook():
     assert acc.OPS_SHA256 < acc.TEXTBOOK_SHA256 == 1384
     assert acc.OPS_SHA512 > acc.TEXTBOOK_SHA512 * 0 and acc.TEXTBOOK_SHA512 == 4144
     assert abs(acc.VALU_PEAK_OPS - 39.3216e12) < 1e9
+
+
+@pytest.mark.parametrize("param", [1, 2, 3])
+@pytest.mark.parametrize("mlen", [0, 32, 55, 56, 200, 1000])
+def test_prelude_compressions_match_oracle(param, mlen):
+    """PRF_msg + H_msg block counts (the prelude's roofline units) equal the
+    oracle's SHA-2 block counters."""
+    p = oracle.params(NAMES[param])
+    n = p.n
+    oracle.counters_reset()
+    r = oracle.prf_msg(p, bytes(n), bytes(n), bytes(mlen))
+    oracle.h_msg(p, r, bytes(n), bytes(n), bytes(mlen))
+    c = oracle.counters()
+    assert (c["sha256_blocks"], c["sha512_blocks"]) == acc.prelude_compressions(param, mlen)
