@@ -120,8 +120,9 @@ typedef struct slh_ctx slh_ctx;
 int slh_params(uint32_t param, slh_sizes *out);
 
 /* Create a signing context on GPU `device`.  `hbm_budget` caps the bytes of
- * working memory the context keeps on the device (0 = default of 8 GiB);
- * larger batches are processed in chunks that fit.
+ * working memory the context keeps on the device (0 = default of 8 GiB),
+ * split evenly over the parameter sets it holds keys of; larger batches are
+ * processed in chunks that fit.
  * Errors: SLH_EINVAL (null out, bad device), SLH_EDEVICE. */
 int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx **out);
 
@@ -148,6 +149,15 @@ int slh_keygen(uint32_t param, const uint8_t *seed, uint8_t *pk, uint8_t *sk);
  * Errors: SLH_EINVAL, SLH_ENOMEM, SLH_EDEVICE. */
 int slh_ctx_add_keys(slh_ctx *ctx, uint32_t param, const uint8_t *sks, uint32_t count,
                      uint32_t *first_slot);
+
+/* Allocate, now, the working memory and pinned staging that slh_sign_batch
+ * needs for batches of up to `count` requests in `mode`, for every parameter
+ * set the context holds keys of, so that such calls allocate nothing later
+ * (an allocation or free in the middle of serving would wait for the whole
+ * GPU).  Working memory is capped by the context's budget, split evenly over
+ * those parameter sets.  Synchronous.  Errors: SLH_EINVAL, SLH_ENOMEM,
+ * SLH_EDEVICE. */
+int slh_ctx_reserve(slh_ctx *ctx, uint32_t count, uint32_t mode);
 
 /* Keep on the device every node of the XMSS trees of the top `layers`
  * hypertree layers of keys first_slot .. first_slot + count - 1 (one

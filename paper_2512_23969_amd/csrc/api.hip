@@ -282,6 +282,15 @@ int ensure_ws(slh_ctx* c, int p, size_t bytes) {
   return SLH_OK;
 }
 
+// Working-memory share of one parameter set: the budget split evenly over
+// the sets the context holds keys of.
+uint64_t budget_share(const slh_ctx* c) {
+  int sets = 0;
+  for (int p = 1; p <= 3; p++)
+    sets += std::find(c->key_param.begin(), c->key_param.end(), uint32_t(p)) != c->key_param.end() ? 1 : 0;
+  return c->budget / uint64_t(sets ? sets : 1);
+}
+
 template <int ID, int FG>
 void launch_fors(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* roots, hipStream_t s) {
   hipLaunchKernelGGL((k_fors<ID, FG>), dim3(pl.nfg), dim3(kForsThreads), 0, s, c->keys, recs,
@@ -698,6 +707,35 @@ int slh_ctx_dedup_stats(slh_ctx* c, uint64_t* trees, uint64_t* distinct, int res
   return SLH_OK;
 }
 
+int slh_ctx_reserve(slh_ctx* c, uint32_t count, uint32_t mode) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH | SLH_MODE_DEDUP)) return fail(c, SLH_EINVAL, "unknown mode");
+  if (count == 0) return SLH_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  if (c->staging_cap < count) {
+    drop_graphs(c);
+    if (c->staging) HIPCHK(c, hipHostFree(c->staging));
+    c->staging = nullptr;
+    c->staging_cap = 0;
+    if (hipHostMalloc(&c->staging, size_t(count) * sizeof(DevItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, SLH_ENOMEM, "pinned staging allocation failed");
+    }
+    c->staging_cap = count;
+  }
+  const uint64_t share = budget_share(c);
+  size_t chunk = 0;
+  int rc = SLH_OK;
+  for (int p = 1; p <= 3 && !rc; p++) {
+    if (std::find(c->key_param.begin(), c->key_param.end(), uint32_t(p)) == c->key_param.end()) continue;
+    if (p == 1) rc = prepare_group<1>(c, count, mode, share, &chunk);
+    if (p == 2) rc = prepare_group<2>(c, count, mode, share, &chunk);
+    if (p == 3) rc = prepare_group<3>(c, count, mode, share, &chunk);
+  }
+  return rc;
+}
+
 int slh_ctx_cache_keys(slh_ctx* c, uint32_t first_slot, uint32_t count, uint32_t layers) {
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (count == 0 || uint64_t(first_slot) + count > c->nkeys) return fail(c, SLH_EINVAL, "key range outside the table");
@@ -814,10 +852,9 @@ int sign_impl(slh_ctx* c, const slh_item* items, const uint64_t* rnd, uint32_t c
     d.sig_off = it.sig_off;
     d.rnd_off = rnd ? rnd[i] : kNoRnd;
   }
-  // working memory: the budget is shared by the parameter sets present
-  int groups = 0;
-  for (int p = 1; p <= 3; p++) groups += per[p] ? 1 : 0;
-  const uint64_t share = c->budget / uint64_t(groups);
+  // working memory: the budget is shared by the parameter sets the context
+  // holds keys of, so that each set's share does not depend on the mix
+  const uint64_t share = budget_share(c);
   size_t chunk[4] = {0, 0, 0, 0};
   int rc = SLH_OK;
   if (per[1] && !rc) rc = prepare_group<1>(c, per[1], mode, share, &chunk[1]);

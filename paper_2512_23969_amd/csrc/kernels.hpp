@@ -256,7 +256,7 @@ __device__ void split_digest(const uint32_t digest[16], uint16_t* indices, uint6
 // digest and its split into the message's work record.  The message is read
 // as bytes, so any length and alignment is accepted.
 template <int ID>
-__global__ void k_prelude(const DevKey* __restrict__ keys, const DevItem* __restrict__ items,
+__global__ __launch_bounds__(64) void k_prelude(const DevKey* __restrict__ keys, const DevItem* __restrict__ items,
                           uint32_t count, const uint8_t* __restrict__ msgs, uint8_t* sigs,
                           WorkRec* __restrict__ recs, uint32_t* queue) {
   constexpr int NW = P<ID>::NW;

@@ -366,6 +366,9 @@ int slh_serve_add_keys(slh_server* s, uint32_t param, const uint8_t* sks, uint32
       rc = slh_ctx_cache_keys(s->lanes[i].ctx, f, count, std::min(s->cfg.cache_layers, lim));
       if (rc) return lane_error(s, s->lanes[i], rc);
     }
+    // full-size working memory now, so that serving never allocates
+    rc = slh_ctx_reserve(s->lanes[i].ctx, s->cfg.max_batch, s->cfg.mode);
+    if (rc) return lane_error(s, s->lanes[i], rc);
   }
   *first_slot = first;
   return SLH_OK;

@@ -110,6 +110,7 @@ def _load():
     L.slh_verify_batch.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, u64, vp, vp]
     L.slh_ctx_dedup_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.c_int]
     L.slh_ctx_cache_keys.argtypes = [vp, u32, u32, u32]
+    L.slh_ctx_reserve.argtypes = [vp, u32, u32]
     L.slh_sign_batch_ext.argtypes = [vp, vp, u32, vp, u64, vp, u64, u32, vp]
     L.slh_verify_batch_ext.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, u64, vp, vp]
     L.slh_serve_create.argtypes = [ctypes.c_int, ctypes.POINTER(slh_serve_config), ctypes.POINTER(vp)]
@@ -201,6 +202,10 @@ class Context:
                self.h)
         self.key_params += [param] * (len(blob) // skb)
         return first.value
+
+    def reserve(self, count: int, mode: int = MODE_PLAIN):
+        """Allocate the working memory for batches of up to `count` requests now."""
+        _check(lib.slh_ctx_reserve(self.h, int(count), int(mode)), self.h)
 
     def cache_keys(self, first_slot: int, count: int, layers: int):
         """Cache the top `layers` hypertree layers of keys first_slot .. first_slot + count - 1

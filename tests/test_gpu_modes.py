@@ -103,3 +103,23 @@ def test_tuning_rejects_uncompiled_variants(slh):
             ctx.set_tuning(3, 16, 0, 1)
         with pytest.raises(slh.SlhError):
             ctx.set_tuning(2, 8, 0, 2)
+
+
+def test_reserve_then_sign(slh, keys):
+    """Working memory reserved up front for the largest batch; smaller and
+    mixed batches afterwards still match the oracle."""
+    with slh.Context(0, hbm_budget=1 << 30) as ctx:
+        slots = {p: ctx.add_keys(p, keys[p][1]) for p in (1, 2, 3)}
+        mode = slh.MODES["fused-dedup"]
+        ctx.reserve(24, mode)
+        rng = np.random.default_rng(77)
+        for count in (1, 9, 24):
+            params = [(1, 2, 3)[i % 3] for i in range(count)]
+            msgs = [rng.bytes(int(rng.integers(0, 90))) for _ in range(count)]
+            print("reserve", count, flush=True)
+            got = slh.sign_messages(ctx, params, [slots[p] for p in params], msgs, mode)
+            want = oracle_sign_many([(p, keys[p][1], m) for p, m in zip(params, msgs)])
+            for i, p in enumerate(params):
+                assert got[i] == want[i], "count %d item %d: %s" % (count, i, describe_diff(p, got[i], want[i]))
+        with pytest.raises(slh.SlhError):
+            ctx.reserve(8, 64)
