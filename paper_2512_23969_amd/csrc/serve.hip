@@ -131,7 +131,7 @@ int launch(slh_server* s, Lane& L) {
     std::memcpy(L.h_msgs + moff, r.msg, r.len);
     L.items.push_back({r.param, r.slot, moff, r.len, soff});
     L.sig_off.push_back(soff);
-    moff += r.len;
+    moff = (moff + r.len + 3) / 4 * 4;  // 4-byte aligned messages stream as dwords
     soff += sb;
     L.reqs.push_back(std::move(r));
     s->pending.pop_front();

@@ -298,16 +298,21 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def pack_batch(params, slots, messages, align: int = 16):
-    """Lay out messages and signature slots; returns (items, msg_blob, sig_bytes_total)."""
+def pack_batch(params, slots, messages, align: int = 16, msg_align: int = 4):
+    """Lay out messages (each at a msg_align-byte offset; 4-byte aligned
+    messages are hashed from dword loads) and signature slots; returns
+    (items, msg_blob, sig_bytes_total)."""
     items = np.zeros(len(messages), dtype=ITEM_DTYPE)
+    parts = []
     moff = 0
     soff = 0
     for i, (p, s, m) in enumerate(zip(params, slots, messages)):
         items[i] = (p, s, moff, len(m), soff)
-        moff += len(m)
+        pad = (-len(m)) % msg_align
+        parts.append(m + bytes(pad))
+        moff += len(m) + pad
         soff += (sizes(p)["sig_bytes"] + align - 1) // align * align
-    return items, b"".join(messages), soff
+    return items, b"".join(parts), soff
 
 
 def sign_messages_ext(ctx: Context, params, slots, messages, contexts=None, prehash=None, rnds=None,

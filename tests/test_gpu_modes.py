@@ -62,7 +62,9 @@ def test_graph_mixed_batch_replays(slh, keys):
         d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
         for rep in range(3):
             msgs = [rng.bytes(L) for L in lens]
-            d_m.copy_(torch.frombuffer(bytearray(b"".join(msgs) or b"\0"), dtype=torch.uint8))
+            _, blob2, _ = slh.pack_batch(params, [slots[p] for p in params], msgs)
+            assert len(blob2) == len(blob)
+            d_m.copy_(torch.frombuffer(bytearray(blob2 or b"\0"), dtype=torch.uint8))
             print("graph replay", rep, flush=True)
             ctx.sign_batch(items, (d_m.data_ptr(), len(blob)), d_s, slh.MODES["graph"])
             torch.cuda.synchronize()

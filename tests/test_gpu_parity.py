@@ -103,26 +103,30 @@ def test_mixed_batch_lengths_and_keys(slh, ctx):
     assert alone[0] == got[5]
 
 
-def test_unaligned_message_offsets(slh, ctx):
-    seed = workloads.key_seed(1, 3)
-    pk, sk = oracle_keys(1, [seed])[0]
-    slot = ctx.add_keys(1, sk)
+@pytest.mark.parametrize("param", [1, 3])
+def test_unaligned_message_offsets(slh, ctx, param):
+    seed = workloads.key_seed(param, 3)
+    pk, sk = oracle_keys(param, [seed])[0]
+    slot = ctx.add_keys(param, sk)
     import torch
-    blob = bytes(range(256)) * 4
-    items = np.zeros(5, dtype=slh.ITEM_DTYPE)
-    offs = [1, 7, 130, 333, 999]
-    lens = [5, 60, 1, 200, 25]
-    sigb = slh.sizes(1)["sig_bytes"]
-    for i in range(5):
-        items[i] = (1, slot, offs[i], lens[i], i * sigb)
+    blob = bytes(range(256)) * 8
+    # odd and aligned offsets; long messages cover whole blocks read byte by
+    # byte (odd offsets) and as aligned dwords (offsets 4 and 1032)
+    offs = [1, 7, 130, 333, 999, 3, 4, 1032, 1]
+    lens = [5, 60, 1, 200, 25, 600, 700, 513, 2047]
+    n = len(offs)
+    items = np.zeros(n, dtype=slh.ITEM_DTYPE)
+    sigb = slh.sizes(param)["sig_bytes"]
+    for i in range(n):
+        items[i] = (param, slot, offs[i], lens[i], i * sigb)
     d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
-    d_s = torch.zeros(5 * sigb, dtype=torch.uint8, device="cuda")
+    d_s = torch.zeros(n * sigb, dtype=torch.uint8, device="cuda")
     ctx.sign_batch(items, d_m, d_s)
     torch.cuda.synchronize()
     host = d_s.cpu().numpy().tobytes()
-    want = oracle_sign_many([(1, sk, blob[o:o + L]) for o, L in zip(offs, lens)])
-    for i in range(5):
-        assert host[i * sigb:(i + 1) * sigb] == want[i]
+    want = oracle_sign_many([(param, sk, blob[o:o + L]) for o, L in zip(offs, lens)])
+    for i in range(n):
+        assert host[i * sigb:(i + 1) * sigb] == want[i], "offset %d length %d" % (offs[i], lens[i])
 
 
 @pytest.mark.parametrize("param", [1, 2, 3])
