@@ -155,10 +155,16 @@ def cpu_baseline(name, workloads, seconds=15.0):
                       % (done, name, threads, el)}
 
 
-# HBM bytes per k_tree launch (4096 signatures) from rocprofv3 FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0 (copy-kernel calibration); None where not measured for the
-# current kernel.
-TRAFFIC = {}  # (param, kernel) -> bytes per launch
+# HBM bytes per launch of the dominant kernel at batch 4096, from rocprofv3
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB per dispatch (a 1 GiB device copy
+# reads 524 300 KiB of FETCH_SIZE and 1 048 576 KiB of WRITE_SIZE); the
+# summaries are in profiles/.  Absent where not measured for the current
+# kernel.
+TRAFFIC = {  # (param, kernel) -> bytes per launch
+    (1, "k_fused"): (194784 * 2 + 1214190) * 1024,
+    (2, "k_tree"): (433176 * 2 + 2611719) * 1024,
+    (3, "k_tree"): (1172797 * 2 + 4684233) * 1024,
+}
 
 
 def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0):

@@ -15,8 +15,11 @@ block), counted from its disassembly and confirmed by SQ_INSTS_VALU:
   SHA-256: 1232 (rounds 0-4 of every chain step and 7 of the 48 schedule
            words depend only on the chain's address, so they are computed
            once per chain, not per step);
-  SHA-512: 4541 (rounds 0-15 peeled, then four 16-round blocks; 64-bit adds
-           are single v_lshl_add_u64 instructions).
+  SHA-512: 3490 (rounds 0-15 peeled, about 490 instructions, then four
+           16-round blocks of about 750; every 64-bit add is one
+           v_lshl_add_u64).
+SQ_INSTS_VALU of whole launches agrees within 2 % (the rest is loads,
+address arithmetic and lanes masked off in the upper Merkle levels).
 For comparison, the textbook count with one instruction per primitive of
 FIPS 180-4 and no precomputation is:
   SHA-256: round = Sigma1 (3 rotates + 1 xor3) + Ch + Sigma0 (3 + 1) + Maj
@@ -36,7 +39,7 @@ from dataclasses import dataclass
 TEXTBOOK_SHA256 = 64 * 14 + 48 * 10 + 8
 TEXTBOOK_SHA512 = 80 * 34 + 64 * 22 + 16
 OPS_SHA256 = 1232
-OPS_SHA512 = 4541
+OPS_SHA512 = 3490
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock for 32-bit integer VALU
 # operations at the 2.4 GHz peak engine clock.
