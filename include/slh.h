@@ -245,8 +245,9 @@ typedef struct {
     uint64_t pk_off;
 } slh_verify_item;
 
-/* Verify a batch (Algorithm 20 per item) on the context's GPU: one
- * workgroup per signature.  results (device, count int32) receives 1 for a
+/* Verify a batch (Algorithm 20 per item) on the context's GPU: 16 lanes per
+ * signature, 16 signatures per workgroup, the WOTS+ chains of each layer
+ * balanced over the 16 lanes.  results (device, count int32) receives 1 for a
  * valid signature and 0 otherwise, in item order.  Asynchronous on `stream`
  * like slh_sign_batch.  Errors: SLH_EINVAL (nothing launched), SLH_ENOMEM,
  * SLH_EDEVICE. */

@@ -1104,14 +1104,14 @@ int slh_verify_batch(slh_ctx* c, const slh_verify_item* items, uint32_t count, c
   VerifyItem* d = reinterpret_cast<VerifyItem*>(c->vbuf);
   HIPCHK(c, hipMemcpyAsync(d, c->vstage, size_t(count) * sizeof(VerifyItem), hipMemcpyHostToDevice, s));
   if (per[1])
-    hipLaunchKernelGGL((k_verify<1>), dim3(uint32_t(per[1])), dim3(kVerifyThreads), 0, s, d + start[1],
-                       uint32_t(per[1]), msgs, sigs, pks, results);
+    hipLaunchKernelGGL((k_verify<1>), dim3(uint32_t((per[1] + kVerifySigs - 1) / kVerifySigs)),
+                       dim3(kVerifyThreads), 0, s, d + start[1], uint32_t(per[1]), msgs, sigs, pks, results);
   if (per[2])
-    hipLaunchKernelGGL((k_verify<2>), dim3(uint32_t(per[2])), dim3(kVerifyThreads), 0, s, d + start[2],
-                       uint32_t(per[2]), msgs, sigs, pks, results);
+    hipLaunchKernelGGL((k_verify<2>), dim3(uint32_t((per[2] + kVerifySigs - 1) / kVerifySigs)),
+                       dim3(kVerifyThreads), 0, s, d + start[2], uint32_t(per[2]), msgs, sigs, pks, results);
   if (per[3])
-    hipLaunchKernelGGL((k_verify<3>), dim3(uint32_t(per[3])), dim3(kVerifyThreads), 0, s, d + start[3],
-                       uint32_t(per[3]), msgs, sigs, pks, results);
+    hipLaunchKernelGGL((k_verify<3>), dim3(uint32_t((per[3] + kVerifySigs - 1) / kVerifySigs)),
+                       dim3(kVerifyThreads), 0, s, d + start[3], uint32_t(per[3]), msgs, sigs, pks, results);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->done, s));
   c->pending = true;

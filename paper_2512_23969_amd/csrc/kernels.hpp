@@ -970,14 +970,26 @@ __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restric
 }
 
 // ------------------------------------------------------------------ verify
-// One workgroup of 128 lanes per signature (FIPS 205 Algorithm 20): the
-// digest on lane 0; FORS pkFromSig with one lane per tree; then, layer by
-// layer, WOTS+ pkFromSig with one lane per chain, T_len and the auth-path
-// climb on lane 0.  The result is 1 (valid) or 0.
+// Batched verification (FIPS 205 Algorithm 20).  A group of kVerifyGroup
+// lanes (a quarter of a wave) verifies one signature; a workgroup of 256
+// lanes holds 16 signatures that go through the same phases together:
+//   setup   : the group's first lane derives the per-key chaining values,
+//             recomputes the digest (H_msg) and splits it;
+//   FORS    : one lane per FORS tree (trees g, g + 16, ...) climbs from the
+//             revealed secret value to the root; the first lane runs T_k;
+//   layers  : per hypertree layer, the len WOTS+ chains are spread over the
+//             16 lanes, longest first in a snake order (rank r goes to lane
+//             r mod 16, reversed on odd rounds), so that every lane has about
+//             the same number of F steps; each lane works through its chains
+//             step by step; the first lane then runs T_len and climbs the
+//             h' authentication levels to the layer's root.
+// The result (1 valid, 0 invalid) is written to results[res_idx].
 struct VerifyItem {
   uint64_t msg_off, msg_len, sig_off, pk_off, res_idx;
 };
-constexpr int kVerifyThreads = 128;
+constexpr int kVerifyThreads = 256;
+constexpr int kVerifyGroup = 16;
+constexpr int kVerifySigs = kVerifyThreads / kVerifyGroup;
 
 __device__ __forceinline__ uint32_t load_be32(const uint8_t* p) {
   return (uint32_t(p[0]) << 24) | (uint32_t(p[1]) << 16) | (uint32_t(p[2]) << 8) | uint32_t(p[3]);
@@ -988,27 +1000,39 @@ __device__ __forceinline__ void load_be(const uint8_t* p, uint32_t* v) {
   for (int i = 0; i < NW; i++) v[i] = load_be32(p + 4 * i);
 }
 
+// Base-16 digit of WOTS+ chain c for message words M (len1 message digits,
+// then the three checksum digits of csum << 4), FIPS 205 Algorithm 7.
+template <int ID>
+__device__ __forceinline__ uint32_t verify_digit(const uint32_t* M, uint32_t csum, uint32_t c) {
+  if (c < uint32_t(P<ID>::len1)) return (M[c >> 3] >> (28 - 4 * (c & 7))) & 15u;
+  return (csum >> (12 - 4 * (c - P<ID>::len1))) & 15u;
+}
+
 template <int ID>
 __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __restrict__ items,
                                                           uint32_t count, const uint8_t* msgs,
                                                           const uint8_t* sigs, const uint8_t* pks,
                                                           int* results) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a;
-  static_assert(LEN <= kVerifyThreads && KT <= kVerifyThreads, "one lane per chain / tree");
-  __shared__ uint32_t pk_seed[8], pk_root[8], mid256[8], mid512[16];
-  __shared__ uint32_t vals[(LEN > KT ? LEN : KT) * NW];
-  __shared__ uint32_t cur[8];
-  __shared__ uint16_t indices[64];
-  __shared__ uint64_t s_tree;
-  __shared__ uint32_t s_leaf;
-  const uint32_t b = blockIdx.x;
-  if (b >= count) return;
-  const VerifyItem it = items[b];
+  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a, G = kVerifyGroup;
+  constexpr int SLOTS = (LEN + G - 1) / G;
+  static_assert(KT <= 64, "FORS indices per signature");
+  __shared__ uint32_t s_vals[kVerifySigs][(LEN > KT ? LEN : KT) * NW];
+  __shared__ uint16_t s_order[kVerifySigs][SLOTS * G];
+  __shared__ uint16_t s_idx[kVerifySigs][64];
+  __shared__ uint32_t s_mid256[kVerifySigs][8], s_mid512[kVerifySigs][16], s_root[kVerifySigs][8];
+  __shared__ uint32_t s_cur[kVerifySigs][8];
+  __shared__ uint64_t s_tree[kVerifySigs];
+  __shared__ uint32_t s_leaf[kVerifySigs];
+  const int tid = threadIdx.x, grp = tid / G, g = tid % G;
+  const uint32_t sidx = blockIdx.x * kVerifySigs + grp;
+  const bool valid = sidx < count;
+  const VerifyItem it = valid ? items[sidx] : VerifyItem{0, 0, 0, 0, 0};
   const uint8_t* sig = sigs + it.sig_off;
-  const uint8_t* msg = msgs + it.msg_off;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
+  uint32_t* vals = s_vals[grp];
+  // ---- setup
+  if (valid && g == 0) {
+    uint32_t pk_seed[8] = {0}, pk_root[8] = {0};
     load_be<NW>(pks + it.pk_off, pk_seed);
     load_be<NW>(pks + it.pk_off + Q::n, pk_root);
     uint32_t st[8], w[16];
@@ -1017,86 +1041,127 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     for (int j = 0; j < 16; j++) w[j] = j < NW ? pk_seed[j] : 0u;
     sha256_compress(st, w);
 #pragma unroll
-    for (int j = 0; j < 8; j++) mid256[j] = st[j];
-    u64p s5[8], w5[16];
-    sha512_iv(s5);
+    for (int j = 0; j < 8; j++) s_mid256[grp][j] = st[j];
+    if constexpr (Q::wide) {
+      u64p s5[8], w5[16];
+      sha512_iv(s5);
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-      w5[j] = u64p{2 * j < NW ? pk_seed[2 * j] : 0u, 2 * j + 1 < NW ? pk_seed[2 * j + 1] : 0u};
-    sha512_compress(s5, w5);
+      for (int j = 0; j < 16; j++)
+        w5[j] = u64p{2 * j < NW ? pk_seed[2 * j] : 0u, 2 * j + 1 < NW ? pk_seed[2 * j + 1] : 0u};
+      sha512_compress(s5, w5);
 #pragma unroll
-    for (int j = 0; j < 8; j++) { mid512[2 * j] = s5[j].hi; mid512[2 * j + 1] = s5[j].lo; }
+      for (int j = 0; j < 8; j++) { s_mid512[grp][2 * j] = s5[j].hi; s_mid512[grp][2 * j + 1] = s5[j].lo; }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) s_root[grp][j] = pk_root[j];
     uint32_t R[NW], digest[16];
     load_be<NW>(sig, R);
     const KeyView kv{nullptr, pk_seed, pk_root, nullptr};
-    h_msg<ID>(kv, R, msg, it.msg_len, digest);
+    h_msg<ID>(kv, R, msgs + it.msg_off, it.msg_len, digest);
     uint64_t tree;
     uint32_t leaf;
-    split_digest<ID>(digest, indices, &tree, &leaf);
-    s_tree = tree;
-    s_leaf = leaf;
+    split_digest<ID>(digest, s_idx[grp], &tree, &leaf);
+    s_tree[grp] = tree;
+    s_leaf[grp] = leaf;
   }
   __syncthreads();
-  uint64_t tree = s_tree;
-  uint32_t leaf = s_leaf;
-  // FORS: root of tree t from its secret value and auth path
-  if (tid < KT) {
-    const uint8_t* ts = sig + Q::n + tid * (A + 1) * Q::n;
-    const uint32_t idx = indices[tid];
-    uint32_t x[NW], y[NW], lr[2 * NW];
-    load_be<NW>(ts, x);
-    uint32_t gi = (uint32_t(tid) << A) + idx;
-    thF<ID>(mid256, make_adrs(0, tree, A_FORS_TREE, leaf, 0, gi), x, y);
-    for (int j = 0; j < A; j++) {
-      uint32_t au[NW];
-      load_be<NW>(ts + (1 + j) * Q::n, au);
-      const bool even = ((idx >> j) & 1u) == 0;
+  uint32_t mid256[8], mid512[16];
 #pragma unroll
-      for (int u = 0; u < NW; u++) {
-        lr[u] = even ? y[u] : au[u];
-        lr[NW + u] = even ? au[u] : y[u];
+  for (int j = 0; j < 8; j++) mid256[j] = s_mid256[grp][j];
+#pragma unroll
+  for (int j = 0; j < 16; j++) mid512[j] = Q::wide ? s_mid512[grp][j] : 0u;
+  uint64_t tree = s_tree[grp];
+  uint32_t leaf = s_leaf[grp];
+  // ---- FORS: roots of trees g, g + G, ...
+  if (valid) {
+    for (int t = g; t < KT; t += G) {
+      const uint8_t* ts = sig + Q::n + t * (A + 1) * Q::n;
+      const uint32_t idx = s_idx[grp][t];
+      uint32_t x[NW], y[NW], lr[2 * NW];
+      load_be<NW>(ts, x);
+      uint32_t gi = (uint32_t(t) << A) + idx;
+      thF<ID>(mid256, make_adrs(0, tree, A_FORS_TREE, leaf, 0, gi), x, y);
+      for (int j = 0; j < A; j++) {
+        uint32_t au[NW];
+        load_be<NW>(ts + (1 + j) * Q::n, au);
+        const bool even = ((idx >> j) & 1u) == 0;
+#pragma unroll
+        for (int u = 0; u < NW; u++) {
+          lr[u] = even ? y[u] : au[u];
+          lr[NW + u] = even ? au[u] : y[u];
+        }
+        gi >>= 1;
+        thH<ID>(mid256, mid512, make_adrs(0, tree, A_FORS_TREE, leaf, j + 1, gi), lr, y);
       }
-      gi >>= 1;
-      thH<ID>(mid256, mid512, make_adrs(0, tree, A_FORS_TREE, leaf, j + 1, gi), lr, y);
+      store_words<NW>(&vals[t * NW], y);
     }
-    store_words<NW>(&vals[tid * NW], y);
   }
   __syncthreads();
-  if (tid == 0) {
+  if (valid && g == 0) {
     auto get = [&](int wi) -> uint32_t { return vals[wi]; };
     uint32_t pk[NW];
     thT<ID, KT>(mid256, mid512, make_adrs(0, tree, A_FORS_ROOTS, leaf, 0, 0), get, pk);
-    store_words<NW>(cur, pk);
+    store_words<NW>(s_cur[grp], pk);
   }
   __syncthreads();
   const uint8_t* ht = sig + Q::ht_off;
   for (int layer = 0; layer < Q::d; layer++) {
     const uint8_t* xs = ht + layer * Q::xmss_bytes;
-    if (tid < LEN) {
-      auto nib = [&](int i) -> uint32_t { return (cur[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
-      uint32_t digit;
-      if (tid < Q::len1) {
-        digit = nib(tid);
-      } else {
-        uint32_t csum = 0;
-        for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
-        csum <<= 4;
-        digit = (csum >> (12 - 4 * (tid - Q::len1))) & 15u;
+    uint32_t M[NW];
+#pragma unroll
+    for (int u = 0; u < NW; u++) M[u] = s_cur[grp][u];
+    uint32_t csum = 0;
+#pragma unroll
+    for (int i = 0; i < Q::len1; i++) csum += 15u - ((M[i >> 3] >> (28 - 4 * (i & 7))) & 15u);
+    csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
+    if (valid) {
+      // chain start values (the signature's WOTS+ part) into LDS, and the
+      // rank of each of this lane's home chains by descending step count
+      for (int c = g; c < LEN; c += G) {
+        uint32_t x[NW];
+        load_be<NW>(xs + c * Q::n, x);
+        store_words<NW>(&vals[c * NW], x);
+        const uint32_t sc = 15u - verify_digit<ID>(s_cur[grp], csum, c);
+        uint32_t rank = 0;
+#pragma unroll
+        for (int c2 = 0; c2 < LEN; c2++) {
+          const uint32_t s2 = 15u - verify_digit<ID>(M, csum, c2);
+          rank += (s2 > sc || (s2 == sc && c2 < c)) ? 1u : 0u;
+        }
+        s_order[grp][rank] = uint16_t(c);
       }
-      uint32_t x[NW];
-      load_be<NW>(xs + tid * Q::n, x);
-      Adrs Ad = make_adrs(layer, tree, A_WOTS_HASH, leaf, tid, 0);
-      for (uint32_t s = digit; s < 15; s++) {
-        Ad.tail = s << 16;
+    }
+    __syncthreads();
+    if (valid) {
+      // this lane's chains: ranks g, 2G - 1 - g, 2G + g, ... (snake order)
+      int slot = 0;
+      int c = -1;
+      uint32_t st = 15, x[NW];
+      for (;;) {
+        while (st == 15) {
+          if (c >= 0) store_words<NW>(&vals[c * NW], x);
+          c = -1;
+          if (slot >= SLOTS) break;
+          const int r = slot * G + ((slot & 1) ? G - 1 - g : g);
+          slot++;
+          if (r >= LEN) continue;
+          c = s_order[grp][r];
+          st = verify_digit<ID>(s_cur[grp], csum, uint32_t(c));
+#pragma unroll
+          for (int u = 0; u < NW; u++) x[u] = vals[c * NW + u];
+        }
+        if (c < 0) break;
+        Adrs Ad = make_adrs(layer, tree, A_WOTS_HASH, leaf, uint32_t(c), 0);
+        Ad.tail = st << 16;
         uint32_t y[NW];
         th256<NW, NW>(mid256, Ad, x, y);
 #pragma unroll
         for (int u = 0; u < NW; u++) x[u] = y[u];
+        st++;
       }
-      store_words<NW>(&vals[tid * NW], x);
     }
     __syncthreads();
-    if (tid == 0) {
+    if (valid && g == 0) {
       auto get = [&](int wi) -> uint32_t { return vals[wi]; };
       uint32_t node[NW], lr[2 * NW];
       thT<ID, LEN>(mid256, mid512, make_adrs(layer, tree, A_WOTS_PK, leaf, 0, 0), get, node);
@@ -1104,7 +1169,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
       for (int j = 0; j < Q::hp; j++) {
         uint32_t au[NW];
         load_be<NW>(xs + (LEN + j) * Q::n, au);
-        const bool even = ((leaf >> j) & 1u) == 0;
+        const bool even = (ti & 1u) == 0;
 #pragma unroll
         for (int u = 0; u < NW; u++) {
           lr[u] = even ? node[u] : au[u];
@@ -1113,16 +1178,16 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
         ti >>= 1;
         thH<ID>(mid256, mid512, make_adrs(layer, tree, A_TREE, 0, j + 1, ti), lr, node);
       }
-      store_words<NW>(cur, node);
+      store_words<NW>(s_cur[grp], node);
     }
     __syncthreads();
     leaf = uint32_t(tree & ((1u << Q::hp) - 1));
     tree = Q::hp >= 64 ? 0 : (tree >> Q::hp);
   }
-  if (tid == 0) {
+  if (valid && g == 0) {
     bool ok = true;
 #pragma unroll
-    for (int u = 0; u < NW; u++) ok = ok && (cur[u] == pk_root[u]);
+    for (int u = 0; u < NW; u++) ok = ok && (s_cur[grp][u] == s_root[grp][u]);
     results[it.res_idx] = ok ? 1 : 0;
   }
 }
