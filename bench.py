@@ -324,6 +324,8 @@ def main():
     ap.add_argument("--serve-mode", default="fused", choices=["plain", "fused", "dedup", "fused-dedup"])
     ap.add_argument("--serve-cache-layers", type=int, default=0,
                     help="upper hypertree layers cached per key on the server's lanes (dedup modes)")
+    ap.add_argument("--no-serve-dedup", action="store_true",
+                    help="skip the second serving run (fused-dedup with 4 cached layers per key)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
@@ -394,9 +396,14 @@ def main():
         line["extra"] = extra
     if args.serve_n:
         log("bench: serving")
-        line["serving"] = serve_bench(slh, workloads, args.serve_n,
-                                      [float(x) for x in args.serve_rates.split(",")], log,
-                                      args.serve_mode, args.serve_cache_layers)
+        rates = [float(x) for x in args.serve_rates.split(",")]
+        line["serving"] = serve_bench(slh, workloads, args.serve_n, rates, log, args.serve_mode,
+                                      args.serve_cache_layers)
+        if not args.no_serve_dedup:
+            # tree sharing across the requests of a key (within-batch dedup and
+            # a per-key cache of the top layers): same bytes, less work
+            log("bench: serving with dedup and key cache")
+            line["serving_dedup_cache"] = serve_bench(slh, workloads, args.serve_n, rates, log, "fused-dedup", 4)
     if not args.no_cpu:
         log("bench: cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args.workload, workloads, args.cpu_seconds)

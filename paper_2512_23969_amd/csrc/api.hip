@@ -35,31 +35,6 @@ bool sizes_of(uint32_t param, Sizes* s) {
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Working memory of one chunk of `c` messages of parameter set ID.
-template <int ID>
-struct Layout {
-  using Q = P<ID>;
-  static size_t tree_blocks(size_t c) {
-    const size_t trees = c * Q::d;
-    const size_t tpb = kLeavesPerBlock / Q::leaves;
-    return (trees + tpb - 1) / tpb;
-  }
-  static size_t recs(size_t c) { return up(c * sizeof(WorkRec)); }
-  static size_t items(size_t c) { return up(c * sizeof(DevItem)); }
-  static size_t stage(size_t c) { return up(tree_blocks(c) * Q::len * kLeavesPerBlock * Q::NW * 4); }
-  static size_t spill(size_t c) { return up(c * Q::d * Q::len * 16 * Q::NW * 4); }
-  static size_t roots(size_t c) { return up(c * Q::k * Q::NW * 4); }
-  static size_t total(size_t c) { return recs(c) + items(c) + stage(c) + spill(c) + roots(c); }
-};
-
-size_t per_message_bytes(uint32_t param) {
-  switch (param) {
-    case 1: return Layout<1>::total(1024) / 1024 + 1;
-    case 2: return Layout<2>::total(1024) / 1024 + 1;
-    default: return Layout<3>::total(1024) / 1024 + 1;
-  }
-}
-
 void be_words(const uint8_t* b, int nbytes, uint32_t* w) {
   for (int i = 0; i < nbytes / 4; i++)
     w[i] = (uint32_t(b[4 * i]) << 24) | (uint32_t(b[4 * i + 1]) << 16) | (uint32_t(b[4 * i + 2]) << 8) |

@@ -130,3 +130,39 @@ def test_dedup_rejects_unknown_mode_bits(slh):
         slot = ctx.add_keys(p, sk)
         with pytest.raises(slh.SlhError):
             slh.sign_messages(ctx, [p], [slot], [b"x"], 8)
+
+
+def test_graph_dedup_replays(slh):
+    """A captured dedup pipeline replayed with new message bytes: the hash
+    table, representative list and leaf owners are rebuilt inside the graph
+    on every replay, so every replay matches the oracle."""
+    import torch
+    p = 1
+    keys = oracle_keys(p, [workloads.key_seed(p, 150), workloads.key_seed(p, 151)])
+    rng = np.random.default_rng(41)
+    kidx = [int(rng.integers(0, 2)) for _ in range(40)]
+    lens = [int(rng.integers(0, 100)) for _ in range(40)]
+    lens[5], kidx[5] = lens[3], kidx[3]  # room for an exact repeat
+    with slh.Context(0) as ctx:
+        first = ctx.add_keys(p, [sk for _, sk in keys])
+        msgs = [rng.bytes(L) for L in lens]
+        items, blob, total = slh.pack_batch([p] * 40, [first + k for k in kidx], msgs)
+        d_m = torch.zeros(max(1, len(blob)), dtype=torch.uint8, device="cuda")
+        d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
+        for rep in range(3):
+            msgs = [rng.bytes(L) for L in lens]
+            if rep == 2:  # an exact repeat of (key, message) inside the batch
+                msgs[5] = msgs[3]
+            _, blob2, _ = slh.pack_batch([p] * 40, [first + k for k in kidx], msgs)
+            d_m.copy_(torch.frombuffer(bytearray(blob2 or b"\0"), dtype=torch.uint8))
+            print("graph-dedup replay", rep, flush=True)
+            ctx.sign_batch(items, (d_m.data_ptr(), len(blob)), d_s, slh.MODES["graph-dedup"])
+            torch.cuda.synchronize()
+            host = d_s.cpu().numpy().tobytes()
+            sb = slh.sizes(p)["sig_bytes"]
+            want = oracle_sign_many([(p, keys[k][1], m) for k, m in zip(kidx, msgs)])
+            for i in range(40):
+                o = int(items[i]["sig_off"])
+                assert host[o:o + sb] == want[i], "replay %d item %d: %s" % (rep, i, describe_diff(p, host[o:o + sb], want[i]))
+            d_s.zero_()
+            torch.cuda.synchronize()
