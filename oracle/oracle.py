@@ -16,7 +16,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-PARAM_IDS = {"128f": 1, "192f": 2, "256f": 3}
+PARAM_IDS = {"128f": 1, "192f": 2, "256f": 3, "128s": 4, "192s": 5, "256s": 6}
 
 
 def build(force: bool = True) -> str:
@@ -91,7 +91,7 @@ def lib():
 
 
 def params(which) -> or_params:
-    """Parameter struct for '128f' / '192f' / '256f' (or ids 1..3)."""
+    """Parameter struct for '128f' / '192f' / '256f' / '128s' / '192s' / '256s' (or ids 1..6)."""
     pid = PARAM_IDS.get(which, which)
     p = or_params()
     if lib().or_params_get(int(pid), ctypes.byref(p)) != 0:

@@ -331,6 +331,9 @@ int or_params_get(int id, or_params *p)
     case 1: return or_params_custom(16, 66, 22, 6, 33, p);  /* SHA2-128f */
     case 2: return or_params_custom(24, 66, 22, 8, 33, p);  /* SHA2-192f */
     case 3: return or_params_custom(32, 68, 17, 9, 35, p);  /* SHA2-256f */
+    case 4: return or_params_custom(16, 63, 7, 12, 14, p);  /* SHA2-128s */
+    case 5: return or_params_custom(24, 63, 7, 14, 17, p);  /* SHA2-192s */
+    case 6: return or_params_custom(32, 64, 8, 14, 22, p);  /* SHA2-256s */
     default: return -1;
     }
 }

@@ -49,8 +49,8 @@ extern "C" {
 #define OR_MAX_N 32
 #define OR_MAX_LEN 70     /* WOTS+ chains per key (67 for n = 32) */
 #define OR_MAX_K 64       /* FORS trees */
-#define OR_MAX_A 12       /* FORS tree height */
-#define OR_MAX_HP 8       /* XMSS tree height h' */
+#define OR_MAX_A 14       /* FORS tree height (14 for 192s / 256s) */
+#define OR_MAX_HP 9       /* XMSS tree height h' (9 for 128s / 192s) */
 #define OR_MAX_D 32       /* hypertree layers */
 
 /* A parameter set (FIPS 205 Table 2 naming; the paper's Table 1 gives

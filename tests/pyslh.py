@@ -68,6 +68,9 @@ SETS = {
     "128f": P(16, 66, 22, 6, 33),
     "192f": P(24, 66, 22, 8, 33),
     "256f": P(32, 68, 17, 9, 35),
+    "128s": P(16, 63, 7, 12, 14),
+    "192s": P(24, 63, 7, 14, 17),
+    "256s": P(32, 64, 8, 14, 22),
 }
 
 # address types
