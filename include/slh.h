@@ -46,9 +46,18 @@
 extern "C" {
 #endif
 
+/* Parameter sets: the SHA2 "fast" sets the paper evaluates (its Table 1)
+ * and the SHA2 "small" sets (FIPS 205 Table 2; h' = 8-9, FORS trees of
+ * 2^12-2^14 leaves, built on the GPU in units of 64 XMSS leaves and 2^12
+ * FORS leaves).  SLH_MODE_FUSED, SLH_MODE_DEDUP and slh_ctx_cache_keys
+ * apply to the fast sets; small-set requests always take the per-phase
+ * path. */
 #define SLH_SHA2_128F 1u
 #define SLH_SHA2_192F 2u
 #define SLH_SHA2_256F 3u
+#define SLH_SHA2_128S 4u
+#define SLH_SHA2_192S 5u
+#define SLH_SHA2_256S 6u
 
 #define SLH_OK 0
 #define SLH_EINVAL (-1)  /* bad parameter set, slot, size, offset or null pointer */

@@ -68,7 +68,8 @@ class Params:
         return self.n >= 24
 
 
-PARAMS = {1: Params(16, 66, 22, 6, 33), 2: Params(24, 66, 22, 8, 33), 3: Params(32, 68, 17, 9, 35)}
+PARAMS = {1: Params(16, 66, 22, 6, 33), 2: Params(24, 66, 22, 8, 33), 3: Params(32, 68, 17, 9, 35),
+          4: Params(16, 63, 7, 12, 14), 5: Params(24, 63, 7, 14, 17), 6: Params(32, 64, 8, 14, 22)}
 
 
 def t_blocks(p: Params, l: int) -> int:
@@ -105,7 +106,7 @@ def prelude_compressions(param: int, mlen: int) -> tuple[int, int]:
     inner digest) and H_msg = MGF1(R | PK.seed | Hash(R | PK.seed | PK.root
     | M), m)."""
     p = PARAMS[param]
-    m = {1: 34, 2: 42, 3: 49}[param]
+    m = (p.k * p.a + 7) // 8 + (p.h - p.hp + 7) // 8 + (p.hp + 7) // 8
     if not p.wide:
         blk = lambda b: (b + 9 + 63) // 64  # noqa: E731
         prf = blk(64 + p.n + mlen) + blk(64 + 32)

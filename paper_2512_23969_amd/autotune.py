@@ -32,7 +32,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
 
 # (n, a = log t, k) of the parameter sets (the paper's Table 1)
-FORS_SHAPE = {1: (16, 6, 33), 2: (24, 8, 33), 3: (32, 9, 35)}
+FORS_SHAPE = {1: (16, 6, 33), 2: (24, 8, 33), 3: (32, 9, 35), 4: (16, 12, 14), 5: (24, 14, 17), 6: (32, 14, 22)}
 
 
 def tree_tuning(k: int, log_t: int, n: int, s_max: int, t_max: int = 1024, alpha: float = 0.6):
@@ -64,26 +64,30 @@ def tree_tuning(k: int, log_t: int, n: int, s_max: int, t_max: int = 1024, alpha
     return best, cand
 
 
-COMPILED_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8)}
+COMPILED_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8), 4: (1, 2), 5: (1, 2), 6: (1, 2)}
 
 
 def gfx950_groups(param: int, lds_bytes: int = 160 * 1024, lanes: int = 256, compiled=None):
     """FORS groupings of this library ranked analytically for gfx950.
 
-    A group of FG trees keeps FG * 2^(a-1) level-1 nodes of n bytes in LDS
-    and is reduced by one workgroup of `lanes` lanes.  Returns a list of
-    dicts sorted by (barriers per message, idle lanes in the pair phase)."""
+    A group of FG units (a unit is a FORS tree, or for trees above 2^12
+    leaves a subtree of 2^12 leaves) keeps FG * 2^(au-1) level-1 nodes of n
+    bytes in LDS and is reduced by one workgroup of `lanes` lanes.  Returns
+    a list of dicts sorted by (barriers per message, idle lanes in the pair
+    phase)."""
     n, a, k = FORS_SHAPE[param]
+    au = min(a, 12)
+    units = k << (a - au)  # units per message
     out = []
     for fg in compiled or COMPILED_GROUPS[param]:
-        lds = fg * (1 << (a - 1)) * n
+        lds = fg * (1 << (au - 1)) * n
         if lds > lds_bytes:
             continue
-        pairs = fg * (1 << (a - 1))
+        pairs = fg * (1 << (au - 1))
         rounds = math.ceil(pairs / lanes)
         idle = rounds * lanes - pairs
-        groups_per_msg = k / fg
-        barriers = groups_per_msg * a  # one per level of every group
+        groups_per_msg = units / fg
+        barriers = groups_per_msg * au  # one per level of every group
         out.append({"fg": fg, "lds_bytes": lds, "pair_rounds": rounds, "idle_lanes": idle,
                     "barriers_per_msg": barriers, "wgs_per_cu_lds": lds_bytes // max(1, lds)})
     out.sort(key=lambda c: (c["barriers_per_msg"], c["idle_lanes"]))

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/slh.h"
@@ -28,10 +29,14 @@ bool sizes_of(uint32_t param, Sizes* s) {
     case SLH_SHA2_128F: *s = {16, 66, 22, 3, 6, 33, 35, 34, uint32_t(P<1>::sig_bytes)}; return true;
     case SLH_SHA2_192F: *s = {24, 66, 22, 3, 8, 33, 51, 42, uint32_t(P<2>::sig_bytes)}; return true;
     case SLH_SHA2_256F: *s = {32, 68, 17, 4, 9, 35, 67, 49, uint32_t(P<3>::sig_bytes)}; return true;
+    case SLH_SHA2_128S: *s = {16, 63, 7, 9, 12, 14, 35, 30, uint32_t(P<4>::sig_bytes)}; return true;
+    case SLH_SHA2_192S: *s = {24, 63, 7, 9, 14, 17, 51, 39, uint32_t(P<5>::sig_bytes)}; return true;
+    case SLH_SHA2_256S: *s = {32, 64, 8, 8, 14, 22, 67, 47, uint32_t(P<6>::sig_bytes)}; return true;
     default: return false;
   }
 }
 
+constexpr int kSets = 6;  // parameter sets 1..6 (slh.h SLH_SHA2_*)
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -64,12 +69,12 @@ struct Tuning {
 };
 
 struct GraphKey {
-  size_t n[4];
+  size_t n[kSets + 1];
   const void* msgs;
   void* sigs;
-  uint8_t* ws[4];
-  size_t ws_bytes[4];
-  uint32_t fg[4], wpc[4], keep[4];
+  uint8_t* ws[kSets + 1];
+  size_t ws_bytes[kSets + 1];
+  uint32_t fg[kSets + 1], wpc[kSets + 1], keep[kSets + 1];
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof o) == 0; }
 };
 
@@ -81,9 +86,9 @@ struct slh_ctx {
   DevKey* keys = nullptr;
   uint32_t nkeys = 0, cap = 0;
   std::vector<uint32_t> key_param;
-  uint8_t* ws[4] = {nullptr, nullptr, nullptr, nullptr};  // working memory per parameter set
-  size_t ws_bytes[4] = {0, 0, 0, 0};
-  Tuning tune[4];
+  uint8_t* ws[kSets + 1] = {};  // working memory per parameter set
+  size_t ws_bytes[kSets + 1] = {};
+  Tuning tune[kSets + 1];
   DevItem* staging = nullptr;  // pinned host copy of the items of a call
   size_t staging_cap = 0;
   uint8_t* vbuf = nullptr;     // device copy of a verify batch's items
@@ -93,8 +98,8 @@ struct slh_ctx {
   hipEvent_t done = nullptr;   // end of the last call's GPU work
   bool pending = false;
   hipStream_t cap_stream = nullptr;          // stream graphs are captured on
-  hipStream_t branch[4] = {nullptr, nullptr, nullptr, nullptr};
-  hipEvent_t fork = nullptr, join[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t branch[kSets + 1] = {};
+  hipEvent_t fork = nullptr, join[kSets + 1] = {};
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
   // optional per-phase timing: event pairs around every kernel launch
   bool profile = false;
@@ -165,11 +170,45 @@ void drop_graphs(slh_ctx* c) {
 }
 
 // FORS trees per workgroup that have a compiled variant, per parameter set.
+// Small sets: FORS units of 2^12 leaves, one or two per workgroup.
 bool fg_ok(uint32_t param, uint32_t fg) {
+  if (param >= 4) return fg == 1 || fg == 2;
   if (param == 3) return fg == 2 || fg == 4 || fg == 8;
   return fg == 4 || fg == 8 || fg == 16;
 }
-uint32_t fg_default(uint32_t param) { return param == 3 ? 4u : 8u; }
+uint32_t fg_default(uint32_t param) { return param >= 4 ? 1u : (param == 3 ? 4u : 8u); }
+
+// The fused persistent kernel, dedup and the key cache cover the sets whose
+// XMSS and FORS trees fit one unit (the fast sets).
+template <int ID>
+constexpr bool whole_trees() { return P<ID>::tree_units == 1 && P<ID>::fors_units == 1; }
+
+// Call f(std::integral_constant<int, FG>) for the compiled FORS group size fg.
+template <int FG>
+using FgC = std::integral_constant<int, FG>;
+template <int ID, typename F>
+void with_fg(uint32_t fg, F&& f) {
+  if constexpr (ID >= 4) {
+    if (fg == 2) f(FgC<2>{}); else f(FgC<1>{});
+  } else if constexpr (ID == 3) {
+    if (fg == 2) f(FgC<2>{}); else if (fg == 8) f(FgC<8>{}); else f(FgC<4>{});
+  } else {
+    if (fg == 4) f(FgC<4>{}); else if (fg == 16) f(FgC<16>{}); else f(FgC<8>{});
+  }
+}
+
+// Call f(std::integral_constant<int, ID>) for parameter set `param` (1..6).
+template <typename F>
+auto with_set(uint32_t param, F&& f) {
+  switch (param) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    default: return f(std::integral_constant<int, 6>{});
+  }
+}
 
 template <int ID, int FG>
 int occupancy_of() {
@@ -185,7 +224,9 @@ int occupancy_of() {
 }
 template <int ID>
 int occupancy(uint32_t fg) {
-  if constexpr (ID == 3) {
+  if constexpr (!whole_trees<ID>()) {
+    return 1;
+  } else if constexpr (ID == 3) {
     return fg == 2 ? occupancy_of<ID, 2>() : fg == 8 ? occupancy_of<ID, 8>() : occupancy_of<ID, 4>();
   } else {
     return fg == 4 ? occupancy_of<ID, 4>() : fg == 16 ? occupancy_of<ID, 16>() : occupancy_of<ID, 8>();
@@ -193,26 +234,34 @@ int occupancy(uint32_t fg) {
 }
 
 // Working-memory plan of one chunk of `n` messages of parameter set ID.
+// TREE blocks of one plain launch at most (the staging is reused by the
+// launches of a chunk when the small sets need more blocks than this).
+constexpr uint32_t kMaxTreeBlocks = 32768;
+
 template <int ID>
 struct Plan {
   using Q = P<ID>;
+  static constexpr uint32_t TPB = kLeavesPerBlock >> Q::unit_hp;  // trees (or units) per TREE block
   size_t n = 0;
   bool fused = false, dedup = false, keep = true;
   uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0, table = 0;
   size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
-  size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, total = 0;
+  size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, o_troots = 0, o_uroots = 0, total = 0;
   static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
   Plan(size_t n_, uint32_t mode, const Tuning& t, int cus)
-      : n(n_), fused((mode & SLH_MODE_FUSED) != 0), dedup((mode & SLH_MODE_DEDUP) != 0), keep(t.keep != 0) {
+      : n(n_),
+        fused(whole_trees<ID>() && (mode & SLH_MODE_FUSED) != 0),
+        dedup(whole_trees<ID>() && (mode & SLH_MODE_DEDUP) != 0),
+        keep(t.keep != 0) {
     fg = t.fg ? t.fg : fg_default(ID);
     const size_t trees = n * Q::d;
-    ntb = uint32_t((trees + kLeavesPerBlock / Q::leaves - 1) / (kLeavesPerBlock / Q::leaves));
-    nfg = uint32_t((n * Q::k + fg - 1) / fg);
+    ntb = uint32_t((trees * Q::tree_units + TPB - 1) / TPB);
+    nfg = uint32_t((n * Q::k * Q::fors_units + fg - 1) / fg);
     if (fused) {
       const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg));
       grid = std::min<uint32_t>(per_cu * uint32_t(cus), ntb + nfg);
     } else {
-      grid = ntb;
+      grid = std::min(ntb, kMaxTreeBlocks);
     }
     o_recs = 0;
     o_items = o_recs + up(n * sizeof(WorkRec));
@@ -220,7 +269,9 @@ struct Plan {
     // the fused kernel double-buffers its staging per workgroup
     o_spill = o_stage + up(size_t(grid) * stage_per_block * (fused ? 2 : 1));
     o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
-    o_queue = o_roots + up(n * Q::k * Q::NW * 4);
+    o_troots = o_roots + up(n * Q::k * Q::fors_units * Q::NW * 4);  // unit roots
+    o_uroots = o_troots + (Q::fors_units > 1 ? up(n * Q::k * Q::NW * 4) : 0);  // tree roots
+    o_queue = o_uroots + (Q::tree_units > 1 ? up(trees * Q::tree_units * Q::NW * 4) : 0);
     // dedup: hash table (>= 2 slots per tree), representative per tree, list
     // of representatives (its count is the word after the work counter), the
     // owner of every leaf of every tree, and every node of every tree
@@ -261,7 +312,7 @@ int ensure_ws(slh_ctx* c, int p, size_t bytes) {
 // the sets the context holds keys of.
 uint64_t budget_share(const slh_ctx* c) {
   int sets = 0;
-  for (int p = 1; p <= 3; p++)
+  for (int p = 1; p <= kSets; p++)
     sets += std::find(c->key_param.begin(), c->key_param.end(), uint32_t(p)) != c->key_param.end() ? 1 : 0;
   return c->budget / uint64_t(sets ? sets : 1);
 }
@@ -269,7 +320,7 @@ uint64_t budget_share(const slh_ctx* c) {
 template <int ID, int FG>
 void launch_fors(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* roots, hipStream_t s) {
   hipLaunchKernelGGL((k_fors<ID, FG>), dim3(pl.nfg), dim3(kForsThreads), 0, s, c->keys, recs,
-                     uint32_t(pl.n * P<ID>::k), sigs, roots);
+                     uint32_t(pl.n * P<ID>::k * P<ID>::fors_units), sigs, roots);
 }
 // Dedup buffers of a chunk (all null without dedup).
 struct DedupBufs {
@@ -316,7 +367,8 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
     PhaseTimer t(c, s, SLH_PHASE_PRELUDE, n, timing);
     hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs, sigs, recs,
                        pl.fused ? queue : nullptr);
-    if (pl.dedup) {
+    if constexpr (whole_trees<ID>()) {
+      if (pl.dedup) {
       const uint32_t nlown = trees * Q::leaves;
       hipLaunchKernelGGL(k_dedup_init, dim3((std::max(pl.table, nlown) + 255) / 256), dim3(256), 0, s, db.table,
                          pl.table, db.lown, nlown, db.ucount);
@@ -325,49 +377,59 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
       hipLaunchKernelGGL((k_dedup_resolve<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, recs, n, db.table,
                          db.rep, db.ulist, db.ucount, db.lown);
       hipLaunchKernelGGL(k_dedup_stats, dim3(1), dim3(64), 0, s, trees, db.ucount, c->dstats);
+      }
     }
   }
-  if (pl.fused) {
-    PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
-    if constexpr (ID == 3) {
-      if (pl.fg == 2) launch_fused<ID, 2>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
-      else if (pl.fg == 8) launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
-      else launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
-    } else {
-      if (pl.fg == 4) launch_fused<ID, 4>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
-      else if (pl.fg == 16) launch_fused<ID, 16>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
-      else launch_fused<ID, 8>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+  if constexpr (whole_trees<ID>()) {
+    if (pl.fused) {
+      PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
+      with_fg<ID>(pl.fg, [&](auto fgc) {
+        launch_fused<ID, decltype(fgc)::value>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+      });
     }
-  } else {
+  }
+  if (!pl.fused) {
     {
       PhaseTimer t(c, s, SLH_PHASE_FORS, n, timing);
-      if constexpr (ID == 3) {
-        if (pl.fg == 2) launch_fors<ID, 2>(c, pl, sigs, recs, roots, s);
-        else if (pl.fg == 8) launch_fors<ID, 8>(c, pl, sigs, recs, roots, s);
-        else launch_fors<ID, 4>(c, pl, sigs, recs, roots, s);
-      } else {
-        if (pl.fg == 4) launch_fors<ID, 4>(c, pl, sigs, recs, roots, s);
-        else if (pl.fg == 16) launch_fors<ID, 16>(c, pl, sigs, recs, roots, s);
-        else launch_fors<ID, 8>(c, pl, sigs, recs, roots, s);
+      with_fg<ID>(pl.fg, [&](auto fgc) { launch_fors<ID, decltype(fgc)::value>(c, pl, sigs, recs, roots, s); });
+      if constexpr (Q::fors_units > 1) {
+        const uint32_t nft = n * Q::k;
+        hipLaunchKernelGGL((k_fors_top<ID>), dim3((nft + 63) / 64), dim3(64), 0, s, c->keys, recs, nft, sigs, roots,
+                           reinterpret_cast<uint32_t*>(base + pl.o_troots));
       }
     }
     {
       PhaseTimer t(c, s, SLH_PHASE_TREE, n, timing);
-      hipLaunchKernelGGL((k_tree<ID, kSignTrees>), dim3(pl.ntb), dim3(kTreeThreads), 0, s, c->keys, recs, trees, sigs,
-                         stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, 0u);
+      uint32_t* uroots = Q::tree_units > 1 ? reinterpret_cast<uint32_t*>(base + pl.o_uroots) : nullptr;
+      const uint32_t units = trees * Q::tree_units;
+      // at most kMaxTreeBlocks blocks per launch, reusing the staging
+      for (uint32_t b0 = 0; b0 < pl.ntb; b0 += kMaxTreeBlocks) {
+        const uint32_t nb = std::min(kMaxTreeBlocks, pl.ntb - b0), first = b0 * Plan<ID>::TPB;
+        hipLaunchKernelGGL((k_tree<ID, kSignTrees>), dim3(nb), dim3(kTreeThreads), 0, s, c->keys, recs,
+                           std::min(units - first, nb * Plan<ID>::TPB), sigs, stage, spill, 0u, nullptr, db.ulist,
+                           db.ucount, db.lown, db.nodes, first, uroots);
+      }
+      if constexpr (Q::tree_units > 1)
+        hipLaunchKernelGGL((k_tree_top<ID, kSignTrees>), dim3((trees + 63) / 64), dim3(64), 0, s, c->keys, recs,
+                           trees, sigs, 0u, nullptr, 0u, uroots);
     }
   }
   {
     PhaseTimer t(c, s, SLH_PHASE_WOTS, n, timing);
-    if (pl.dedup)
-      hipLaunchKernelGGL((k_dedup_scatter<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs,
-                         db.rep, db.nodes, c->cache);
-    hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, roots);
+    if constexpr (whole_trees<ID>()) {
+      if (pl.dedup)
+        hipLaunchKernelGGL((k_dedup_scatter<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, c->keys, recs, n,
+                           sigs, db.rep, db.nodes, c->cache);
+    }
+    const uint32_t* troots =
+        Q::fors_units > 1 ? reinterpret_cast<const uint32_t*>(base + pl.o_troots) : roots;  // tree roots
+    hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, troots);
     const uint32_t nw = n * Q::d * Q::len;
-    if (pl.keep && pl.dedup)
-      hipLaunchKernelGGL((k_wots_dedup<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs, spill,
-                         db.rep, db.lown);
-    else if (pl.keep)
+    if (pl.keep && pl.dedup) {
+      if constexpr (whole_trees<ID>())
+        hipLaunchKernelGGL((k_wots_dedup<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs,
+                           spill, db.rep, db.lown);
+    } else if (pl.keep)
       hipLaunchKernelGGL((k_wots<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, recs, n, sigs, spill);
     else
       hipLaunchKernelGGL((k_wots_recompute<ID>), dim3((nw + 255) / 256), dim3(256), 0, s, c->keys, recs, n, sigs);
@@ -409,23 +471,23 @@ int enqueue_group(slh_ctx* c, const DevItem* h_items, size_t count, size_t chunk
   return SLH_OK;
 }
 
-int enqueue_all(slh_ctx* c, const size_t per[4], const size_t start[4], const size_t chunk[4], const uint8_t* msgs,
+int enqueue_all(slh_ctx* c, const size_t* per, const size_t* start, const size_t* chunk, const uint8_t* msgs,
                 uint8_t* sigs, hipStream_t s, uint32_t mode, bool timing) {
   int groups = 0;
-  for (int p = 1; p <= 3; p++) groups += per[p] ? 1 : 0;
+  for (int p = 1; p <= kSets; p++) groups += per[p] ? 1 : 0;
   const bool branches = (mode & SLH_MODE_FUSED) && groups > 1;
   if (branches) HIPCHK(c, hipEventRecord(c->fork, s));
-  for (int p = 1; p <= 3 ; p++) {
+  for (int p = 1; p <= kSets; p++) {
     if (!per[p]) continue;
     hipStream_t b = s;
     if (branches) {
       b = c->branch[p];
       HIPCHK(c, hipStreamWaitEvent(b, c->fork, 0));
     }
-    int rc = SLH_OK;
-    if (p == 1) rc = enqueue_group<1>(c, c->staging + start[1], per[1], chunk[1], msgs, sigs, b, mode, timing);
-    if (p == 2) rc = enqueue_group<2>(c, c->staging + start[2], per[2], chunk[2], msgs, sigs, b, mode, timing);
-    if (p == 3) rc = enqueue_group<3>(c, c->staging + start[3], per[3], chunk[3], msgs, sigs, b, mode, timing);
+    const int rc = with_set(uint32_t(p), [&](auto id) {
+      return enqueue_group<decltype(id)::value>(c, c->staging + start[p], per[p], chunk[p], msgs, sigs, b, mode,
+                                                timing);
+    });
     if (rc) return rc;
     if (branches) {
       HIPCHK(c, hipEventRecord(c->join[p], b));
@@ -446,28 +508,36 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
   DevKey* dk = nullptr;
   uint32_t* stage = nullptr;
   uint32_t* root = nullptr;
-  const size_t stage_bytes = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
+  uint32_t* uroots = nullptr;
+  constexpr uint32_t UT = Q::tree_units;  // TREE blocks of the top tree (1 for the fast sets)
+  const size_t stage_bytes = size_t(UT) * Q::len * kLeavesPerBlock * Q::NW * 4;
   hipError_t e = hipMalloc(&dk, sizeof(DevKey));
   if (e == hipSuccess) e = hipMalloc(&stage, stage_bytes);
   if (e == hipSuccess) e = hipMalloc(&root, 32);
+  if (e == hipSuccess) e = hipMalloc(&uroots, size_t(UT) * Q::NW * 4);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     if (dk) (void)hipFree(dk);
     if (stage) (void)hipFree(stage);
+    if (root) (void)hipFree(root);
     return fail(nullptr, SLH_ENOMEM, "keygen device allocation failed");
   }
   uint32_t hroot[8] = {0};
   e = hipMemcpy(dk, &hk, sizeof hk, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_key_midstates, dim3(1), dim3(64), 0, 0, dk, 0u, 1u);
-    hipLaunchKernelGGL((k_tree<ID, kKeygenTree>), dim3(1), dim3(kTreeThreads), 0, 0, dk, nullptr, 1u, nullptr,
-                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr, nullptr, 0u);
+    hipLaunchKernelGGL((k_tree<ID, kKeygenTree>), dim3(UT), dim3(kTreeThreads), 0, 0, dk, nullptr, UT, nullptr,
+                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr, nullptr, 0u, uroots);
+    if constexpr (UT > 1)
+      hipLaunchKernelGGL((k_tree_top<ID, kKeygenTree>), dim3(1), dim3(64), 0, 0, dk, nullptr, 1u, nullptr, 0u, root,
+                         0u, uroots);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpy(hroot, root, Q::n, hipMemcpyDeviceToHost);
   (void)hipFree(dk);
   (void)hipFree(stage);
   (void)hipFree(root);
+  (void)hipFree(uroots);
   if (e != hipSuccess) return hip_fail(nullptr, e, "keygen");
   std::memcpy(sk, seed, 3 * n);
   for (uint32_t i = 0; i < n / 4; i++) {
@@ -482,7 +552,8 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
 }
 
 // Most cached layers per parameter set: at most 2^16 trees per key.
-uint32_t max_cache_layers(uint32_t param) { return param == 3 ? 4u : 6u; }
+// (the small sets' trees are built in units; they are not cached)
+uint32_t max_cache_layers(uint32_t param) { return param >= 4 ? 0u : (param == 3 ? 4u : 6u); }
 
 // Build the cached upper layers of keys [first, first + count) (all of set ID).
 template <int ID>
@@ -526,7 +597,8 @@ int cache_impl(slh_ctx* c, uint32_t first, uint32_t count, uint32_t layers) {
   for (uint32_t t0 = 0; t0 < total && e == hipSuccess; t0 += kMaxBlocks * TPB) {
     const uint32_t n = std::min<uint32_t>(kMaxBlocks * TPB, total - t0);
     hipLaunchKernelGGL((k_tree<ID, kCacheTrees>), dim3((n + TPB - 1) / TPB), dim3(kTreeThreads), 0, 0, c->keys,
-                       nullptr, n, nullptr, stage, nullptr, first, nullptr, nullptr, nullptr, nullptr, nodes, t0);
+                       nullptr, n, nullptr, stage, nullptr, first, nullptr, nullptr, nullptr, nullptr, nodes, t0,
+                       nullptr);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -600,7 +672,7 @@ int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
   if (e == hipSuccess) e = hipMemset(c->dstats, 0, 2 * sizeof(unsigned long long));
   // all streams at the default priority
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
-  for (int p = 1; p <= 3 && e == hipSuccess; p++) {
+  for (int p = 1; p <= kSets && e == hipSuccess; p++) {
     e = hipStreamCreateWithFlags(&c->branch[p], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[p], hipEventDisableTiming);
   }
@@ -608,7 +680,7 @@ int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
     slh_ctx_destroy(c);
     return hip_fail(nullptr, e, "context set-up");
   }
-  for (int p = 1; p <= 3; p++) c->tune[p].fg = fg_default(uint32_t(p));
+  for (int p = 1; p <= kSets; p++) c->tune[p].fg = fg_default(uint32_t(p));
   *out = c;
   return SLH_OK;
 }
@@ -619,7 +691,7 @@ int slh_ctx_destroy(slh_ctx* c) {
   if (c->pending) (void)hipEventSynchronize(c->done);
   (void)hipDeviceSynchronize();
   drop_graphs(c);
-  for (int p = 0; p < 4; p++) {
+  for (int p = 0; p <= kSets; p++) {
     if (c->ws[p]) (void)hipFree(c->ws[p]);
     if (c->branch[p]) (void)hipStreamDestroy(c->branch[p]);
     if (c->join[p]) (void)hipEventDestroy(c->join[p]);
@@ -702,11 +774,11 @@ int slh_ctx_reserve(slh_ctx* c, uint32_t count, uint32_t mode) {
   const uint64_t share = budget_share(c);
   size_t chunk = 0;
   int rc = SLH_OK;
-  for (int p = 1; p <= 3 && !rc; p++) {
+  for (int p = 1; p <= kSets && !rc; p++) {
     if (std::find(c->key_param.begin(), c->key_param.end(), uint32_t(p)) == c->key_param.end()) continue;
-    if (p == 1) rc = prepare_group<1>(c, count, mode, share, &chunk);
-    if (p == 2) rc = prepare_group<2>(c, count, mode, share, &chunk);
-    if (p == 3) rc = prepare_group<3>(c, count, mode, share, &chunk);
+    rc = with_set(uint32_t(p), [&](auto id) {
+      return prepare_group<decltype(id)::value>(c, count, mode, share, &chunk);
+    });
   }
   return rc;
 }
@@ -715,6 +787,7 @@ int slh_ctx_cache_keys(slh_ctx* c, uint32_t first_slot, uint32_t count, uint32_t
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (count == 0 || uint64_t(first_slot) + count > c->nkeys) return fail(c, SLH_EINVAL, "key range outside the table");
   const uint32_t param = c->key_param[first_slot];
+  if (max_cache_layers(param) == 0) return fail(c, SLH_EINVAL, "the small parameter sets have no tree cache");
   if (layers == 0 || layers > max_cache_layers(param))
     return fail(c, SLH_EINVAL, "cached layers must be 1.." + std::to_string(max_cache_layers(param)));
   for (uint32_t i = first_slot; i < first_slot + count; i++) {
@@ -725,7 +798,7 @@ int slh_ctx_cache_keys(slh_ctx* c, uint32_t first_slot, uint32_t count, uint32_t
   switch (param) {
     case 1: return cache_impl<1>(c, first_slot, count, layers);
     case 2: return cache_impl<2>(c, first_slot, count, layers);
-    default: return cache_impl<3>(c, first_slot, count, layers);
+    default: return cache_impl<3>(c, first_slot, count, layers);  // the small sets were rejected above
   }
 }
 
@@ -784,7 +857,7 @@ int sign_impl(slh_ctx* c, const slh_item* items, const uint64_t* rnd, uint32_t c
   // validation, and grouping by parameter set
   std::vector<std::pair<uint64_t, uint64_t>> ranges;
   ranges.reserve(count);
-  size_t per[4] = {0, 0, 0, 0};
+  size_t per[kSets + 1] = {};
   for (uint32_t i = 0; i < count; i++) {
     const slh_item& it = items[i];
     Sizes s;
@@ -819,7 +892,8 @@ int sign_impl(slh_ctx* c, const slh_item* items, const uint64_t* rnd, uint32_t c
     }
     c->staging_cap = count;
   }
-  size_t start[4] = {0, 0, per[1], per[1] + per[2]}, fill[4] = {0, 0, 0, 0};
+  size_t start[kSets + 1] = {}, fill[kSets + 1] = {};
+  for (int p = 2; p <= kSets; p++) start[p] = start[p - 1] + per[p - 1];
   for (uint32_t i = 0; i < count; i++) {
     const slh_item& it = items[i];
     DevItem& d = c->staging[start[it.param] + fill[it.param]++];
@@ -830,11 +904,13 @@ int sign_impl(slh_ctx* c, const slh_item* items, const uint64_t* rnd, uint32_t c
   // working memory: the budget is shared by the parameter sets the context
   // holds keys of, so that each set's share does not depend on the mix
   const uint64_t share = budget_share(c);
-  size_t chunk[4] = {0, 0, 0, 0};
+  size_t chunk[kSets + 1] = {};
   int rc = SLH_OK;
-  if (per[1] && !rc) rc = prepare_group<1>(c, per[1], mode, share, &chunk[1]);
-  if (per[2] && !rc) rc = prepare_group<2>(c, per[2], mode, share, &chunk[2]);
-  if (per[3] && !rc) rc = prepare_group<3>(c, per[3], mode, share, &chunk[3]);
+  for (int p = 1; p <= kSets && !rc; p++)
+    if (per[p])
+      rc = with_set(uint32_t(p), [&](auto id) {
+        return prepare_group<decltype(id)::value>(c, per[p], mode, share, &chunk[p]);
+      });
   if (rc) return rc;
   if (!graph) {
     rc = enqueue_all(c, per, start, chunk, msgs, sigs, s, mode, true);
@@ -842,7 +918,7 @@ int sign_impl(slh_ctx* c, const slh_item* items, const uint64_t* rnd, uint32_t c
   } else {
     GraphKey key;
     std::memset(&key, 0, sizeof key);
-    for (int p = 1; p <= 3; p++) {
+    for (int p = 1; p <= kSets; p++) {
       key.n[p] = per[p];
       key.ws[p] = c->ws[p];
       key.ws_bytes[p] = c->ws_bytes[p];
@@ -1034,7 +1110,7 @@ int slh_verify_batch(slh_ctx* c, const slh_verify_item* items, uint32_t count, c
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (count == 0) return SLH_OK;
   if (!items || !sigs || !pks || !results) return fail(c, SLH_EINVAL, "null argument");
-  size_t per[4] = {0, 0, 0, 0};
+  size_t per[kSets + 1] = {};
   for (uint32_t i = 0; i < count; i++) {
     const slh_verify_item& it = items[i];
     Sizes s;
@@ -1071,22 +1147,23 @@ int slh_verify_batch(slh_ctx* c, const slh_verify_item* items, uint32_t count, c
     }
     c->vbuf_bytes = need;
   }
-  size_t start[4] = {0, 0, per[1], per[1] + per[2]}, fill[4] = {0, 0, 0, 0};
+  size_t start[kSets + 1] = {}, fill[kSets + 1] = {};
+  for (int p = 2; p <= kSets; p++) start[p] = start[p - 1] + per[p - 1];
   for (uint32_t i = 0; i < count; i++) {
     const slh_verify_item& it = items[i];
     c->vstage[start[it.param] + fill[it.param]++] = VerifyItem{it.msg_off, it.msg_len, it.sig_off, it.pk_off, i};
   }
   VerifyItem* d = reinterpret_cast<VerifyItem*>(c->vbuf);
   HIPCHK(c, hipMemcpyAsync(d, c->vstage, size_t(count) * sizeof(VerifyItem), hipMemcpyHostToDevice, s));
-  if (per[1])
-    hipLaunchKernelGGL((k_verify<1>), dim3(uint32_t((per[1] + kVerifySigs - 1) / kVerifySigs)),
-                       dim3(kVerifyThreads), 0, s, d + start[1], uint32_t(per[1]), msgs, sigs, pks, results);
-  if (per[2])
-    hipLaunchKernelGGL((k_verify<2>), dim3(uint32_t((per[2] + kVerifySigs - 1) / kVerifySigs)),
-                       dim3(kVerifyThreads), 0, s, d + start[2], uint32_t(per[2]), msgs, sigs, pks, results);
-  if (per[3])
-    hipLaunchKernelGGL((k_verify<3>), dim3(uint32_t((per[3] + kVerifySigs - 1) / kVerifySigs)),
-                       dim3(kVerifyThreads), 0, s, d + start[3], uint32_t(per[3]), msgs, sigs, pks, results);
+  for (int p = 1; p <= kSets; p++) {
+    if (!per[p]) continue;
+    with_set(uint32_t(p), [&](auto id) {
+      constexpr int ID = decltype(id)::value;
+      hipLaunchKernelGGL((k_verify<ID>), dim3(uint32_t((per[p] + kVerifySigs - 1) / kVerifySigs)),
+                         dim3(kVerifyThreads), 0, s, d + start[p], uint32_t(per[p]), msgs, sigs, pks, results);
+      return 0;
+    });
+  }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->done, s));
   c->pending = true;
@@ -1120,12 +1197,9 @@ int slh_ctx_get_tuning(const slh_ctx* c, uint32_t param, slh_tuning* t) {
 
 int slh_keygen(uint32_t param, const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
   if (!seed || !pk || !sk) return fail(nullptr, SLH_EINVAL, "null pointer");
-  switch (param) {
-    case SLH_SHA2_128F: return keygen_impl<1>(seed, pk, sk);
-    case SLH_SHA2_192F: return keygen_impl<2>(seed, pk, sk);
-    case SLH_SHA2_256F: return keygen_impl<3>(seed, pk, sk);
-    default: return fail(nullptr, SLH_EINVAL, "unknown parameter set");
-  }
+  Sizes sz;
+  if (!sizes_of(param, &sz)) return fail(nullptr, SLH_EINVAL, "unknown parameter set");
+  return with_set(param, [&](auto id) { return keygen_impl<decltype(id)::value>(seed, pk, sk); });
 }
 
 int slh_verify(uint32_t param, const uint8_t* msg, size_t msg_len, const uint8_t* sig, size_t sig_len,
@@ -1134,11 +1208,7 @@ int slh_verify(uint32_t param, const uint8_t* msg, size_t msg_len, const uint8_t
   if (!sizes_of(param, &s)) return fail(nullptr, SLH_EINVAL, "unknown parameter set");
   if (!sig || !pk || (msg_len && !msg)) return fail(nullptr, SLH_EINVAL, "null pointer");
   if (sig_len != s.sig) return 0;
-  switch (param) {
-    case SLH_SHA2_128F: return verify_impl<1>(msg, msg_len, sig, pk);
-    case SLH_SHA2_192F: return verify_impl<2>(msg, msg_len, sig, pk);
-    default: return verify_impl<3>(msg, msg_len, sig, pk);
-  }
+  return with_set(param, [&](auto id) { return verify_impl<decltype(id)::value>(msg, msg_len, sig, pk); });
 }
 
 }  // extern "C"

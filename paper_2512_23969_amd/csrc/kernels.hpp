@@ -302,29 +302,32 @@ __global__ __launch_bounds__(64) void k_prelude(const DevKey* __restrict__ keys,
 // once all its trees are done (paper Section II-A "FORS Signature"; the
 // paper's FORS fusion, Section III-B, groups trees per thread block for the
 // same reason: more independent nodes per synchronisation).
+// A FORS unit is a whole tree (f sets) or a subtree of 2^12 leaves (192s,
+// 256s); its root is a FORS root or a level-12 node for k_fors_top.
 template <int ID>
 struct ForsShape {
-  static constexpr int PAIRS = 1 << (P<ID>::a - 1);  // level-1 nodes per tree
-  // default trees per workgroup: 8 x 32 pairs (128f), 8 x 128 (192f), 4 x 256 (256f)
-  static constexpr int FG = ID == 3 ? 4 : 8;
+  static constexpr int PAIRS = 1 << (P<ID>::unit_a - 1);  // level-1 nodes per unit
+  static constexpr int UNITS = P<ID>::fors_units;          // units per FORS tree
 };
 
-// One group of FG trees (flat tree ids group*FG ...).  `node` is LDS of
-// FG * PAIRS * NW words.  All threads of the workgroup must call it.
+// One group of FG units (flat unit ids group*FG ...; unit u of tree ft is
+// ft * UNITS + u).  `node` is LDS of FG * PAIRS * NW words.  All threads of
+// the workgroup must call it.
 template <int ID, int FG>
 __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, const WorkRec* __restrict__ recs,
-                           uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ roots, uint32_t group,
+                           uint32_t nunits, uint8_t* sigs, uint32_t* __restrict__ roots, uint32_t group,
                            uint32_t* node) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, A = Q::a, KT = Q::k;
+  constexpr int NW = Q::NW, A = Q::a, KT = Q::k, AU = Q::unit_a, UNITS = ForsShape<ID>::UNITS;
   constexpr int PAIRS = ForsShape<ID>::PAIRS;
-  const uint32_t ft0 = group * FG;
+  const uint32_t fu0 = group * FG;
 
   // pair phase
   for (int q = threadIdx.x; q < FG * PAIRS; q += kForsThreads) {
-    const uint32_t ft = ft0 + q / PAIRS;
-    if (ft >= ntrees) break;  // q only grows, so the rest of this lane's tasks are out too
-    const uint32_t j = q % PAIRS;
+    const uint32_t fu = fu0 + q / PAIRS;
+    if (fu >= nunits) break;  // q only grows, so the rest of this lane's tasks are out too
+    const uint32_t ft = fu / UNITS, u = fu % UNITS;
+    const uint32_t j = (u << (AU - 1)) + q % PAIRS;  // pair index within the tree
     const uint32_t msg = ft / KT, t = ft - msg * KT;
     const WorkRec& W = recs[msg];
     const DevKey& K = keys[W.key_slot];
@@ -365,12 +368,13 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
   __syncthreads();
   // level phase
 #pragma unroll 1
-  for (int z = 2; z <= A; z++) {
-    const int per = 1 << (A - z);  // nodes of level z per tree
+  for (int z = 2; z <= AU; z++) {
+    const int per = 1 << (AU - z);  // nodes of level z per unit
     for (int q = threadIdx.x; q < FG * per; q += kForsThreads) {
-      const uint32_t ft = ft0 + q / per;
-      if (ft >= ntrees) break;
-      const uint32_t i = q % per;
+      const uint32_t fu = fu0 + q / per;
+      if (fu >= nunits) break;
+      const uint32_t ft = fu / UNITS, u = fu % UNITS;
+      const uint32_t i = (u << (AU - z)) + q % per;  // node index within the tree's level z
       const uint32_t msg = ft / KT, t = ft - msg * KT;
       const WorkRec& W = recs[msg];
       const DevKey& K = keys[W.key_slot];
@@ -383,7 +387,7 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
       thH<ID>(K, make_adrs(0, W.idx_tree, A_FORS_TREE, W.idx_leaf, z, (t << (A - z)) + i), lr, out);
       if (z < A && (((idx >> z) ^ 1u) == i))
         store_be<NW>(sigs + W.sig_off + Q::n + t * (A + 1) * Q::n + (1 + z) * Q::n, out);  // auth[z]
-      if (z == A) store_words<NW>(roots + size_t(ft) * NW, out);
+      if (z == AU) store_words<NW>(roots + size_t(fu) * NW, out);
       else store_words<NW>(&node[ls * NW], out);
     }
     __syncthreads();
@@ -392,10 +396,43 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
 
 template <int ID, int FG>
 __global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict__ keys,
-                                                       const WorkRec* __restrict__ recs, uint32_t ntrees,
+                                                       const WorkRec* __restrict__ recs, uint32_t nunits,
                                                        uint8_t* sigs, uint32_t* __restrict__ roots) {
   __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * P<ID>::NW];
-  fors_group<ID, FG>(keys, recs, ntrees, sigs, roots, blockIdx.x, node);
+  fors_group<ID, FG>(keys, recs, nunits, sigs, roots, blockIdx.x, node);
+}
+
+// FORS trees built in units: one lane per tree combines its unit roots
+// (level unit_a) up to the tree root, writing the authentication nodes of
+// those upper levels; tree roots go to `troots` for k_fors_pk.
+template <int ID>
+__global__ void k_fors_top(const DevKey* __restrict__ keys, const WorkRec* __restrict__ recs, uint32_t ntrees,
+                           uint8_t* sigs, const uint32_t* __restrict__ uroots, uint32_t* __restrict__ troots) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, A = Q::a, KT = Q::k, AU = Q::unit_a, UNITS = Q::fors_units;
+  const uint32_t ft = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ft >= ntrees) return;
+  const uint32_t msg = ft / KT, t = ft - msg * KT;
+  const WorkRec& W = recs[msg];
+  const DevKey& K = keys[W.key_slot];
+  const uint32_t idx = W.indices[t];
+  uint32_t lvl[UNITS * NW];
+#pragma unroll
+  for (int w = 0; w < UNITS * NW; w++) lvl[w] = uroots[size_t(ft) * UNITS * NW + w];
+#pragma unroll
+  for (int z = AU + 1; z <= A; z++) {
+    const int cnt = 1 << (A - z);  // nodes of level z in this tree
+#pragma unroll
+    for (int i = 0; i < cnt; i++) {
+      uint32_t out[NW];
+      thH<ID>(K, make_adrs(0, W.idx_tree, A_FORS_TREE, W.idx_leaf, z, (t << (A - z)) + i), &lvl[2 * i * NW], out);
+#pragma unroll
+      for (int u = 0; u < NW; u++) lvl[i * NW + u] = out[u];
+      if (z < A && (((idx >> z) ^ 1u) == uint32_t(i)))
+        store_be<NW>(sigs + W.sig_off + Q::n + t * (A + 1) * Q::n + (1 + z) * Q::n, out);  // auth[z]
+    }
+  }
+  store_words<NW>(troots + size_t(ft) * NW, lvl);
 }
 
 // FORS public key T_k(FORS_ROOTS address, roots) of each message, one lane
@@ -479,7 +516,7 @@ __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t
 // (len - w0) / 3 gives 8, 11 and 14.
 template <int ID>
 struct TreeSplit {
-  static constexpr int wave0 = ID == 1 ? 8 : (ID == 2 ? 11 : 14);
+  static constexpr int wave0 = P<ID>::len == 35 ? 8 : (P<ID>::len == 51 ? 11 : 14);
 };
 
 // What a TREE block works on: the trees of a batch's signatures, the top tree
@@ -548,12 +585,15 @@ __device__ __forceinline__ TreeJob tree_job(const DevKey* __restrict__ keys, Wor
 // With dedup, lown[ft * leaves + leaf] names the (message, layer) pair whose
 // kept-chain area receives the chains of that leaf of tree ft (~0: no pair
 // signs with that leaf).
-// Without a list, slot i is tree first + i.
+// Without a list, slot i is tree first + i.  For trees built in units
+// (XMSS trees above 64 leaves), slots are units (unit u of tree ft is
+// ft * tree_units + u) and each unit's root goes to uroots.
 struct TreeList {
   const uint32_t* ulist;
   const uint32_t* ucount;
   const uint32_t* lown;
   uint32_t first;
+  uint32_t* uroots = nullptr;
   __device__ __forceinline__ uint32_t count(uint32_t ntrees) const { return ucount ? *ucount : ntrees; }
   __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : first + i; }
 };
@@ -564,21 +604,22 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
                                             uint32_t block, TreeList tl = TreeList{nullptr, nullptr, nullptr, 0u}) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, LV = Q::leaves;
+  constexpr int NW = Q::NW, LEN = Q::len, LV = 1 << Q::unit_hp, UT = Q::tree_units;
   constexpr int TPB = kLeavesPerBlock / LV;
   constexpr int W0 = TreeSplit<ID>::wave0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tree0 = block * TPB;
-  const uint32_t lt = lane / LV, kp = lane % LV;
+  const uint32_t lt = lane / LV;
   if (tree0 + lt >= tl.count(ntrees)) return;
-  const uint32_t ft = tl.at(tree0 + lt);
+  const uint32_t fu = tl.at(tree0 + lt), ft = fu / UT;
+  const uint32_t kp = ((fu % UT) << Q::unit_hp) + lane % LV;  // leaf within the tree
   const TreeJob J = tree_job<ID, KIND>(keys, recs, sigs, spill, key_slot, root_out, ft);
   uint32_t mid[8], sks[NW];
   load_words<8>(J.key->mid256, mid);
   load_words<NW>(J.key->sk_seed, sks);
   uint32_t* keep = nullptr;
   if (tl.lown) {
-    const uint32_t o = tl.lown[size_t(ft) * LV + kp];
+    const uint32_t o = tl.lown[size_t(ft) * Q::leaves + kp];
     if (spill && o != 0xffffffffu) keep = spill + size_t(o) * LEN * 16 * NW;
   } else if (J.spill && int32_t(kp) == J.sign_leaf) {
     keep = J.spill;
@@ -607,14 +648,15 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
                                             uint32_t block, TreeList tl = TreeList{nullptr, nullptr, nullptr, 0u},
                                             uint32_t* __restrict__ nodes = nullptr) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, HP = Q::hp, LV = Q::leaves;
+  constexpr int NW = Q::NW, LEN = Q::len, UH = Q::unit_hp, LV = 1 << UH, UT = Q::tree_units;
   constexpr int TPB = kLeavesPerBlock / LV;
   const int lane = threadIdx.x & 63;
   const uint32_t tree0 = block * TPB;
-  const uint32_t lt = lane / LV, kp = lane % LV;
+  const uint32_t lt = lane / LV, kl = lane % LV;  // leaf within the unit
   const bool valid = tree0 + lt < tl.count(ntrees);
-  const uint32_t ft = valid ? tl.at(tree0 + lt) : 0u;
-  uint32_t* tn = nodes ? nodes + size_t(ft) * TreeNodes<ID>::count * NW : nullptr;
+  const uint32_t fu = valid ? tl.at(tree0 + lt) : 0u, ft = fu / UT;
+  const uint32_t kp = ((fu % UT) << UH) + kl;  // leaf within the tree
+  uint32_t* tn = (UT == 1 && nodes) ? nodes + size_t(ft) * TreeNodes<ID>::count * NW : nullptr;
   uint32_t v[NW];
   TreeJob J{};
   if (valid) {
@@ -629,15 +671,15 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
     for (int u = 0; u < NW; u++) v[u] = 0;
   }
 #pragma unroll 1
-  for (int z = 1; z <= HP; z++) {
+  for (int z = 1; z <= UH; z++) {
     const uint32_t span = 1u << (z - 1);
     // auth node of level z-1
-    if (valid && J.sig_xmss && (kp & (span - 1)) == 0) {
+    if (valid && J.sig_xmss && (kl & (span - 1)) == 0) {
       const uint32_t i = kp >> (z - 1);
       if (i == ((uint32_t(J.sign_leaf) >> (z - 1)) ^ 1u))
         store_be<NW>(J.sig_xmss + (LEN + z - 1) * Q::n, v);
     }
-    if (valid && tn && (kp & (span - 1)) == 0)
+    if (valid && tn && (kl & (span - 1)) == 0)
       store_words<NW>(tn + (TreeNodes<ID>::off(z - 1) + (kp >> (z - 1))) * NW, v);
     uint32_t lr[2 * NW];
 #pragma unroll
@@ -645,12 +687,16 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
       lr[u] = v[u];
       lr[NW + u] = __shfl_down(v[u], span, 64);
     }
-    if (valid && (kp & ((span << 1) - 1)) == 0) {
+    if (valid && (kl & ((span << 1) - 1)) == 0) {
       thH<ID>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_TREE, 0, z, kp >> z), lr, v);
     }
   }
-  if (valid && kp == 0 && J.root_out) store_words<NW>(J.root_out, v);
-  if (valid && kp == 0 && tn) store_words<NW>(tn + TreeNodes<ID>::off(HP) * NW, v);
+  if constexpr (UT == 1) {
+    if (valid && kl == 0 && J.root_out) store_words<NW>(J.root_out, v);
+    if (valid && kl == 0 && tn) store_words<NW>(tn + TreeNodes<ID>::off(UH) * NW, v);
+  } else {
+    if (valid && kl == 0) store_words<NW>(tl.uroots + size_t(fu) * NW, v);  // level-UH node
+  }
 }
 
 template <int ID, int KIND>
@@ -660,14 +706,50 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
                                                        uint32_t* __restrict__ spill,
                                                        uint32_t key_slot, uint32_t* root_out,
                                                        const uint32_t* ulist, const uint32_t* ucount,
-                                                       const uint32_t* lown, uint32_t* nodes, uint32_t first) {
-  const TreeList tl{ulist, ucount, lown, first};
-  if (blockIdx.x * (kLeavesPerBlock / P<ID>::leaves) >= tl.count(ntrees)) return;  // beyond the distinct trees
+                                                       const uint32_t* lown, uint32_t* nodes, uint32_t first,
+                                                       uint32_t* uroots) {
+  const TreeList tl{ulist, ucount, lown, first, uroots};
+  if (blockIdx.x * (kLeavesPerBlock >> P<ID>::unit_hp) >= tl.count(ntrees)) return;  // beyond the distinct trees
   uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
   tree_chains<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl);
   __syncthreads();
   if ((threadIdx.x >> 6) == 0)
     tree_finish<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
+}
+
+// XMSS trees built in units (the small sets): one lane per tree combines the
+// unit roots (level unit_hp) up to the root, writing the authentication
+// nodes of those levels for the signing leaf (FIPS 205 Algorithms 9-10).
+template <int ID, int KIND>
+__global__ void k_tree_top(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t ntrees,
+                           uint8_t* sigs, uint32_t key_slot, uint32_t* root_out, uint32_t first,
+                           const uint32_t* __restrict__ uroots) {
+  using Q = P<ID>;
+  constexpr int NW = Q::NW, LEN = Q::len, UH = Q::unit_hp, HP = Q::hp, UT = Q::tree_units;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntrees) return;
+  const uint32_t ft = first + i;
+  const TreeJob J = tree_job<ID, KIND>(keys, recs, sigs, nullptr, key_slot, root_out, ft);
+  uint32_t lvl[UT * NW];
+#pragma unroll
+  for (int w = 0; w < UT * NW; w++) lvl[w] = uroots[size_t(ft) * UT * NW + w];
+#pragma unroll
+  for (int z = UH + 1; z <= HP; z++) {
+    const int cnt = 1 << (HP - z);  // nodes of level z
+    // auth node of level z-1: the sibling of the signing leaf's ancestor
+#pragma unroll
+    for (int q = 0; q < 2 * cnt; q++)
+      if (J.sig_xmss && uint32_t(q) == ((uint32_t(J.sign_leaf) >> (z - 1)) ^ 1u))
+        store_be<NW>(J.sig_xmss + (LEN + z - 1) * Q::n, &lvl[q * NW]);
+#pragma unroll
+    for (int q = 0; q < cnt; q++) {
+      uint32_t out[NW];
+      thH<ID>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_TREE, 0, z, q), &lvl[2 * q * NW], out);
+#pragma unroll
+      for (int u = 0; u < NW; u++) lvl[q * NW + u] = out[u];
+    }
+  }
+  if (J.root_out) store_words<NW>(J.root_out, lvl);
 }
 
 // ------------------------------------------------------------------ fused

@@ -42,6 +42,25 @@ struct Prm<3> {
   static constexpr bool wide = true;
 };
 
+// SHA2-128s: n=16, h=63, d=7, h'=9, a=12, k=14, w=16 (FIPS 205 Table 2)
+template <>
+struct Prm<4> {
+  static constexpr int n = 16, h = 63, d = 7, hp = 9, a = 12, k = 14, len1 = 32, len2 = 3, m = 30;
+  static constexpr bool wide = false;
+};
+// SHA2-192s: n=24, h=63, d=7, h'=9, a=14, k=17, w=16
+template <>
+struct Prm<5> {
+  static constexpr int n = 24, h = 63, d = 7, hp = 9, a = 14, k = 17, len1 = 48, len2 = 3, m = 39;
+  static constexpr bool wide = true;
+};
+// SHA2-256s: n=32, h=64, d=8, h'=8, a=14, k=22, w=16
+template <>
+struct Prm<6> {
+  static constexpr int n = 32, h = 64, d = 8, hp = 8, a = 14, k = 22, len1 = 64, len2 = 3, m = 47;
+  static constexpr bool wide = true;
+};
+
 template <int ID>
 struct P : Prm<ID> {
   using B = Prm<ID>;
@@ -56,6 +75,13 @@ struct P : Prm<ID> {
   static constexpr int tree_bits = B::h - B::hp;
   static constexpr int tree_bytes = (tree_bits + 7) / 8;
   static constexpr int leaf_bytes = (B::hp + 7) / 8;
+  // Trees taller than one wave's 64 leaves (the small sets) are built in
+  // units of 64 leaves (height 6) whose roots a second step combines; FORS
+  // trees above 2^12 leaves likewise in units of 2^12 leaves.
+  static constexpr int unit_hp = B::hp < 6 ? B::hp : 6;          // height of a TREE unit
+  static constexpr int tree_units = 1 << (B::hp - unit_hp);      // units per XMSS tree
+  static constexpr int unit_a = B::a < 12 ? B::a : 12;           // height of a FORS unit
+  static constexpr int fors_units = 1 << (B::a - unit_a);        // units per FORS tree
 };
 
 // Address types (FIPS 205 Section 4.2)

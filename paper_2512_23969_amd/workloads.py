@@ -15,8 +15,8 @@ from __future__ import annotations
 import numpy as np
 
 # parameter-set id -> security parameter n in bytes (the paper's Table 1)
-N_OF = {1: 16, 2: 24, 3: 32}
-NAME_OF = {1: "128f", 2: "192f", 3: "256f"}
+N_OF = {1: 16, 2: 24, 3: 32, 4: 16, 5: 24, 6: 32}
+NAME_OF = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s"}
 ID_OF = {v: k for k, v in NAME_OF.items()}
 
 
@@ -51,6 +51,10 @@ CONFIGS = {
     "c2_128f_4096": dict(cfg=2, param=1, batch=4096, keys=1, length=32),
     "c3_192f_4096": dict(cfg=3, param=2, batch=4096, keys=1, length=32),
     "c4_256f_4096x64": dict(cfg=4, param=3, batch=4096, keys=64, length=32),
+    # the small sets (not in the paper): one key, 1024 x 32-byte messages
+    "s1_128s_1024": dict(cfg=11, param=4, batch=1024, keys=1, length=32),
+    "s2_192s_1024": dict(cfg=12, param=5, batch=1024, keys=1, length=32),
+    "s3_256s_1024": dict(cfg=13, param=6, batch=1024, keys=1, length=32),
 }
 
 

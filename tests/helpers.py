@@ -6,7 +6,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 import oracle
 
-NAMES = {1: "128f", 2: "192f", 3: "256f"}
+NAMES = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s"}
 
 
 def host_threads() -> int:
