@@ -22,6 +22,9 @@ WORKLOADS = {
     "c2_128f_4096": "SPHINCS+-SHA2-128f, 1 key, 4096 x 32-byte messages",
     "c3_192f_4096": "SPHINCS+-SHA2-192f, 1 key, 4096 x 32-byte messages",
     "c4_256f_4096x64": "SPHINCS+-SHA2-256f, 64 keys, 4096 x 32-byte messages",
+    "s1_128s_1024": "SPHINCS+-SHA2-128s, 1 key, 1024 x 32-byte messages",
+    "s2_192s_1024": "SPHINCS+-SHA2-192s, 1 key, 1024 x 32-byte messages",
+    "s3_256s_1024": "SPHINCS+-SHA2-256s, 1 key, 1024 x 32-byte messages",
 }
 
 
@@ -379,11 +382,14 @@ def main():
         line["dedup"] = {"trees_per_step": res["dedup"][0], "distinct_trees_per_step": res["dedup"][1]}
     if args.all:
         # every batch-4096 workload in the plain per-phase path and in the
-        # batched modes (fused persistent kernel; hipGraph-captured pipeline)
+        # batched modes (fused persistent kernel; hipGraph-captured pipeline;
+        # tree dedup), and the small sets at batch 1024
         extra = {}
         steps_c = max(3, args.steps // 2)
-        for name in ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64"):
-            for mode in ("plain", "fused", "graph", "dedup", "fused-dedup"):
+        for name in ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64", "s1_128s_1024", "s2_192s_1024",
+                     "s3_256s_1024"):
+            # the small sets take the per-phase path in every mode
+            for mode in (("plain",) if name.startswith("s") else ("plain", "fused", "graph", "dedup", "fused-dedup")):
                 if name == args.workload and mode == res["mode"]:
                     continue
                 log("bench: workload", name, mode)
