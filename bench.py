@@ -164,9 +164,9 @@ def cpu_baseline(name, workloads, seconds=15.0):
 # summaries are in profiles/.  Absent where not measured for the current
 # kernel.
 TRAFFIC = {  # (param, kernel) -> bytes per launch
-    (1, "k_fused"): (194784 * 2 + 1214190) * 1024,
-    (2, "k_tree"): (433176 * 2 + 2611719) * 1024,
-    (3, "k_tree"): (1172797 * 2 + 4684233) * 1024,
+    (1, "k_fused"): (195083 * 2 + 1214199) * 1024,
+    (2, "k_tree"): (433164 * 2 + 2611460) * 1024,
+    (3, "k_tree"): (1172762 * 2 + 4684838) * 1024,
 }
 
 
