@@ -16,7 +16,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-PARAM_IDS = {"128f": 1, "192f": 2, "256f": 3, "128s": 4, "192s": 5, "256s": 6}
+PARAM_IDS = {"128f": 1, "192f": 2, "256f": 3, "128s": 4, "192s": 5, "256s": 6,
+             "shake-128f": 7, "shake-192f": 8, "shake-256f": 9, "shake-128s": 10, "shake-192s": 11,
+             "shake-256s": 12}
 
 
 def build(force: bool = True) -> str:
@@ -32,7 +34,7 @@ def build(force: bool = True) -> str:
 
 class or_params(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int) for f in
-                ("n", "h", "d", "hp", "a", "k", "lg_w", "len1", "len2", "len", "m", "wide")]
+                ("n", "h", "d", "hp", "a", "k", "lg_w", "len1", "len2", "len", "m", "wide", "shake")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -52,7 +54,8 @@ def lib():
             L.or_params_custom.argtypes = [ctypes.c_int] * 5 + [P]
             L.or_sig_bytes.argtypes = [P]
             L.or_sig_bytes.restype = sz
-            for fn in ("or_sha256", "or_sha512"):
+            L.or_shake256.argtypes = [u8p, sz, ctypes.c_void_p, sz]
+            for fn in ("or_sha256", "or_sha512", "or_sha3_256"):
                 getattr(L, fn).argtypes = [u8p, sz, ctypes.c_void_p]
             for fn in ("or_hmac_sha256", "or_hmac_sha512"):
                 getattr(L, fn).argtypes = [u8p, sz, u8p, sz, ctypes.c_void_p]
@@ -117,6 +120,18 @@ def sig_bytes(p) -> int:
 def sha256(b: bytes) -> bytes:
     out = ctypes.create_string_buffer(32)
     lib().or_sha256(b, len(b), out)
+    return out.raw
+
+
+def shake256(b: bytes, outlen: int) -> bytes:
+    out = ctypes.create_string_buffer(max(1, outlen))
+    lib().or_shake256(b, len(b), out, outlen)
+    return out.raw[:outlen]
+
+
+def sha3_256(b: bytes) -> bytes:
+    out = ctypes.create_string_buffer(32)
+    lib().or_sha3_256(b, len(b), out)
     return out.raw
 
 
@@ -312,7 +327,7 @@ def verify_ext(p, msg: bytes, sig: bytes, pk: bytes, ctx: bytes = b"", ph: int =
     return rc == 1
 
 
-COUNTER_NAMES = ("F", "PRF", "H", "T", "sha256_blocks", "sha512_blocks", "PRF_msg", "H_msg")
+COUNTER_NAMES = ("F", "PRF", "H", "T", "sha256_blocks", "sha512_blocks", "PRF_msg", "H_msg", "keccak_f")
 
 
 def counters_reset():
@@ -320,7 +335,7 @@ def counters_reset():
 
 
 def counters():
-    out = (ctypes.c_uint64 * 8)()
+    out = (ctypes.c_uint64 * len(COUNTER_NAMES))()
     lib().or_counters_get(out)
     return dict(zip(COUNTER_NAMES, list(out)))
 

@@ -21,7 +21,7 @@
 /* Counters (per thread, so that a multi-threaded timing run is race free).  */
 /* ------------------------------------------------------------------------ */
 static __thread uint64_t g_cnt[OR_NCOUNTERS];
-enum { C_F = 0, C_PRF, C_H, C_T, C_SHA256_BLK, C_SHA512_BLK, C_PRFMSG, C_HMSG };
+enum { C_F = 0, C_PRF, C_H, C_T, C_SHA256_BLK, C_SHA512_BLK, C_PRFMSG, C_HMSG, C_KECCAK };
 
 void or_counters_reset(void) { memset(g_cnt, 0, sizeof g_cnt); }
 void or_counters_get(uint64_t out[OR_NCOUNTERS]) { memcpy(out, g_cnt, sizeof g_cnt); }
@@ -334,13 +334,144 @@ int or_params_get(int id, or_params *p)
     case 4: return or_params_custom(16, 63, 7, 12, 14, p);  /* SHA2-128s */
     case 5: return or_params_custom(24, 63, 7, 14, 17, p);  /* SHA2-192s */
     case 6: return or_params_custom(32, 64, 8, 14, 22, p);  /* SHA2-256s */
-    default: return -1;
+    default:
+        /* the SHAKE sets share the shapes of their SHA2 counterparts */
+        if (id >= 7 && id <= 12 && or_params_get(id - 6, p) == 0) {
+            p->shake = 1;
+            p->wide = 0;
+            return 0;
+        }
+        return -1;
     }
 }
 
 size_t or_sig_bytes(const or_params *p)
 {
     return (size_t)p->n * (1 + (size_t)p->k * (p->a + 1) + p->h + (size_t)p->d * p->len);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Keccak-f[1600] and the SHAKE256 / SHA3-256 sponges (FIPS 202).            */
+/* The state is 25 lanes A[x + 5 y] of 64 bits; byte i of the sponge is byte */
+/* i % 8 (little-endian) of lane i / 8.  The round constants and rotation    */
+/* offsets are computed from their definitions (Algorithms 5 and 2).         */
+/* ------------------------------------------------------------------------ */
+static uint64_t g_keccak_rc[24];
+static int g_keccak_rho[25];
+static int g_keccak_ready;
+static void keccak_init_tables(void);
+/* filled once when the library is loaded, before any thread can use them */
+__attribute__((constructor)) static void keccak_tables_at_load(void) { keccak_init_tables(); }
+
+/* rc(t) of FIPS 202 Algorithm 5: an LFSR over GF(2)[x] / (x^8 + x^6 + x^5 + x^4 + 1) */
+static int keccak_rc_bit(int t)
+{
+    if (t % 255 == 0) return 1;
+    unsigned r = 1; /* R[0] is bit 0 */
+    for (int i = 1; i <= t % 255; i++) {
+        r <<= 1;                      /* R = 0 || R */
+        if (r & 0x100) r ^= 0x171;    /* R[0], R[4], R[5], R[6] ^= R[8]; truncate to 8 bits */
+    }
+    return r & 1;
+}
+
+static void keccak_init_tables(void)
+{
+    if (g_keccak_ready) return;
+    for (int ir = 0; ir < 24; ir++) {
+        uint64_t rc = 0;
+        for (int j = 0; j <= 6; j++)
+            if (keccak_rc_bit(j + 7 * ir)) rc |= (uint64_t)1 << ((1 << j) - 1);
+        g_keccak_rc[ir] = rc;
+    }
+    g_keccak_rho[0] = 0;
+    int x = 1, y = 0;
+    for (int t = 0; t < 24; t++) {  /* Algorithm 2 (rho) */
+        g_keccak_rho[x + 5 * y] = ((t + 1) * (t + 2) / 2) % 64;
+        int nx = y, ny = (2 * x + 3 * y) % 5;
+        x = nx;
+        y = ny;
+    }
+    g_keccak_ready = 1;
+}
+
+static uint64_t rotl64(uint64_t v, int r) { return r ? (v << r) | (v >> (64 - r)) : v; }
+
+static void keccak_f1600(uint64_t A[25])
+{
+    g_cnt[C_KECCAK]++;
+    keccak_init_tables();
+    for (int ir = 0; ir < 24; ir++) {
+        uint64_t C[5], D[5], B[25];
+        for (int x = 0; x < 5; x++) C[x] = A[x] ^ A[x + 5] ^ A[x + 10] ^ A[x + 15] ^ A[x + 20];   /* theta */
+        for (int x = 0; x < 5; x++) D[x] = C[(x + 4) % 5] ^ rotl64(C[(x + 1) % 5], 1);
+        for (int i = 0; i < 25; i++) A[i] ^= D[i % 5];
+        for (int x = 0; x < 5; x++)                                                           /* rho, pi */
+            for (int y = 0; y < 5; y++) B[y + 5 * ((2 * x + 3 * y) % 5)] = rotl64(A[x + 5 * y], g_keccak_rho[x + 5 * y]);
+        for (int y = 0; y < 5; y++)                                                           /* chi */
+            for (int x = 0; x < 5; x++)
+                A[x + 5 * y] = B[x + 5 * y] ^ (~B[(x + 1) % 5 + 5 * y] & B[(x + 2) % 5 + 5 * y]);
+        A[0] ^= g_keccak_rc[ir];                                                              /* iota */
+    }
+}
+
+typedef struct {
+    uint64_t A[25];
+    size_t rate, pos;
+} sponge_ctx;
+
+static void sponge_init(sponge_ctx *c, size_t rate)
+{
+    memset(c, 0, sizeof *c);
+    c->rate = rate;
+}
+static void sponge_byte(sponge_ctx *c, size_t i, uint8_t b) { c->A[i / 8] ^= (uint64_t)b << (8 * (i % 8)); }
+static void sponge_absorb(sponge_ctx *c, const uint8_t *in, size_t len)
+{
+    for (size_t i = 0; i < len; i++) {
+        sponge_byte(c, c->pos++, in[i]);
+        if (c->pos == c->rate) {
+            keccak_f1600(c->A);
+            c->pos = 0;
+        }
+    }
+}
+/* domain suffix and pad10*1: 0x1F for SHAKE, 0x06 for SHA-3 */
+static void sponge_finish(sponge_ctx *c, uint8_t suffix)
+{
+    sponge_byte(c, c->pos, suffix);
+    sponge_byte(c, c->rate - 1, 0x80);
+    keccak_f1600(c->A);
+    c->pos = 0;
+}
+static void sponge_squeeze(sponge_ctx *c, uint8_t *out, size_t len)
+{
+    for (size_t i = 0; i < len; i++) {
+        if (c->pos == c->rate) {
+            keccak_f1600(c->A);
+            c->pos = 0;
+        }
+        out[i] = (uint8_t)(c->A[c->pos / 8] >> (8 * (c->pos % 8)));
+        c->pos++;
+    }
+}
+
+void or_shake256(const uint8_t *in, size_t len, uint8_t *out, size_t outlen)
+{
+    sponge_ctx c;
+    sponge_init(&c, 136);
+    sponge_absorb(&c, in, len);
+    sponge_finish(&c, 0x1F);
+    sponge_squeeze(&c, out, outlen);
+}
+
+void or_sha3_256(const uint8_t *in, size_t len, uint8_t out[32])
+{
+    sponge_ctx c;
+    sponge_init(&c, 136);
+    sponge_absorb(&c, in, len);
+    sponge_finish(&c, 0x06);
+    sponge_squeeze(&c, out, 32);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -422,25 +553,42 @@ static void th512(const or_params *p, const uint8_t *pk_seed, const uint8_t *A,
     memcpy(out, dig, p->n);
 }
 
+/* SHAKE256(PK.seed || ADRS || M, 8n) with the full 32-byte ADRS (FIPS 205
+ * Section 11.1: PRF, F, H and T_l of the SHAKE sets). */
+static void thshake(const or_params *p, const uint8_t *pk_seed, const uint8_t *A,
+                    const uint8_t *m, size_t mlen, uint8_t *out)
+{
+    sponge_ctx c;
+    sponge_init(&c, 136);
+    sponge_absorb(&c, pk_seed, p->n);
+    sponge_absorb(&c, A, 32);
+    sponge_absorb(&c, m, mlen);
+    sponge_finish(&c, 0x1F);
+    sponge_squeeze(&c, out, p->n);
+}
+
 void or_prf(const or_params *p, const uint8_t *pk_seed, const uint8_t *sk_seed,
             const uint8_t adrs[32], uint8_t *out)
 {
     g_cnt[C_PRF]++;
-    th256(p, pk_seed, adrs, sk_seed, p->n, out);  /* SHA-256 in every category */
+    if (p->shake) thshake(p, pk_seed, adrs, sk_seed, p->n, out);
+    else th256(p, pk_seed, adrs, sk_seed, p->n, out);  /* SHA-256 in every SHA2 category */
 }
 
 void or_f(const or_params *p, const uint8_t *pk_seed, const uint8_t adrs[32],
           const uint8_t *m1, uint8_t *out)
 {
     g_cnt[C_F]++;
-    th256(p, pk_seed, adrs, m1, p->n, out);  /* SHA-256 in every category */
+    if (p->shake) thshake(p, pk_seed, adrs, m1, p->n, out);
+    else th256(p, pk_seed, adrs, m1, p->n, out);  /* SHA-256 in every SHA2 category */
 }
 
 void or_h(const or_params *p, const uint8_t *pk_seed, const uint8_t adrs[32],
           const uint8_t *m2, uint8_t *out)
 {
     g_cnt[C_H]++;
-    if (p->wide) th512(p, pk_seed, adrs, m2, 2 * (size_t)p->n, out);
+    if (p->shake) thshake(p, pk_seed, adrs, m2, 2 * (size_t)p->n, out);
+    else if (p->wide) th512(p, pk_seed, adrs, m2, 2 * (size_t)p->n, out);
     else th256(p, pk_seed, adrs, m2, 2 * (size_t)p->n, out);
 }
 
@@ -448,7 +596,8 @@ void or_t(const or_params *p, const uint8_t *pk_seed, const uint8_t adrs[32],
           const uint8_t *ml, size_t l_blocks, uint8_t *out)
 {
     g_cnt[C_T]++;
-    if (p->wide) th512(p, pk_seed, adrs, ml, l_blocks * p->n, out);
+    if (p->shake) thshake(p, pk_seed, adrs, ml, l_blocks * p->n, out);
+    else if (p->wide) th512(p, pk_seed, adrs, ml, l_blocks * p->n, out);
     else th256(p, pk_seed, adrs, ml, l_blocks * p->n, out);
 }
 
@@ -459,6 +608,16 @@ void or_prf_msg(const or_params *p, const uint8_t *sk_prf, const uint8_t *opt_ra
     /* HMAC over the concatenation opt_rand || M, written out without a
      * temporary copy of M by feeding the inner hash in two parts. */
     g_cnt[C_PRFMSG]++;
+    if (p->shake) {  /* SHAKE256(SK.prf || opt_rand || M, 8n) */
+        sponge_ctx c;
+        sponge_init(&c, 136);
+        sponge_absorb(&c, sk_prf, p->n);
+        sponge_absorb(&c, opt_rand, p->n);
+        sponge_absorb(&c, msg, mlen);
+        sponge_finish(&c, 0x1F);
+        sponge_squeeze(&c, out, p->n);
+        return;
+    }
     if (!p->wide) {
         uint8_t k0[64] = {0}, ipad[64], opad[64], inner[32], mac[32];
         memcpy(k0, sk_prf, p->n);
@@ -490,6 +649,17 @@ void or_h_msg(const or_params *p, const uint8_t *r, const uint8_t *pk_seed,
     uint8_t seed[2 * OR_MAX_N + 64];
     size_t n = p->n;
     g_cnt[C_HMSG]++;
+    if (p->shake) {  /* SHAKE256(R || PK.seed || PK.root || M, 8m) */
+        sponge_ctx c;
+        sponge_init(&c, 136);
+        sponge_absorb(&c, r, n);
+        sponge_absorb(&c, pk_seed, n);
+        sponge_absorb(&c, pk_root, n);
+        sponge_absorb(&c, msg, mlen);
+        sponge_finish(&c, 0x1F);
+        sponge_squeeze(&c, out, p->m);
+        return;
+    }
     memcpy(seed, r, n);
     memcpy(seed + n, pk_seed, n);
     if (!p->wide) {

@@ -68,9 +68,11 @@ typedef struct {
     int len;    /* len1 + len2 */
     int m;      /* digest bytes taken from H_msg */
     int wide;   /* 1: H, T_l, H_msg, PRF_msg use SHA-512 (n >= 24) */
+    int shake;  /* 1: every hash is SHAKE256 (FIPS 205 Section 11.1) */
 } or_params;
 
-/* id 1 = SHA2-128f, 2 = SHA2-192f, 3 = SHA2-256f. */
+/* id 1 = SHA2-128f, 2 = SHA2-192f, 3 = SHA2-256f, 4 = SHA2-128s,
+ * 5 = SHA2-192s, 6 = SHA2-256s; 7..12 = the SHAKE sets in the same order. */
 int or_params_get(int id, or_params *p);
 /* Fill derived fields (len1, len2, len, m, wide) of a custom set from
  * n, h, d, a, k.  Returns 0 or -1 if outside the limits. */
@@ -79,6 +81,9 @@ size_t or_sig_bytes(const or_params *p);
 
 /* FIPS 180-4 / FIPS 198-1 / RFC 8017 primitives. */
 void or_sha256(const uint8_t *in, size_t len, uint8_t out[32]);
+/* FIPS 202: SHAKE256 with `outlen` output bytes, and SHA3-256. */
+void or_shake256(const uint8_t *in, size_t len, uint8_t *out, size_t outlen);
+void or_sha3_256(const uint8_t *in, size_t len, uint8_t out[32]);
 void or_sha512(const uint8_t *in, size_t len, uint8_t out[64]);
 void or_hmac_sha256(const uint8_t *key, size_t klen, const uint8_t *msg,
                     size_t mlen, uint8_t out[32]);
@@ -155,8 +160,9 @@ int or_verify_ext(const or_params *p, const uint8_t *msg, size_t mlen, const uin
                   size_t ctxlen, int ph, const uint8_t *sig, size_t siglen, const uint8_t *pk);
 
 /* Per-thread call counters (reset / read).  Index: 0 F, 1 PRF, 2 H, 3 T_l,
- * 4 SHA-256 compressions, 5 SHA-512 compressions, 6 PRF_msg, 7 H_msg. */
-#define OR_NCOUNTERS 8
+ * 4 SHA-256 compressions, 5 SHA-512 compressions, 6 PRF_msg, 7 H_msg,
+ * 8 Keccak-f[1600] permutations. */
+#define OR_NCOUNTERS 9
 void or_counters_reset(void);
 void or_counters_get(uint64_t out[OR_NCOUNTERS]);
 

@@ -6,7 +6,7 @@ level) rather than with the recursive node functions of the C oracle, and
 it hashes with Python's hashlib/hmac instead of the oracle's own SHA-2, so
 a transcription slip in either one shows up as a byte difference.
 
-Definitions followed: FIPS 205 Sections 4-9 and 11.2 (SHA2 "simple"), the
+Definitions followed: FIPS 205 Sections 4-9, 11.1 (SHAKE) and 11.2 (SHA2), the
 paper's Section II-A description of WOTS+, FORS, XMSS and the hypertree, and
 the Fig. 2 signing listing (leaf index = tree mod 2^h', tree >>= h').
 """
@@ -25,6 +25,7 @@ class P:
     a: int
     k: int
     lg_w: int = 4
+    shake: bool = False  # FIPS 205 Section 11.1: every hash is SHAKE256
 
     @property
     def hp(self):
@@ -71,6 +72,12 @@ SETS = {
     "128s": P(16, 63, 7, 12, 14),
     "192s": P(24, 63, 7, 14, 17),
     "256s": P(32, 64, 8, 14, 22),
+    "shake-128f": P(16, 66, 22, 6, 33, shake=True),
+    "shake-192f": P(24, 66, 22, 8, 33, shake=True),
+    "shake-256f": P(32, 68, 17, 9, 35, shake=True),
+    "shake-128s": P(16, 63, 7, 12, 14, shake=True),
+    "shake-192s": P(24, 63, 7, 14, 17, shake=True),
+    "shake-256s": P(32, 64, 8, 14, 22, shake=True),
 }
 
 # address types
@@ -92,6 +99,10 @@ class Hashes:
     def _th(self, wide: bool, ac: bytes, data: bytes) -> bytes:
         self.calls += 1
         n = self.p.n
+        if self.p.shake:
+            # the full 32-byte address: 4-byte layer, 12-byte tree, 4-byte type, 3 words
+            full = bytes(3) + ac[0:1] + bytes(4) + ac[1:9] + bytes(3) + ac[9:10] + ac[10:22]
+            return hashlib.shake_256(self.pk_seed + full + data).digest(n)
         if wide:
             return hashlib.sha512(self.pk_seed + bytes(128 - n) + ac + data).digest()[:n]
         return hashlib.sha256(self.pk_seed + bytes(64 - n) + ac + data).digest()[:n]
@@ -205,11 +216,15 @@ class ForsForest:
 
 
 def prf_msg(p: P, sk_prf, opt_rand, msg):
+    if p.shake:
+        return hashlib.shake_256(sk_prf + opt_rand + msg).digest(p.n)
     alg = "sha512" if p.wide else "sha256"
     return hmac.new(sk_prf, opt_rand + msg, alg).digest()[:p.n]
 
 
 def h_msg(p: P, r, pk_seed, pk_root, msg):
+    if p.shake:
+        return hashlib.shake_256(r + pk_seed + pk_root + msg).digest(p.m)
     H = hashlib.sha512 if p.wide else hashlib.sha256
     seed = r + pk_seed + H(r + pk_seed + pk_root + msg).digest()
     out = b""
