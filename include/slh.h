@@ -9,7 +9,8 @@
  * Section 11.2): keygen is slh_keygen_internal (Algorithm 18), signing is
  * slh_sign_internal (Algorithm 19) with opt_rand = PK.seed (deterministic
  * signing, no context prefix: the raw message M is signed), verification is
- * slh_verify_internal (Algorithm 20).
+ * slh_verify_internal (Algorithm 20).  The SHAKE sets (ids 7..12) use the
+ * SHAKE256 instantiation of FIPS 205 Section 11.1 on the same trees.
  *
  * Parameter sets (the paper's Table 1):
  *   SLH_SHA2_128F  n=16 h=66 d=22 a=6 k=33 w=16   signature 17088 bytes
@@ -49,15 +50,24 @@ extern "C" {
 /* Parameter sets: the SHA2 "fast" sets the paper evaluates (its Table 1)
  * and the SHA2 "small" sets (FIPS 205 Table 2; h' = 8-9, FORS trees of
  * 2^12-2^14 leaves, built on the GPU in units of 64 XMSS leaves and 2^12
- * FORS leaves).  SLH_MODE_FUSED, SLH_MODE_DEDUP and slh_ctx_cache_keys
- * apply to the fast sets; small-set requests always take the per-phase
- * path. */
+ * FORS leaves), then the same six shapes with the SHAKE256 hashes of FIPS
+ * 205 Section 11.1 (SLH_SHAKE_*: F, H, T_l, PRF = SHAKE256(PK.seed | ADRS |
+ * ..., 8n) over the full 32-byte address; PRF_msg and H_msg are SHAKE256 of
+ * the concatenated inputs).  SLH_MODE_FUSED, SLH_MODE_DEDUP and
+ * slh_ctx_cache_keys apply to the fast sets (1-3, 7-9); small-set requests
+ * always take the per-phase path. */
 #define SLH_SHA2_128F 1u
 #define SLH_SHA2_192F 2u
 #define SLH_SHA2_256F 3u
 #define SLH_SHA2_128S 4u
 #define SLH_SHA2_192S 5u
 #define SLH_SHA2_256S 6u
+#define SLH_SHAKE_128F 7u
+#define SLH_SHAKE_192F 8u
+#define SLH_SHAKE_256F 9u
+#define SLH_SHAKE_128S 10u
+#define SLH_SHAKE_192S 11u
+#define SLH_SHAKE_256S 12u
 
 #define SLH_OK 0
 #define SLH_EINVAL (-1)  /* bad parameter set, slot, size, offset or null pointer */

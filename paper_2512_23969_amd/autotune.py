@@ -33,6 +33,7 @@ DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
 
 # (n, a = log t, k) of the parameter sets (the paper's Table 1)
 FORS_SHAPE = {1: (16, 6, 33), 2: (24, 8, 33), 3: (32, 9, 35), 4: (16, 12, 14), 5: (24, 14, 17), 6: (32, 14, 22)}
+FORS_SHAPE.update({p + 6: s for p, s in list(FORS_SHAPE.items())})  # SHAKE sets: same shapes
 
 
 def tree_tuning(k: int, log_t: int, n: int, s_max: int, t_max: int = 1024, alpha: float = 0.6):
@@ -65,6 +66,7 @@ def tree_tuning(k: int, log_t: int, n: int, s_max: int, t_max: int = 1024, alpha
 
 
 COMPILED_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8), 4: (1, 2), 5: (1, 2), 6: (1, 2)}
+COMPILED_GROUPS.update({p + 6: g for p, g in list(COMPILED_GROUPS.items())})
 
 
 def gfx950_groups(param: int, lds_bytes: int = 160 * 1024, lanes: int = 256, compiled=None):

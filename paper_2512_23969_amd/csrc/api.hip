@@ -32,11 +32,20 @@ bool sizes_of(uint32_t param, Sizes* s) {
     case SLH_SHA2_128S: *s = {16, 63, 7, 9, 12, 14, 35, 30, uint32_t(P<4>::sig_bytes)}; return true;
     case SLH_SHA2_192S: *s = {24, 63, 7, 9, 14, 17, 51, 39, uint32_t(P<5>::sig_bytes)}; return true;
     case SLH_SHA2_256S: *s = {32, 64, 8, 8, 14, 22, 67, 47, uint32_t(P<6>::sig_bytes)}; return true;
+    case SLH_SHAKE_128F: *s = {16, 66, 22, 3, 6, 33, 35, 34, uint32_t(P<7>::sig_bytes)}; return true;
+    case SLH_SHAKE_192F: *s = {24, 66, 22, 3, 8, 33, 51, 42, uint32_t(P<8>::sig_bytes)}; return true;
+    case SLH_SHAKE_256F: *s = {32, 68, 17, 4, 9, 35, 67, 49, uint32_t(P<9>::sig_bytes)}; return true;
+    case SLH_SHAKE_128S: *s = {16, 63, 7, 9, 12, 14, 35, 30, uint32_t(P<10>::sig_bytes)}; return true;
+    case SLH_SHAKE_192S: *s = {24, 63, 7, 9, 14, 17, 51, 39, uint32_t(P<11>::sig_bytes)}; return true;
+    case SLH_SHAKE_256S: *s = {32, 64, 8, 8, 14, 22, 67, 47, uint32_t(P<12>::sig_bytes)}; return true;
     default: return false;
   }
 }
 
-constexpr int kSets = 6;  // parameter sets 1..6 (slh.h SLH_SHA2_*)
+constexpr int kSets = 12;  // parameter sets 1..12 (slh.h SLH_SHA2_*, SLH_SHAKE_*)
+// SHA2 set with the same shape (n, h, d, a, k): ids 7..12 are the SHAKE
+// counterparts of ids 1..6.
+constexpr uint32_t shape_of(uint32_t param) { return (param - 1) % 6 + 1; }
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -172,11 +181,15 @@ void drop_graphs(slh_ctx* c) {
 // FORS trees per workgroup that have a compiled variant, per parameter set.
 // Small sets: FORS units of 2^12 leaves, one or two per workgroup.
 bool fg_ok(uint32_t param, uint32_t fg) {
+  param = shape_of(param);
   if (param >= 4) return fg == 1 || fg == 2;
   if (param == 3) return fg == 2 || fg == 4 || fg == 8;
   return fg == 4 || fg == 8 || fg == 16;
 }
-uint32_t fg_default(uint32_t param) { return param >= 4 ? 1u : (param == 3 ? 4u : 8u); }
+uint32_t fg_default(uint32_t param) {
+  param = shape_of(param);
+  return param >= 4 ? 1u : (param == 3 ? 4u : 8u);
+}
 
 // The fused persistent kernel, dedup and the key cache cover the sets whose
 // XMSS and FORS trees fit one unit (the fast sets).
@@ -188,16 +201,17 @@ template <int FG>
 using FgC = std::integral_constant<int, FG>;
 template <int ID, typename F>
 void with_fg(uint32_t fg, F&& f) {
-  if constexpr (ID >= 4) {
+  constexpr uint32_t S = shape_of(ID);
+  if constexpr (S >= 4) {
     if (fg == 2) f(FgC<2>{}); else f(FgC<1>{});
-  } else if constexpr (ID == 3) {
+  } else if constexpr (S == 3) {
     if (fg == 2) f(FgC<2>{}); else if (fg == 8) f(FgC<8>{}); else f(FgC<4>{});
   } else {
     if (fg == 4) f(FgC<4>{}); else if (fg == 16) f(FgC<16>{}); else f(FgC<8>{});
   }
 }
 
-// Call f(std::integral_constant<int, ID>) for parameter set `param` (1..6).
+// Call f(std::integral_constant<int, ID>) for parameter set `param` (1..12).
 template <typename F>
 auto with_set(uint32_t param, F&& f) {
   switch (param) {
@@ -206,7 +220,13 @@ auto with_set(uint32_t param, F&& f) {
     case 3: return f(std::integral_constant<int, 3>{});
     case 4: return f(std::integral_constant<int, 4>{});
     case 5: return f(std::integral_constant<int, 5>{});
-    default: return f(std::integral_constant<int, 6>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 9: return f(std::integral_constant<int, 9>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    case 11: return f(std::integral_constant<int, 11>{});
+    default: return f(std::integral_constant<int, 12>{});
   }
 }
 
@@ -226,7 +246,7 @@ template <int ID>
 int occupancy(uint32_t fg) {
   if constexpr (!whole_trees<ID>()) {
     return 1;
-  } else if constexpr (ID == 3) {
+  } else if constexpr (shape_of(ID) == 3) {
     return fg == 2 ? occupancy_of<ID, 2>() : fg == 8 ? occupancy_of<ID, 8>() : occupancy_of<ID, 4>();
   } else {
     return fg == 4 ? occupancy_of<ID, 4>() : fg == 16 ? occupancy_of<ID, 16>() : occupancy_of<ID, 8>();
@@ -520,6 +540,7 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
     if (dk) (void)hipFree(dk);
     if (stage) (void)hipFree(stage);
     if (root) (void)hipFree(root);
+    if (uroots) (void)hipFree(uroots);
     return fail(nullptr, SLH_ENOMEM, "keygen device allocation failed");
   }
   uint32_t hroot[8] = {0};
@@ -553,7 +574,10 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
 
 // Most cached layers per parameter set: at most 2^16 trees per key.
 // (the small sets' trees are built in units; they are not cached)
-uint32_t max_cache_layers(uint32_t param) { return param >= 4 ? 0u : (param == 3 ? 4u : 6u); }
+uint32_t max_cache_layers(uint32_t param) {
+  param = shape_of(param);
+  return param >= 4 ? 0u : (param == 3 ? 4u : 6u);
+}
 
 // Build the cached upper layers of keys [first, first + count) (all of set ID).
 template <int ID>
@@ -798,7 +822,10 @@ int slh_ctx_cache_keys(slh_ctx* c, uint32_t first_slot, uint32_t count, uint32_t
   switch (param) {
     case 1: return cache_impl<1>(c, first_slot, count, layers);
     case 2: return cache_impl<2>(c, first_slot, count, layers);
-    default: return cache_impl<3>(c, first_slot, count, layers);  // the small sets were rejected above
+    case 3: return cache_impl<3>(c, first_slot, count, layers);
+    case 7: return cache_impl<7>(c, first_slot, count, layers);
+    case 8: return cache_impl<8>(c, first_slot, count, layers);
+    default: return cache_impl<9>(c, first_slot, count, layers);  // the small sets were rejected above
   }
 }
 

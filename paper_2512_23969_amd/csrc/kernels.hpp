@@ -32,12 +32,18 @@ constexpr int kLeavesPerBlock = 64; // one wave's worth of leaves
 constexpr int kForsThreads = 256;
 
 // ------------------------------------------------------------------ keys
-// Chaining values after the PK.seed block, one lane per key.
+// Chaining values after the PK.seed block, one lane per key.  Keys of the
+// SHAKE sets (parameter ids 7..12) keep PK.seed itself in the mid256 slot.
 __global__ void k_key_midstates(DevKey* keys, uint32_t first, uint32_t count) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   DevKey& K = keys[first + i];
   const int nw = int(K.n) / 4;
+  if (K.param >= 7) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) K.mid256[j] = j < nw ? K.pk_seed[j] : 0u;
+    return;
+  }
   {
     uint32_t st[8], w[16];
     sha256_iv(st);
@@ -136,11 +142,17 @@ struct KeyView {
   const uint32_t* opt_rand;  // PK.seed for deterministic signing
 };
 
-// R = PRF_msg(SK.prf, opt_rand, M) = Trunc_n(HMAC-SHA-X(SK.prf, opt_rand | M))
+// R = PRF_msg(SK.prf, opt_rand, M) = Trunc_n(HMAC-SHA-X(SK.prf, opt_rand | M)),
+// or SHAKE256(SK.prf | opt_rand | M, 8n) for the SHAKE sets
 template <int ID>
 __device__ void prf_msg(const KeyView& K, const uint8_t* msg, uint64_t mlen, uint32_t* R) {
   constexpr int NW = P<ID>::NW;
-  if constexpr (!P<ID>::wide) {
+  if constexpr (P<ID>::shake) {
+    uint32_t pre[2 * NW];
+#pragma unroll
+    for (int j = 0; j < NW; j++) { pre[j] = K.sk_prf[j]; pre[NW + j] = K.opt_rand[j]; }
+    shake256_stream<2 * NW, NW>(pre, msg, mlen, R);
+  } else if constexpr (!P<ID>::wide) {
     uint32_t st[8], blk[16];
     sha256_iv(st);
 #pragma unroll
@@ -183,6 +195,7 @@ __device__ void prf_msg(const KeyView& K, const uint8_t* msg, uint64_t mlen, uin
 
 // digest = H_msg(R, PK.seed, PK.root, M)
 //        = MGF1-SHA-X(R | PK.seed | SHA-X(R | PK.seed | PK.root | M), m)
+//        (SHA2 sets) or SHAKE256(R | PK.seed | PK.root | M, 8m) (SHAKE sets)
 // (16 BE words; the first m bytes are meaningful)
 template <int ID>
 __device__ void h_msg(const KeyView& K, const uint32_t* R, const uint8_t* msg, uint64_t mlen,
@@ -191,7 +204,10 @@ __device__ void h_msg(const KeyView& K, const uint32_t* R, const uint8_t* msg, u
   uint32_t pre[3 * NW];
 #pragma unroll
   for (int j = 0; j < NW; j++) { pre[j] = R[j]; pre[NW + j] = K.pk_seed[j]; pre[2 * NW + j] = K.pk_root[j]; }
-  if constexpr (!P<ID>::wide) {
+  if constexpr (P<ID>::shake) {
+    // SHAKE256(R | PK.seed | PK.root | M, 8m)
+    shake256_stream<3 * NW, 16>(pre, msg, mlen, digest);
+  } else if constexpr (!P<ID>::wide) {
     uint32_t st[8];
     sha256_iv(st);
     sha256_stream<3 * NW>(st, pre, msg, mlen, 0);
@@ -347,7 +363,7 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
       uint32_t in[NW], out[NW];
 #pragma unroll
       for (int u = 0; u < NW; u++) in[u] = isF ? sk[u] : sks[u];
-      th256<NW, NW>(mid, make_adrs(0, tree, isF ? A_FORS_TREE : A_FORS_PRF, kp, 0, g), in, out);
+      thF<ID>(mid, make_adrs(0, tree, isF ? A_FORS_TREE : A_FORS_PRF, kp, 0, g), in, out);
       if (!isF) {
 #pragma unroll
         for (int u = 0; u < NW; u++) sk[u] = out[u];
@@ -502,7 +518,7 @@ __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t
     Adrs A = A0;
     A.tail = s << 16;
     uint32_t y[NW];
-    th256<NW, NW>(mid, A, x, y);
+    thF<ID>(mid, A, x, y);
 #pragma unroll
     for (int u = 0; u < NW; u++) x[u] = y[u];
     if (keep) store_words<NW>(keep + (s + 1) * NW, x);
@@ -845,7 +861,7 @@ __device__ __forceinline__ void wots_value(const TreeJob& J, uint32_t c, uint32_
   for (uint32_t st = 0; st < digit; st++) {
     A.tail = st << 16;
     uint32_t y[NW];
-    th256<NW, NW>(mid, A, x, y);
+    thF<ID>(mid, A, x, y);
 #pragma unroll
     for (int u = 0; u < NW; u++) x[u] = y[u];
   }
@@ -1117,13 +1133,18 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     uint32_t pk_seed[8] = {0}, pk_root[8] = {0};
     load_be<NW>(pks + it.pk_off, pk_seed);
     load_be<NW>(pks + it.pk_off + Q::n, pk_root);
-    uint32_t st[8], w[16];
-    sha256_iv(st);
+    if constexpr (Q::shake) {
 #pragma unroll
-    for (int j = 0; j < 16; j++) w[j] = j < NW ? pk_seed[j] : 0u;
-    sha256_compress(st, w);
+      for (int j = 0; j < 8; j++) s_mid256[grp][j] = pk_seed[j];
+    } else {
+      uint32_t st[8], w[16];
+      sha256_iv(st);
 #pragma unroll
-    for (int j = 0; j < 8; j++) s_mid256[grp][j] = st[j];
+      for (int j = 0; j < 16; j++) w[j] = j < NW ? pk_seed[j] : 0u;
+      sha256_compress(st, w);
+#pragma unroll
+      for (int j = 0; j < 8; j++) s_mid256[grp][j] = st[j];
+    }
     if constexpr (Q::wide) {
       u64p s5[8], w5[16];
       sha512_iv(s5);
@@ -1236,7 +1257,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
         Adrs Ad = make_adrs(layer, tree, A_WOTS_HASH, leaf, uint32_t(c), 0);
         Ad.tail = st << 16;
         uint32_t y[NW];
-        th256<NW, NW>(mid256, Ad, x, y);
+        thF<ID>(mid256, Ad, x, y);
 #pragma unroll
         for (int u = 0; u < NW; u++) x[u] = y[u];
         st++;

@@ -28,18 +28,21 @@ template <>
 struct Prm<1> {
   static constexpr int n = 16, h = 66, d = 22, hp = 3, a = 6, k = 33, len1 = 32, len2 = 3, m = 34;
   static constexpr bool wide = false;
+  static constexpr bool shake = false;
 };
 // SHA2-192f: n=24, h=66, d=22, h'=3, a=8, k=33, w=16
 template <>
 struct Prm<2> {
   static constexpr int n = 24, h = 66, d = 22, hp = 3, a = 8, k = 33, len1 = 48, len2 = 3, m = 42;
   static constexpr bool wide = true;
+  static constexpr bool shake = false;
 };
 // SHA2-256f: n=32, h=68, d=17, h'=4, a=9, k=35, w=16
 template <>
 struct Prm<3> {
   static constexpr int n = 32, h = 68, d = 17, hp = 4, a = 9, k = 35, len1 = 64, len2 = 3, m = 49;
   static constexpr bool wide = true;
+  static constexpr bool shake = false;
 };
 
 // SHA2-128s: n=16, h=63, d=7, h'=9, a=12, k=14, w=16 (FIPS 205 Table 2)
@@ -47,19 +50,36 @@ template <>
 struct Prm<4> {
   static constexpr int n = 16, h = 63, d = 7, hp = 9, a = 12, k = 14, len1 = 32, len2 = 3, m = 30;
   static constexpr bool wide = false;
+  static constexpr bool shake = false;
 };
 // SHA2-192s: n=24, h=63, d=7, h'=9, a=14, k=17, w=16
 template <>
 struct Prm<5> {
   static constexpr int n = 24, h = 63, d = 7, hp = 9, a = 14, k = 17, len1 = 48, len2 = 3, m = 39;
   static constexpr bool wide = true;
+  static constexpr bool shake = false;
 };
 // SHA2-256s: n=32, h=64, d=8, h'=8, a=14, k=22, w=16
 template <>
 struct Prm<6> {
   static constexpr int n = 32, h = 64, d = 8, hp = 8, a = 14, k = 22, len1 = 64, len2 = 3, m = 47;
   static constexpr bool wide = true;
+  static constexpr bool shake = false;
 };
+
+// SHAKE-128f .. SHAKE-256s: the shapes of sets 1..6 with every hash SHAKE256
+// (FIPS 205 Section 11.1).
+template <int BASE>
+struct PrmShake : Prm<BASE> {
+  static constexpr bool wide = false;
+  static constexpr bool shake = true;
+};
+template <> struct Prm<7> : PrmShake<1> {};
+template <> struct Prm<8> : PrmShake<2> {};
+template <> struct Prm<9> : PrmShake<3> {};
+template <> struct Prm<10> : PrmShake<4> {};
+template <> struct Prm<11> : PrmShake<5> {};
+template <> struct Prm<12> : PrmShake<6> {};
 
 template <int ID>
 struct P : Prm<ID> {
@@ -174,6 +194,10 @@ __device__ __forceinline__ Adrs make_adrs(uint32_t layer, uint64_t tree, uint32_
   return A;
 }
 
+}  // namespace slh
+#include "keccak_dev.hpp"
+namespace slh {
+
 // Message words 0..15 of a block holding ADRSc | x (NX BE words) | padding,
 // where the block follows one earlier block (the PK.seed block).
 // For SHA-256: 22 + 4 NX + 9 <= 64, i.e. NX <= 8.
@@ -231,17 +255,27 @@ __device__ __forceinline__ void th512(const uint32_t mid[16], const Adrs& A, con
   for (int i = 0; i < NOUT; i++) out[i] = (i & 1) ? st[i >> 1].lo : st[i >> 1].hi;
 }
 
-// F and PRF: always SHA-256 (FIPS 205 Section 11.2.1 and 11.2.2).
+// For the SHAKE sets the key's mid256 slot holds PK.seed itself (there is
+// no chaining value to precompute: PK.seed, ADRS and the input share one
+// SHAKE256 block), so every tweakable hash below takes `mid256` as either.
+//
+// F and PRF: SHA-256 in every SHA2 category (FIPS 205 Sections 11.2.1 and
+// 11.2.2), SHAKE256 in the SHAKE ones (Section 11.1).
 template <int ID>
 __device__ __forceinline__ void thF(const uint32_t mid256[8], const Adrs& A, const uint32_t* x,
                                     uint32_t* out) {
-  th256<P<ID>::NW, P<ID>::NW>(mid256, A, x, out);
+  if constexpr (P<ID>::shake)
+    thshake<P<ID>::NW, P<ID>::NW, P<ID>::NW>(mid256, A, x, out);
+  else
+    th256<P<ID>::NW, P<ID>::NW>(mid256, A, x, out);
 }
-// H: SHA-256 for n = 16, SHA-512 for n = 24, 32.
+// H: SHA-256 for n = 16, SHA-512 for n = 24, 32; SHAKE256 for the SHAKE sets.
 template <int ID>
 __device__ __forceinline__ void thH(const DevKey& key, const Adrs& A, const uint32_t* lr,
                                     uint32_t* out) {
-  if constexpr (P<ID>::wide)
+  if constexpr (P<ID>::shake)
+    thshake<P<ID>::NW, 2 * P<ID>::NW, P<ID>::NW>(key.mid256, A, lr, out);
+  else if constexpr (P<ID>::wide)
     th512<2 * P<ID>::NW, P<ID>::NW>(key.mid512, A, lr, out);
   else
     th256<2 * P<ID>::NW, P<ID>::NW>(key.mid256, A, lr, out);
@@ -249,7 +283,9 @@ __device__ __forceinline__ void thH(const DevKey& key, const Adrs& A, const uint
 template <int ID>
 __device__ __forceinline__ void thH(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
                                     const uint32_t* lr, uint32_t* out) {
-  if constexpr (P<ID>::wide)
+  if constexpr (P<ID>::shake)
+    thshake<P<ID>::NW, 2 * P<ID>::NW, P<ID>::NW>(mid256, A, lr, out);
+  else if constexpr (P<ID>::wide)
     th512<2 * P<ID>::NW, P<ID>::NW>(mid512, A, lr, out);
   else
     th256<2 * P<ID>::NW, P<ID>::NW>(mid256, A, lr, out);
@@ -261,8 +297,8 @@ __device__ __forceinline__ void thH(const uint32_t* mid256, const uint32_t* mid5
 // ADRSc (22 bytes) | values, after the PK.seed block; SHA-256 for n = 16,
 // SHA-512 for n >= 24.  Message word q >= 6 is alignbit(V[q-6], V[q-5], 16).
 template <int ID, int L, class Get>
-__device__ __forceinline__ void thT(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
-                                    Get get, uint32_t* out) {
+__device__ __forceinline__ void thT_sha2(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
+                                         Get get, uint32_t* out) {
   constexpr int NW = P<ID>::NW;
   constexpr int NV = L * NW;                 // value words
   constexpr int MB = 22 + 4 * NV;            // message bytes after the seed block
@@ -322,6 +358,16 @@ __device__ __forceinline__ void thT(const uint32_t* mid256, const uint32_t* mid5
 #pragma unroll
     for (int i = 0; i < NW; i++) out[i] = (i & 1) ? st[i >> 1].lo : st[i >> 1].hi;
   }
+}
+
+// T_l: SHA-2 after the PK.seed block, or SHAKE256 for the SHAKE sets.
+template <int ID, int L, class Get>
+__device__ __forceinline__ void thT(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
+                                    Get get, uint32_t* out) {
+  if constexpr (P<ID>::shake)
+    thshake_t<P<ID>::NW, L>(mid256, A, get, out);
+  else
+    thT_sha2<ID, L>(mid256, mid512, A, get, out);
 }
 
 // ---------------------------------------------------------------- byte streams

@@ -15,7 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libslh.so")
 
 SHA2_128F, SHA2_192F, SHA2_256F = 1, 2, 3
-NAMES = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s"}
+NAMES = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s",
+         7: "shake-128f", 8: "shake-192f", 9: "shake-256f", 10: "shake-128s", 11: "shake-192s",
+         12: "shake-256s"}
 IDS = {v: k for k, v in NAMES.items()}
 MODE_PLAIN, MODE_FUSED, MODE_GRAPH, MODE_DEDUP = 0, 1, 2, 4
 MODES = {"plain": MODE_PLAIN, "fused": MODE_FUSED, "graph": MODE_GRAPH | MODE_FUSED,
@@ -26,6 +28,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EBUSY = 0, -1, -2, -3, -4
 PHASES = ("prelude", "fors", "tree", "wots", "fused")
 # compiled FORS group sizes per parameter set
 FORS_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8), 4: (1, 2), 5: (1, 2), 6: (1, 2)}
+FORS_GROUPS.update({p + 6: g for p, g in list(FORS_GROUPS.items())})  # SHAKE: same shapes
 
 ITEM_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"),
                        ("msg_len", "<u8"), ("sig_off", "<u8")])

@@ -15,8 +15,10 @@ from __future__ import annotations
 import numpy as np
 
 # parameter-set id -> security parameter n in bytes (the paper's Table 1)
-N_OF = {1: 16, 2: 24, 3: 32, 4: 16, 5: 24, 6: 32}
-NAME_OF = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s"}
+N_OF = {1: 16, 2: 24, 3: 32, 4: 16, 5: 24, 6: 32, 7: 16, 8: 24, 9: 32, 10: 16, 11: 24, 12: 32}
+NAME_OF = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s",
+           7: "shake-128f", 8: "shake-192f", 9: "shake-256f", 10: "shake-128s", 11: "shake-192s",
+           12: "shake-256s"}
 ID_OF = {v: k for k, v in NAME_OF.items()}
 
 
@@ -55,6 +57,11 @@ CONFIGS = {
     "s1_128s_1024": dict(cfg=11, param=4, batch=1024, keys=1, length=32),
     "s2_192s_1024": dict(cfg=12, param=5, batch=1024, keys=1, length=32),
     "s3_256s_1024": dict(cfg=13, param=6, batch=1024, keys=1, length=32),
+    # the SHAKE256 instantiation of the same shapes (not in the paper)
+    "k1_shake128f_4096": dict(cfg=21, param=7, batch=4096, keys=1, length=32),
+    "k2_shake192f_4096": dict(cfg=22, param=8, batch=4096, keys=1, length=32),
+    "k3_shake256f_4096x64": dict(cfg=23, param=9, batch=4096, keys=64, length=32),
+    "k4_shake128s_1024": dict(cfg=24, param=10, batch=1024, keys=1, length=32),
 }
 
 

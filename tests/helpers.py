@@ -6,7 +6,9 @@ from concurrent.futures import ThreadPoolExecutor
 
 import oracle
 
-NAMES = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s"}
+NAMES = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s",
+         7: "shake-128f", 8: "shake-192f", 9: "shake-256f", 10: "shake-128s", 11: "shake-192s",
+         12: "shake-256s"}
 
 
 def host_threads() -> int:

@@ -41,7 +41,10 @@ def test_no_oracle_symbols_in_product_library():
             getattr(slh.lib, name)
 
 
-@pytest.mark.parametrize("param,n,sig", [(1, 16, 17088), (2, 24, 35664), (3, 32, 49856)])
+SIZES = [(1, 16, 17088), (2, 24, 35664), (3, 32, 49856), (4, 16, 7856), (5, 24, 16224), (6, 32, 29792)]
+
+
+@pytest.mark.parametrize("param,n,sig", SIZES + [(p + 6, n, sig) for p, n, sig in SIZES])
 def test_sizes(param, n, sig):
     import oracle
     slh = _lib()
@@ -55,7 +58,8 @@ def test_sizes(param, n, sig):
 def test_bad_arguments_rejected_on_host():
     slh = _lib()
     L = slh.lib
-    assert L.slh_params(7, ctypes.byref(slh.slh_sizes())) == slh.EINVAL
+    assert L.slh_params(13, ctypes.byref(slh.slh_sizes())) == slh.EINVAL
+    assert L.slh_params(0, ctypes.byref(slh.slh_sizes())) == slh.EINVAL
     assert L.slh_params(1, None) == slh.EINVAL
     assert L.slh_keygen(9, b"x" * 48, None, None) == slh.EINVAL
     assert L.slh_keygen(1, None, None, None) == slh.EINVAL
