@@ -25,6 +25,10 @@ WORKLOADS = {
     "s1_128s_1024": "SPHINCS+-SHA2-128s, 1 key, 1024 x 32-byte messages",
     "s2_192s_1024": "SPHINCS+-SHA2-192s, 1 key, 1024 x 32-byte messages",
     "s3_256s_1024": "SPHINCS+-SHA2-256s, 1 key, 1024 x 32-byte messages",
+    "k1_shake128f_4096": "SPHINCS+-SHAKE-128f, 1 key, 4096 x 32-byte messages",
+    "k2_shake192f_4096": "SPHINCS+-SHAKE-192f, 1 key, 4096 x 32-byte messages",
+    "k3_shake256f_4096x64": "SPHINCS+-SHAKE-256f, 64 keys, 4096 x 32-byte messages",
+    "k4_shake128s_1024": "SPHINCS+-SHAKE-128s, 1 key, 1024 x 32-byte messages",
 }
 
 
@@ -255,8 +259,8 @@ def roofline(param, res):
             "traffic": TRAFFIC.get((param, kernel)),
             "avg_launch_ms": round(ms / launches, 4),
             "units_per_launch": {h: int(sum(c[h][p] * scale.get(p, 1.0) for p in parts) * per_launch_msgs)
-                                 for h in ("sha256", "sha512")},
-            "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512},
+                                 for h in ("sha256", "sha512", "keccak") if sum(c[h].values())},
+            "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512, "keccak": acc.OPS_KECCAK},
             "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4)}
 
 
@@ -280,8 +284,7 @@ def phase_rooflines(param, res, msg_bytes=32):
             out[ph] = {"bound": "alu", "achieved": round(ops / s / 1e12, 3), "unit": "TOP/s",
                        "frac": round(ops / s / peak_ops, 4)}
         elif ph == "prelude":
-            c256, c512 = acc.prelude_compressions(param, msg_bytes)
-            ops = (c256 * acc.TEXTBOOK_SHA256 + c512 * acc.TEXTBOOK_SHA512) * msgs
+            ops = acc.prelude_ops(param, msg_bytes) * msgs
             out[ph] = {"bound": "alu (one lane per message)", "achieved": round(ops / s / 1e12, 4),
                        "unit": "TOP/s", "frac": round(ops / s / peak_ops, 5)}
         elif ph == "wots":
@@ -354,8 +357,9 @@ def main():
               verify=True)
     param = res["cfg"]["param"]
     c256, c512 = acc.compressions_per_signature(param)
+    ckf = acc.permutations_per_signature(param)
     line = {
-        "metric": "signatures/s (SPHINCS+-SHA2-%s, batch %d)" % (workloads.NAME_OF[param], res["cfg"]["batch"]),
+        "metric": "signatures/s (SPHINCS+-%s, batch %d)" % (acc.full_name(param), res["cfg"]["batch"]),
         "value": round(res["sig_per_s"], 1),
         "unit": "signatures/s",
         "n_gpus": 1,
@@ -371,7 +375,8 @@ def main():
                    "batch": res["cfg"]["batch"], "keys": res["cfg"]["keys"], "msg_bytes": 32,
                    "mode": res["mode"], "tuning": res["tuning"]},
         "compressions_per_s": {"sha256": round(res["sig_per_s"] * c256, 0),
-                               "sha512": round(res["sig_per_s"] * c512, 0)},
+                               "sha512": round(res["sig_per_s"] * c512, 0),
+                               "keccak_f": round(res["sig_per_s"] * ckf, 0)},
         "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param) / acc.VALU_PEAK_OPS, 4),
         "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items() if v[1]},
         "roofline": roofline(param, res),
@@ -383,13 +388,20 @@ def main():
     if args.all:
         # every batch-4096 workload in the plain per-phase path and in the
         # batched modes (fused persistent kernel; hipGraph-captured pipeline;
-        # tree dedup), and the small sets at batch 1024
+        # tree dedup), the small sets at batch 1024 and the SHAKE sets
         extra = {}
         steps_c = max(3, args.steps // 2)
         for name in ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64", "s1_128s_1024", "s2_192s_1024",
-                     "s3_256s_1024"):
+                     "s3_256s_1024", "k1_shake128f_4096", "k2_shake192f_4096", "k3_shake256f_4096x64",
+                     "k4_shake128s_1024"):
             # the small sets take the per-phase path in every mode
-            for mode in (("plain",) if name.startswith("s") else ("plain", "fused", "graph", "dedup", "fused-dedup")):
+            if name.startswith("s") or name.startswith("k4"):
+                modes = ("plain",)
+            elif name.startswith("k"):
+                modes = ("plain", "fused", "dedup")
+            else:
+                modes = ("plain", "fused", "graph", "dedup", "fused-dedup")
+            for mode in modes:
                 if name == args.workload and mode == res["mode"]:
                     continue
                 log("bench: workload", name, mode)

@@ -20,6 +20,16 @@ block), counted from its disassembly and confirmed by SQ_INSTS_VALU:
            v_lshl_add_u64).
 SQ_INSTS_VALU of whole launches agrees within 2 % (the rest is loads,
 address arithmetic and lanes masked off in the upper Merkle levels).
+
+The SHAKE sets (FIPS 205 Section 11.1) count Keccak-f[1600] permutations
+instead: F, PRF and H absorb one 136-byte block, T_l takes
+ceil((n + 32 + l n + 1) / 136) blocks, PRF_msg and H_msg absorb their
+concatenated inputs.  One permutation on 32-bit lanes (a 64-bit lane as two
+halves) is 24 rounds of 180 instructions: theta 20 three-input XORs for
+the column parities, 10 alignbits for their 1-bit rotates, 50 three-input
+XORs to apply them; rho 48 alignbits (24 rotated lanes); chi 50 one-
+instruction a ^ (~b & c); iota 2 XORs.  The compiled round body is exactly
+that count (240 v_bitop3 + 116 v_alignbit + 4 v_xor per two rounds).
 For comparison, the textbook count with one instruction per primitive of
 FIPS 180-4 and no precomputation is:
   SHA-256: round = Sigma1 (3 rotates + 1 xor3) + Ch + Sigma0 (3 + 1) + Maj
@@ -40,6 +50,7 @@ TEXTBOOK_SHA256 = 64 * 14 + 48 * 10 + 8
 TEXTBOOK_SHA512 = 80 * 34 + 64 * 22 + 16
 OPS_SHA256 = 1232
 OPS_SHA512 = 3490
+TEXTBOOK_KECCAK = OPS_KECCAK = 24 * (20 + 10 + 50 + 48 + 50 + 2)
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock for 32-bit integer VALU
 # operations at the 2.4 GHz peak engine clock.
@@ -54,6 +65,7 @@ class Params:
     d: int
     a: int
     k: int
+    shake: bool = False
 
     @property
     def hp(self):
@@ -65,15 +77,25 @@ class Params:
 
     @property
     def wide(self):
-        return self.n >= 24
+        return self.n >= 24 and not self.shake
 
 
 PARAMS = {1: Params(16, 66, 22, 6, 33), 2: Params(24, 66, 22, 8, 33), 3: Params(32, 68, 17, 9, 35),
           4: Params(16, 63, 7, 12, 14), 5: Params(24, 63, 7, 14, 17), 6: Params(32, 64, 8, 14, 22)}
+PARAMS.update({i + 6: Params(p.n, p.h, p.d, p.a, p.k, True) for i, p in list(PARAMS.items())})
+
+
+def full_name(param: int) -> str:
+    """SHA2-128f ... SHAKE-256s."""
+    p = PARAMS[param]
+    return "%s-%d%s" % ("SHAKE" if p.shake else "SHA2", 8 * p.n, "s" if p.hp >= 8 else "f")
 
 
 def t_blocks(p: Params, l: int) -> int:
-    """Compressions of T_l after the PK.seed block."""
+    """Compressions of T_l after the PK.seed block (SHA2 sets), or Keccak-f
+    permutations of T_l (SHAKE sets)."""
+    if p.shake:
+        return (p.n + 32 + l * p.n + 1 + 135) // 136
     mb = 22 + l * p.n
     if p.wide:
         return (mb + 17 + 127) // 128
@@ -81,11 +103,18 @@ def t_blocks(p: Params, l: int) -> int:
 
 
 def per_signature(param: int) -> dict:
-    """Compressions of one signature on the signing path, split by phase and
-    hash (no WOTS+ recomputation: the chain values are kept)."""
+    """Compressions (Keccak-f permutations for the SHAKE sets) of one
+    signature on the signing path, split by phase and hash (no WOTS+
+    recomputation: the chain values are kept)."""
     p = PARAMS[param]
     leaves = p.d << p.hp
     fors_leaves = p.k << p.a
+    if p.shake:
+        kf = {"fors": 2 * fors_leaves + (fors_leaves - p.k) + t_blocks(p, p.k),
+              "tree": leaves * p.len * 16 + leaves * t_blocks(p, p.len) + p.d * ((1 << p.hp) - 1),
+              "wots": 0}
+        zero = {ph: 0 for ph in kf}
+        return {"sha256": zero, "sha512": dict(zero), "keccak": kf}
     c256 = {}
     c512 = {}
     c256["fors"] = 2 * fors_leaves + (0 if p.wide else (fors_leaves - p.k) + t_blocks(p, p.k))
@@ -96,7 +125,7 @@ def per_signature(param: int) -> dict:
     c256["tree"] = chains + (0 if p.wide else tlen + merkle)
     c512["tree"] = (tlen + merkle) if p.wide else 0
     c256["wots"] = c512["wots"] = 0
-    return {"sha256": c256, "sha512": c512}
+    return {"sha256": c256, "sha512": c512, "keccak": {ph: 0 for ph in c256}}
 
 
 def prelude_compressions(param: int, mlen: int) -> tuple[int, int]:
@@ -107,6 +136,8 @@ def prelude_compressions(param: int, mlen: int) -> tuple[int, int]:
     | M), m)."""
     p = PARAMS[param]
     m = (p.k * p.a + 7) // 8 + (p.h - p.hp + 7) // 8 + (p.hp + 7) // 8
+    if p.shake:
+        return 0, 0
     if not p.wide:
         blk = lambda b: (b + 9 + 63) // 64  # noqa: E731
         prf = blk(64 + p.n + mlen) + blk(64 + 32)
@@ -116,6 +147,24 @@ def prelude_compressions(param: int, mlen: int) -> tuple[int, int]:
     prf = blk(128 + p.n + mlen) + blk(128 + 64)
     hm = blk(3 * p.n + mlen) + -(-m // 64) * blk(2 * p.n + 64 + 4)
     return 0, prf + hm
+
+
+def prelude_permutations(param: int, mlen: int) -> int:
+    """Keccak-f permutations of the prelude of one message (SHAKE sets):
+    PRF_msg = SHAKE256(SK.prf | opt_rand | M, 8n) and
+    H_msg = SHAKE256(R | PK.seed | PK.root | M, 8m), m <= 136."""
+    p = PARAMS[param]
+    if not p.shake:
+        return 0
+    blk = lambda b: (b + 1 + 135) // 136  # noqa: E731
+    return blk(2 * p.n + mlen) + blk(3 * p.n + mlen)
+
+
+def prelude_ops(param: int, mlen: int) -> int:
+    """Textbook VALU operations of the prelude of one message."""
+    c256, c512 = prelude_compressions(param, mlen)
+    return (c256 * TEXTBOOK_SHA256 + c512 * TEXTBOOK_SHA512
+            + prelude_permutations(param, mlen) * TEXTBOOK_KECCAK)
 
 
 def wots_gather_bytes(param: int) -> int:
@@ -130,10 +179,15 @@ def ops_per_signature(param: int, phase: str | None = None, textbook: bool = Fal
     """VALU lane-operations per signature (ISA counts, or the textbook counts)."""
     c = per_signature(param)
     o256, o512 = (TEXTBOOK_SHA256, TEXTBOOK_SHA512) if textbook else (OPS_SHA256, OPS_SHA512)
+    ok = TEXTBOOK_KECCAK if textbook else OPS_KECCAK
     phases = [phase] if phase else list(c["sha256"])
-    return sum(c["sha256"][ph] * o256 + c["sha512"][ph] * o512 for ph in phases)
+    return sum(c["sha256"][ph] * o256 + c["sha512"][ph] * o512 + c["keccak"][ph] * ok for ph in phases)
 
 
 def compressions_per_signature(param: int) -> tuple[int, int]:
     c = per_signature(param)
     return sum(c["sha256"].values()), sum(c["sha512"].values())
+
+
+def permutations_per_signature(param: int) -> int:
+    return sum(per_signature(param)["keccak"].values())

@@ -57,3 +57,51 @@ def test_prelude_compressions_match_oracle(param, mlen):
     oracle.h_msg(p, r, bytes(n), bytes(n), bytes(mlen))
     c = oracle.counters()
     assert (c["sha256_blocks"], c["sha512_blocks"]) == acc.prelude_compressions(param, mlen)
+
+
+SHAKE_NAMES = {7: "shake-128f", 8: "shake-192f", 9: "shake-256f", 10: "shake-128s", 11: "shake-192s",
+               12: "shake-256s"}
+
+
+@pytest.mark.parametrize("param", sorted(SHAKE_NAMES))
+def test_shake_t_permutations_match_oracle(param):
+    """Keccak-f permutations of T_l (SHAKE sets) equal the oracle's
+    permutation counter; F/H take one."""
+    p = oracle.params(SHAKE_NAMES[param])
+    a = acc.PARAMS[param]
+    for l in (p.len, p.k, 2, 1):
+        oracle.counters_reset()
+        oracle.T(p, bytes(p.n), bytes(32), bytes(l * p.n))
+        want = acc.t_blocks(a, l) if l > 2 else 1
+        assert oracle.counters()["keccak_f"] == want
+
+
+@pytest.mark.parametrize("param", [7, 9, 11])
+@pytest.mark.parametrize("mlen", [0, 32, 40, 88, 89, 200, 1000])
+def test_prelude_permutations_match_oracle(param, mlen):
+    p = oracle.params(SHAKE_NAMES[param])
+    n = p.n
+    oracle.counters_reset()
+    r = oracle.prf_msg(p, bytes(n), bytes(n), bytes(mlen))
+    oracle.h_msg(p, r, bytes(n), bytes(n), bytes(mlen))
+    c = oracle.counters()
+    assert c["keccak_f"] == acc.prelude_permutations(param, mlen)
+    assert (c["sha256_blocks"], c["sha512_blocks"]) == acc.prelude_compressions(param, mlen) == (0, 0)
+
+
+def test_keccak_round_cost():
+    # theta 20 + 10 + 50, rho 48, chi 50, iota 2 per round
+    assert acc.OPS_KECCAK == acc.TEXTBOOK_KECCAK == 24 * 180
+
+
+@pytest.mark.parametrize("sp", [1, 2, 3, 4, 5, 6])
+def test_shake_sets_hash_the_same_trees(sp):
+    """Apart from the blocks of T_l, a SHAKE set makes one permutation per
+    tweakable-hash call where its SHA2 twin makes one compression."""
+    a, b = acc.PARAMS[sp], acc.PARAMS[sp + 6]
+    s, k = acc.per_signature(sp), acc.per_signature(sp + 6)
+    leaves = a.d << a.hp
+    sha_tree = s["sha256"]["tree"] + s["sha512"]["tree"] - leaves * acc.t_blocks(a, a.len)
+    assert k["keccak"]["tree"] - leaves * acc.t_blocks(b, b.len) == sha_tree
+    sha_fors = s["sha256"]["fors"] + s["sha512"]["fors"] - acc.t_blocks(a, a.k)
+    assert k["keccak"]["fors"] - acc.t_blocks(b, b.k) == sha_fors == 3 * (a.k << a.a) - a.k
