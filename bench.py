@@ -168,7 +168,8 @@ def cpu_baseline(name, workloads, seconds=15.0):
 # summaries are in profiles/.  Absent where not measured for the current
 # kernel.
 TRAFFIC = {  # (param, kernel) -> bytes per launch
-    (1, "k_fused"): (195083 * 2 + 1214199) * 1024,
+    (1, "k_fused"): (195253 * 2 + 1213971) * 1024,
+    (7, "k_fused"): (198265 * 2 + 1208880) * 1024,
     (2, "k_tree"): (433164 * 2 + 2611460) * 1024,
     (3, "k_tree"): (1172762 * 2 + 4684838) * 1024,
 }
@@ -254,14 +255,19 @@ def roofline(param, res):
     achieved = ops / avg_s / 1e12
     peak = acc.VALU_PEAK_OPS / 1e12
     c = acc.per_signature(param)
+    units = {h: int(sum(c[h][p] * scale.get(p, 1.0) for p in parts) * per_launch_msgs)
+             for h in ("sha256", "sha512", "keccak") if sum(c[h].values())}
     return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": round(peak, 3),
             "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
             "traffic": TRAFFIC.get((param, kernel)),
             "avg_launch_ms": round(ms / launches, 4),
-            "units_per_launch": {h: int(sum(c[h][p] * scale.get(p, 1.0) for p in parts) * per_launch_msgs)
-                                 for h in ("sha256", "sha512", "keccak") if sum(c[h].values())},
+            "units_per_launch": units,
             "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512, "keccak": acc.OPS_KECCAK},
-            "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4)}
+            "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4),
+            # the same work at the rate each hash's instruction mix reaches in
+            # isolation (calibration probe): 1.0 = as fast as that mix runs
+            "mix_ceiling_frac": round(acc.mix_ceiling_seconds(units) / avg_s, 4),
+            "single_rate_frac": round(ops / avg_s / acc.VALU_SINGLE_RATE_OPS, 4)}
 
 
 def phase_rooflines(param, res, msg_bytes=32):
@@ -281,8 +287,11 @@ def phase_rooflines(param, res, msg_bytes=32):
         if ph in ("fors", "tree", "fused"):
             parts = ("fors", "tree") if ph == "fused" else (ph,)
             ops = sum(acc.ops_per_signature(param, p) * scale.get(p, 1.0) for p in parts) * msgs
+            units = {h: sum(c[h][p] * scale.get(p, 1.0) for p in parts) * msgs
+                     for h in ("sha256", "sha512", "keccak")}
             out[ph] = {"bound": "alu", "achieved": round(ops / s / 1e12, 3), "unit": "TOP/s",
-                       "frac": round(ops / s / peak_ops, 4)}
+                       "frac": round(ops / s / peak_ops, 4),
+                       "mix_ceiling_frac": round(acc.mix_ceiling_seconds(units) / s, 4)}
         elif ph == "prelude":
             ops = acc.prelude_ops(param, msg_bytes) * msgs
             out[ph] = {"bound": "alu (one lane per message)", "achieved": round(ops / s / 1e12, 4),

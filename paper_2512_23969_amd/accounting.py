@@ -52,10 +52,33 @@ OPS_SHA256 = 1232
 OPS_SHA512 = 3490
 TEXTBOOK_KECCAK = OPS_KECCAK = 24 * (20 + 10 + 50 + 48 + 50 + 2)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock for 32-bit integer VALU
-# operations at the 2.4 GHz peak engine clock.
+# MI355X VALU issue ceilings for 32-bit integer lane-operations.  A wave64
+# instruction occupies a SIMD for 4 clocks at 16 lanes per clock, but on
+# gfx950 the simple operations (v_bitop3, v_xor/or/and/not, v_add/sub,
+# v_lshrrev, v_mov) issue faster: the valu_probe program measures up to 1.68
+# wave64 instructions per 4 SIMD clocks for them, against 0.85-0.95 for
+# v_alignbit, v_add3, v_perm, v_lshlrev, v_lshl_add_u64 and the other
+# three-operand or 64-bit forms.  The roofline peak is therefore the
+# dual-rate ceiling, 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T
+# lane-ops/s (the same figure as the published FP32 vector rate counted in
+# FMA lane-operations).
 CUS, SIMDS, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
-VALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK_HZ   # 3.93e13 lane-ops/s
+VALU_SINGLE_RATE_OPS = CUS * SIMDS * LANES * CLOCK_HZ   # 3.93e13 lane-ops/s
+VALU_PEAK_OPS = 2 * VALU_SINGLE_RATE_OPS                 # 7.86e13 lane-ops/s
+
+# Rate each hash's instruction mix reaches with no loads, stores or barriers:
+# valu_probe runs the library's own SHA-256 / SHA-512 compressions and
+# Keccak-f[1600] on every lane of a full grid (lane-ops/s; SHA-256 1399,
+# SHA-512 3417 and Keccak-f 4320 instructions per unit in that program).  The
+# rotates are single-rate v_alignbit (41 % of SHA-256, 32 % of Keccak-f), so
+# these mixes stay near the single-rate line.
+MIX_CEILING_OPS = {"sha256": 39.62e12, "sha512": 39.14e12, "keccak": 42.66e12}
+
+
+def mix_ceiling_seconds(units: dict) -> float:
+    """Shortest time for {hash: units} at the measured mix ceilings."""
+    ops = {"sha256": OPS_SHA256, "sha512": OPS_SHA512, "keccak": OPS_KECCAK}
+    return sum(units[h] * ops[h] / MIX_CEILING_OPS[h] for h in units)
 
 
 @dataclass(frozen=True)

@@ -13,6 +13,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslh.so")
 SOURCES = [os.path.join(CSRC, "api.hip"), os.path.join(CSRC, "serve.hip")]
+# VALU issue-rate calibration program (the roofline's per-unit ceilings)
+PROBE_SRC = os.path.join(CSRC, "valu_probe.hip")
+PROBE = os.path.join(HERE, "valu_probe")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -38,7 +41,21 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str | None
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, out)
+    if out == LIB:
+        build_probe(verbose)
     return out
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the VALU calibration program (an executable, not part of the library)."""
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    tmp = PROBE + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + flags + [PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":

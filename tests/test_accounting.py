@@ -42,7 +42,11 @@ def test_t_blocks_match_oracle_block_counter(param):
 def test_isa_costs_below_textbook():
     assert acc.OPS_SHA256 < acc.TEXTBOOK_SHA256 == 1384
     assert acc.OPS_SHA512 > acc.TEXTBOOK_SHA512 * 0 and acc.TEXTBOOK_SHA512 == 4144
-    assert abs(acc.VALU_PEAK_OPS - 39.3216e12) < 1e9
+    assert abs(acc.VALU_SINGLE_RATE_OPS - 39.3216e12) < 1e9
+    assert abs(acc.VALU_PEAK_OPS - 78.6432e12) < 1e9
+    # the measured mix ceilings lie between the single-rate and dual-rate lines
+    for v in acc.MIX_CEILING_OPS.values():
+        assert acc.VALU_SINGLE_RATE_OPS * 0.95 < v < acc.VALU_PEAK_OPS
 
 
 @pytest.mark.parametrize("param", [1, 2, 3])
