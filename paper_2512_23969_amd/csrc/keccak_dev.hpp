@@ -82,12 +82,17 @@ __device__ __forceinline__ void keccak_round(KLane s[25], uint64_t rc) {
   s[0].hi ^= uint32_t(rc >> 32);
 }
 
+// Rounds 0 and 23 stand outside the loop: once a caller's absorb and
+// squeeze are inlined around them, the zero and constant lanes of round 0
+// fold away and round 23 computes only the lanes the caller reads.
 __device__ __forceinline__ void keccak_f1600(KLane s[25]) {
+  keccak_round(s, 0x0000000000000001ull);  // RC[0]
 #pragma unroll 1
-  for (int ir = 0; ir < 24; ir += 2) {
+  for (int ir = 1; ir < 23; ir += 2) {
     keccak_round(s, kKeccakRC[ir]);
     keccak_round(s, kKeccakRC[ir + 1]);
   }
+  keccak_round(s, 0x8000000080008008ull);  // RC[23]
 }
 
 // XOR big-endian message word q of a block into the state.
