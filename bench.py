@@ -169,7 +169,7 @@ def cpu_baseline(name, workloads, seconds=15.0):
 # kernel.
 TRAFFIC = {  # (param, kernel) -> bytes per launch
     (1, "k_fused"): (195253 * 2 + 1213971) * 1024,
-    (7, "k_fused"): (198265 * 2 + 1208880) * 1024,
+    (7, "k_tree"): (199082 * 2 + 1197261) * 1024,
     (2, "k_tree"): (433164 * 2 + 2611460) * 1024,
     (3, "k_tree"): (1172762 * 2 + 4684838) * 1024,
 }

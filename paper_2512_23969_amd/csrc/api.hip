@@ -46,6 +46,7 @@ constexpr int kSets = 12;  // parameter sets 1..12 (slh.h SLH_SHA2_*, SLH_SHAKE_
 // SHA2 set with the same shape (n, h, d, a, k): ids 7..12 are the SHAKE
 // counterparts of ids 1..6.
 constexpr uint32_t shape_of(uint32_t param) { return (param - 1) % 6 + 1; }
+constexpr int kBranches = 3;  // branch streams per context
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -107,8 +108,12 @@ struct slh_ctx {
   hipEvent_t done = nullptr;   // end of the last call's GPU work
   bool pending = false;
   hipStream_t cap_stream = nullptr;          // stream graphs are captured on
-  hipStream_t branch[kSets + 1] = {};
-  hipEvent_t fork = nullptr, join[kSets + 1] = {};
+  // concurrent branches of a mixed fused batch: the g-th parameter set with
+  // work runs on branch[g % kBranches].  A few streams per context, not one
+  // per set: a process has only a few hardware queues, and more streams
+  // make the busy ones of different contexts (server lanes) share queues.
+  hipStream_t branch[kBranches] = {};
+  hipEvent_t fork = nullptr, join[kBranches] = {};
   std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
   // optional per-phase timing: event pairs around every kernel launch
   bool profile = false;
@@ -497,11 +502,13 @@ int enqueue_all(slh_ctx* c, const size_t* per, const size_t* start, const size_t
   for (int p = 1; p <= kSets; p++) groups += per[p] ? 1 : 0;
   const bool branches = (mode & SLH_MODE_FUSED) && groups > 1;
   if (branches) HIPCHK(c, hipEventRecord(c->fork, s));
+  int g = 0;
   for (int p = 1; p <= kSets; p++) {
     if (!per[p]) continue;
     hipStream_t b = s;
+    const int br = g++ % kBranches;
     if (branches) {
-      b = c->branch[p];
+      b = c->branch[br];
       HIPCHK(c, hipStreamWaitEvent(b, c->fork, 0));
     }
     const int rc = with_set(uint32_t(p), [&](auto id) {
@@ -510,8 +517,8 @@ int enqueue_all(slh_ctx* c, const size_t* per, const size_t* start, const size_t
     });
     if (rc) return rc;
     if (branches) {
-      HIPCHK(c, hipEventRecord(c->join[p], b));
-      HIPCHK(c, hipStreamWaitEvent(s, c->join[p], 0));
+      HIPCHK(c, hipEventRecord(c->join[br], b));
+      HIPCHK(c, hipStreamWaitEvent(s, c->join[br], 0));
     }
   }
   return SLH_OK;
@@ -696,9 +703,9 @@ int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
   if (e == hipSuccess) e = hipMemset(c->dstats, 0, 2 * sizeof(unsigned long long));
   // all streams at the default priority
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
-  for (int p = 1; p <= kSets && e == hipSuccess; p++) {
-    e = hipStreamCreateWithFlags(&c->branch[p], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[p], hipEventDisableTiming);
+  for (int b = 0; b < kBranches && e == hipSuccess; b++) {
+    e = hipStreamCreateWithFlags(&c->branch[b], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[b], hipEventDisableTiming);
   }
   if (e != hipSuccess) {
     slh_ctx_destroy(c);
@@ -715,10 +722,11 @@ int slh_ctx_destroy(slh_ctx* c) {
   if (c->pending) (void)hipEventSynchronize(c->done);
   (void)hipDeviceSynchronize();
   drop_graphs(c);
-  for (int p = 0; p <= kSets; p++) {
+  for (int p = 0; p <= kSets; p++)
     if (c->ws[p]) (void)hipFree(c->ws[p]);
-    if (c->branch[p]) (void)hipStreamDestroy(c->branch[p]);
-    if (c->join[p]) (void)hipEventDestroy(c->join[p]);
+  for (int b = 0; b < kBranches; b++) {
+    if (c->branch[b]) (void)hipStreamDestroy(c->branch[b]);
+    if (c->join[b]) (void)hipEventDestroy(c->join[b]);
   }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->keys) (void)hipFree(c->keys);
