@@ -175,7 +175,7 @@ TRAFFIC = {  # (param, kernel) -> bytes per launch
 }
 
 
-def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0):
+def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lanes=4):
     """Serving workload: n requests, parameter set 50/30/20 % 128f/192f/256f,
     256 device-resident keys (128/77/51), log-normal message lengths (median
     256 B, 32 B - 16 KiB), random bytes.  First all requests at time 0 (the
@@ -191,7 +191,7 @@ def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0):
     kidx = [k for _, k, _ in reqs]
     msgs = [m for _, _, m in reqs]
     log("serve: %d requests generated in %.1f s" % (n, time.perf_counter() - t0))
-    srv = slh.Server(0, lanes=4, max_batch=4096, max_wait_us=2000, mode=slh.MODES[mode],
+    srv = slh.Server(0, lanes=lanes, max_batch=4096, max_wait_us=2000, mode=slh.MODES[mode],
                      cache_layers=cache_layers)
     slots = {}
     sks = {}
@@ -339,11 +339,18 @@ def main():
     ap.add_argument("--serve-mode", default="fused", choices=["plain", "fused", "dedup", "fused-dedup"])
     ap.add_argument("--serve-cache-layers", type=int, default=0,
                     help="upper hypertree layers cached per key on the server's lanes (dedup modes)")
+    ap.add_argument("--serve-lanes", type=int, default=4, help="in-flight batches of the signing server")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for this process (0 = keep the environment's). The serving leg "
+                         "keeps 4 lanes x 4 streams busy; with 16 hardware queues none of them share one")
     ap.add_argument("--no-serve-dedup", action="store_true",
                     help="skip the second serving run (fused-dedup with 4 cached layers per key)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.hw_queues:
+        # read by the HIP runtime when it initialises, which nothing has done yet
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, args.hw_queues)))
     if args.copy_calib:
         import torch
         src = torch.ones(args.copy_calib, dtype=torch.uint8, device="cuda")
@@ -382,7 +389,8 @@ def main():
         "data": "synthetic (seeded random keys and 32-byte messages)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "batch": res["cfg"]["batch"], "keys": res["cfg"]["keys"], "msg_bytes": 32,
-                   "mode": res["mode"], "tuning": res["tuning"]},
+                   "mode": res["mode"], "tuning": res["tuning"],
+                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
         "compressions_per_s": {"sha256": round(res["sig_per_s"] * c256, 0),
                                "sha512": round(res["sig_per_s"] * c512, 0),
                                "keccak_f": round(res["sig_per_s"] * ckf, 0)},
@@ -425,12 +433,13 @@ def main():
         log("bench: serving")
         rates = [float(x) for x in args.serve_rates.split(",")]
         line["serving"] = serve_bench(slh, workloads, args.serve_n, rates, log, args.serve_mode,
-                                      args.serve_cache_layers)
+                                      args.serve_cache_layers, args.serve_lanes)
         if not args.no_serve_dedup:
             # tree sharing across the requests of a key (within-batch dedup and
             # a per-key cache of the top layers): same bytes, less work
             log("bench: serving with dedup and key cache")
-            line["serving_dedup_cache"] = serve_bench(slh, workloads, args.serve_n, rates, log, "fused-dedup", 4)
+            line["serving_dedup_cache"] = serve_bench(slh, workloads, args.serve_n, rates, log, "fused-dedup", 4,
+                                                      args.serve_lanes)
     if not args.no_cpu:
         log("bench: cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args.workload, workloads, args.cpu_seconds)

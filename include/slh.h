@@ -374,7 +374,13 @@ typedef struct slh_server slh_server;
  *                SLH_MODE_DEDUP), clamped to the set's limit [0 = none]
  * A batch is launched when it is full, when no lane is busy, when its
  * oldest request has waited max_wait_us times the number of busy lanes, or
- * by the min_batch rule. */
+ * by the min_batch rule.
+ * Every lane keeps up to four streams busy (its own and its context's three
+ * branch streams for mixed parameter sets).  The HIP runtime maps a
+ * process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 unless the
+ * environment says otherwise); lanes whose streams share a queue
+ * serialise.  With 4 lanes, GPU_MAX_HW_QUEUES=16 cut the p50 latency at 90 %
+ * of the saturated rate from 16.5 to 5.7 ms on MI355X; 32 was worse than 16. */
 typedef struct {
     uint32_t lanes;
     uint32_t max_batch;
