@@ -184,35 +184,48 @@ __device__ __forceinline__ void thshake_t(const uint32_t* pk_seed, const Adrs& A
   for (int q = 0; q < NW; q++) out[q] = ksqueeze_word(s, q);
 }
 
+// Big-endian word of the message portion starting at byte p, with the SHAKE
+// domain and first padding byte 0x1F at byte mlen (p >= 0).
+__device__ __forceinline__ uint32_t kmsg_word(const uint8_t* msg, uint64_t mlen, int64_t p) {
+  uint32_t w = 0;
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    const int64_t q = p + t;
+    const uint32_t byte = (q < int64_t(mlen)) ? msg[q] : (q == int64_t(mlen) ? 0x1Fu : 0u);
+    w = (w << 8) | byte;
+  }
+  return w;
+}
+
 // Byte string prefix (PW BE words) | msg (mlen bytes) absorbed into SHAKE256
-// and NOUT BE words squeezed (PRF_msg, H_msg; NOUT <= 34).
+// and NOUT BE words squeezed (PRF_msg, H_msg; NOUT <= 34).  A block that lies
+// inside the message at a 4-byte aligned address is read as dwords; the
+// first block (prefix) and the last (padding) word by word.
 template <int PW, int NOUT>
 __device__ void shake256_stream(const uint32_t* prefix, const uint8_t* msg, uint64_t mlen, uint32_t* out) {
+  static_assert(PW < kShakeRateWords, "prefix fits the first block");
   const uint64_t total = 4 * PW + mlen;
   const uint64_t nblk = (total + 1 + 135) / 136;
   KLane s[25];
 #pragma unroll
   for (int i = 0; i < 25; i++) s[i] = KLane{0u, 0u};
   for (uint64_t b = 0; b < nblk; b++) {
+    uint32_t w[kShakeRateWords];
+    const int64_t p0 = int64_t(b) * 136 - 4 * PW;  // message byte at the block's start
+    if (b == 0) {
 #pragma unroll
-    for (int j = 0; j < kShakeRateWords; j++) {
-      const int64_t p = int64_t(b) * 136 + 4 * j;  // byte offset of this word in the input
-      uint32_t w = 0;
-      if (b == 0 && j < PW) {
-        w = prefix[j];
-      } else {
+      for (int j = 0; j < kShakeRateWords; j++) w[j] = j < PW ? prefix[j] : kmsg_word(msg, mlen, 4 * j - 4 * PW);
+    } else if (uint64_t(p0) + 136 <= mlen && (reinterpret_cast<uintptr_t>(msg + p0) & 3) == 0) {
+      const uint32_t* q4 = reinterpret_cast<const uint32_t*>(msg + p0);
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-          const int64_t q = p + t - 4 * PW;
-          uint32_t byte = 0;
-          if (q >= 0 && q < int64_t(mlen)) byte = msg[q];
-          else if (uint64_t(p + t) == total) byte = 0x1F;
-          if (b == nblk - 1 && j == kShakeRateWords - 1 && t == 3) byte |= 0x80;
-          w = (w << 8) | byte;
-        }
-      }
-      kabsorb_word(s, j, w);
+      for (int j = 0; j < kShakeRateWords; j++) w[j] = __builtin_bswap32(q4[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kShakeRateWords; j++) w[j] = kmsg_word(msg, mlen, p0 + 4 * j);
     }
+    if (b == nblk - 1) w[kShakeRateWords - 1] |= 0x00000080u;  // last padding bit at byte 135
+#pragma unroll
+    for (int j = 0; j < kShakeRateWords; j++) kabsorb_word(s, j, w[j]);
     keccak_f1600(s);
   }
 #pragma unroll

@@ -103,7 +103,7 @@ def test_mixed_batch_lengths_and_keys(slh, ctx):
     assert alone[0] == got[5]
 
 
-@pytest.mark.parametrize("param", [1, 3])
+@pytest.mark.parametrize("param", [1, 3, 7, 9])
 def test_unaligned_message_offsets(slh, ctx, param):
     seed = workloads.key_seed(param, 3)
     pk, sk = oracle_keys(param, [seed])[0]

@@ -122,3 +122,25 @@ def test_replay_rejects_bad_requests(slh, keyset):
             srv.replay(bad, blob)
         sigs, lat, st = srv.replay(reqs, blob)  # still serves afterwards
         assert st["completed"] == 2
+
+
+def test_serving_mixed_sha2_and_shake(slh):
+    """SHA2 and SHAKE keys of the fast and small sets in one served trace,
+    several batches in flight: every signature equals the oracle's."""
+    params = [1, 7, 2, 8, 9, 3, 10, 4, 7, 1] * 4
+    keys = {p: slh.keygen(p, workloads.key_seed(p, 60)) for p in sorted(set(params))}
+    rng = np.random.default_rng(61)
+    msgs = [rng.bytes(int(rng.integers(0, 400))) for _ in params]
+    with slh.Server(0, lanes=3, max_batch=8, max_wait_us=200) as srv:
+        slots = {p: srv.add_keys(p, [keys[p][1]]) for p in keys}
+        ks = [slots[p] for p in params]
+        arr = np.cumsum(np.random.default_rng(62).exponential(1e-4, size=len(params)))
+        reqs, blob = slh.trace(params, ks, msgs, arr)
+        sigs, lat, st = srv.replay(reqs, blob)
+        print("serve stats", st, flush=True)
+        assert st["completed"] == len(params) and st["launches"] >= 2
+        served = [sigs[int(r["sig_off"]):int(r["sig_off"]) + slh.sizes(int(r["param"]))["sig_bytes"]].tobytes()
+                  for r in reqs]
+    want = oracle_sign_many([(p, keys[p][1], m) for p, m in zip(params, msgs)])
+    for i, (g, w) in enumerate(zip(served, want)):
+        assert g == w, "req %d (%s, %d B): %s" % (i, NAMES[params[i]], len(msgs[i]), describe_diff(params[i], g, w))
