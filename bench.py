@@ -157,9 +157,16 @@ def cpu_baseline(name, workloads, seconds=15.0):
             list(ex.map(lambda m: oracle.sign(p, m, sk), chunk))
             done += len(chunk)
     el = time.perf_counter() - t0
+    # one thread on the following messages, for about a tenth of the time
+    one, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < seconds / 10 and one < 64:
+        oracle.sign(p, msgs[(done + one) % len(msgs)], sk)
+        one += 1
+    el1 = time.perf_counter() - t1
     return {"value": done / el, "unit": "signatures/s", "cores": threads, "kind": "oracle",
             "sample": "first %d messages of the %s workload, key 0, %d host threads, %.1f s"
-                      % (done, name, threads, el)}
+                      % (done, name, threads, el),
+            "single_thread": {"value": one / el1, "sample": "%d messages, 1 thread, %.1f s" % (one, el1)}}
 
 
 # HBM bytes per launch of the dominant kernel at batch 4096, from rocprofv3
