@@ -160,7 +160,10 @@ def test_invalid_arguments(slh, ctx):
         "sig out of range": [(1, slot, 0, 4, sigb + 16)],
         "sig misaligned": [(1, slot, 0, 4, 8)],
         "overlap": [(1, slot, 0, 4, 0), (1, slot, 0, 4, 16)],
-        "bad param": [(5, slot, 0, 4, 0)],
+        "bad param": [(13, slot, 0, 4, 0)],
+        "param zero": [(0, slot, 0, 4, 0)],
+        "set of another shape": [(5, slot, 0, 4, 0)],
+        "same shape, other hash": [(7, slot, 0, 4, 0)],
     }
     for name, rows in cases.items():
         items = np.array(rows, dtype=slh.ITEM_DTYPE)
@@ -171,6 +174,21 @@ def test_invalid_arguments(slh, ctx):
     assert bool((d_s == 7).all()), "nothing may be written on EINVAL"
     with pytest.raises(slh.SlhError):
         ctx.sign_batch(np.array([(1, slot, 0, 4, 0)], dtype=slh.ITEM_DTYPE), d_m, d_s, mode=99)
+
+
+def test_empty_batches(slh, ctx):
+    """Zero requests: signing, verification and the external interface
+    return OK and write nothing."""
+    import torch
+    d_m = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    d_s = torch.full((64,), 5, dtype=torch.uint8, device="cuda")
+    for mode in ("plain", "fused", "graph-dedup"):
+        ctx.sign_batch(np.zeros(0, dtype=slh.ITEM_DTYPE), d_m, d_s, mode=slh.MODES[mode])
+    ctx.sign_batch_ext(np.zeros(0, dtype=slh.ITEM_EXT_DTYPE), d_m, d_s)
+    res = torch.full((4,), -1, dtype=torch.int32, device="cuda")
+    ctx.verify_batch(np.zeros(0, dtype=slh.VERIFY_DTYPE), d_m, d_s, d_m, res)
+    torch.cuda.synchronize()
+    assert bool((d_s == 5).all()) and bool((res == -1).all())
 
 
 def test_repeat_determinism(slh, ctx):
