@@ -265,8 +265,9 @@ typedef struct {
 } slh_verify_item;
 
 /* Verify a batch (Algorithm 20 per item) on the context's GPU: 16 lanes per
- * signature, 16 signatures per workgroup, the WOTS+ chains of each layer
- * balanced over the 16 lanes.  results (device, count int32) receives 1 for a
+ * signature (32 when a parameter set has at most 2048 items in the batch),
+ * the WOTS+ chains of each layer balanced over the signature's lanes.
+ * results (device, count int32) receives 1 for a
  * valid signature and 0 otherwise, in item order.  Asynchronous on `stream`
  * like slh_sign_batch.  Errors: SLH_EINVAL (nothing launched), SLH_ENOMEM,
  * SLH_EDEVICE. */

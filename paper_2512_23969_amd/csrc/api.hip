@@ -663,7 +663,7 @@ int verify_impl(const uint8_t* msg, size_t msg_len, const uint8_t* sig, const ui
   if (e == hipSuccess) e = hipMemcpy(d_sig, sig, Q::sig_bytes, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_pk, pk, 2 * Q::n, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((k_verify<ID>), dim3(1), dim3(kVerifyThreads), 0, 0,
+    hipLaunchKernelGGL((k_verify<ID, kVerifyGroupWide>), dim3(1), dim3(kVerifyThreads), 0, 0,
                        reinterpret_cast<const VerifyItem*>(d_items), 1u, d_msg, d_sig, d_pk, d_res);
     e = hipGetLastError();
   }
@@ -1194,8 +1194,17 @@ int slh_verify_batch(slh_ctx* c, const slh_verify_item* items, uint32_t count, c
     if (!per[p]) continue;
     with_set(uint32_t(p), [&](auto id) {
       constexpr int ID = decltype(id)::value;
-      hipLaunchKernelGGL((k_verify<ID>), dim3(uint32_t((per[p] + kVerifySigs - 1) / kVerifySigs)),
-                         dim3(kVerifyThreads), 0, s, d + start[p], uint32_t(per[p]), msgs, sigs, pks, results);
+      // 16 lanes per signature give 1024 signatures one wave per SIMD; below
+      // kVerifyWideMax signatures 32 lanes each keep more of the chip busy
+      if (per[p] <= kVerifyWideMax) {
+        constexpr uint32_t sigs_per_wg = kVerifyThreads / kVerifyGroupWide;
+        hipLaunchKernelGGL((k_verify<ID, kVerifyGroupWide>), dim3(uint32_t((per[p] + sigs_per_wg - 1) / sigs_per_wg)),
+                           dim3(kVerifyThreads), 0, s, d + start[p], uint32_t(per[p]), msgs, sigs, pks, results);
+      } else {
+        constexpr uint32_t sigs_per_wg = kVerifyThreads / kVerifyGroup;
+        hipLaunchKernelGGL((k_verify<ID, kVerifyGroup>), dim3(uint32_t((per[p] + sigs_per_wg - 1) / sigs_per_wg)),
+                           dim3(kVerifyThreads), 0, s, d + start[p], uint32_t(per[p]), msgs, sigs, pks, results);
+      }
       return 0;
     });
   }

@@ -1068,16 +1068,17 @@ __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restric
 }
 
 // ------------------------------------------------------------------ verify
-// Batched verification (FIPS 205 Algorithm 20).  A group of kVerifyGroup
-// lanes (a quarter of a wave) verifies one signature; a workgroup of 256
-// lanes holds 16 signatures that go through the same phases together:
+// Batched verification (FIPS 205 Algorithm 20).  A group of G lanes (16: a
+// quarter of a wave; 32 for batches too small to give every SIMD a wave at
+// 16) verifies one signature; a workgroup of 256 lanes holds 256 / G
+// signatures that go through the same phases together:
 //   setup   : the group's first lane derives the per-key chaining values,
 //             recomputes the digest (H_msg) and splits it;
-//   FORS    : one lane per FORS tree (trees g, g + 16, ...) climbs from the
+//   FORS    : one lane per FORS tree (trees g, g + G, ...) climbs from the
 //             revealed secret value to the root; the first lane runs T_k;
 //   layers  : per hypertree layer, the len WOTS+ chains are spread over the
-//             16 lanes, longest first in a snake order (rank r goes to lane
-//             r mod 16, reversed on odd rounds), so that every lane has about
+//             G lanes, longest first in a snake order (rank r goes to lane
+//             r mod G, reversed on odd rounds), so that every lane has about
 //             the same number of F steps; each lane works through its chains
 //             step by step; the first lane then runs T_len and climbs the
 //             h' authentication levels to the layer's root.
@@ -1086,8 +1087,9 @@ struct VerifyItem {
   uint64_t msg_off, msg_len, sig_off, pk_off, res_idx;
 };
 constexpr int kVerifyThreads = 256;
-constexpr int kVerifyGroup = 16;
-constexpr int kVerifySigs = kVerifyThreads / kVerifyGroup;
+constexpr int kVerifyGroup = 16;      // lanes per signature for large batches
+constexpr int kVerifyGroupWide = 32;  // lanes per signature up to kVerifyWideMax signatures
+constexpr uint32_t kVerifyWideMax = 2048;
 
 __device__ __forceinline__ uint32_t load_be32(const uint8_t* p) {
   return (uint32_t(p[0]) << 24) | (uint32_t(p[1]) << 16) | (uint32_t(p[2]) << 8) | uint32_t(p[3]);
@@ -1106,13 +1108,13 @@ __device__ __forceinline__ uint32_t verify_digit(const uint32_t* M, uint32_t csu
   return (csum >> (12 - 4 * (c - P<ID>::len1))) & 15u;
 }
 
-template <int ID>
+template <int ID, int G>
 __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __restrict__ items,
                                                           uint32_t count, const uint8_t* msgs,
                                                           const uint8_t* sigs, const uint8_t* pks,
                                                           int* results) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a, G = kVerifyGroup;
+  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a, kVerifySigs = kVerifyThreads / G;
   constexpr int SLOTS = (LEN + G - 1) / G;
   static_assert(KT <= 64, "FORS indices per signature");
   __shared__ uint32_t s_vals[kVerifySigs][(LEN > KT ? LEN : KT) * NW];
