@@ -317,12 +317,21 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *   keep_chains           1: the TREE phase keeps every value of the signing
  *                         leaves' WOTS+ chains and the WOTS phase gathers the
  *                         signature from them; 0: nothing is kept (less
- *                         memory) and the WOTS phase recomputes the chains */
+ *                         memory) and the WOTS phase recomputes the chains
+ *   split_max_blocks      a batch of this parameter set with at most this
+ *                         many TREE blocks (64 hypertree leaves each) takes
+ *                         the per-phase path with each block's WOTS+ chains
+ *                         split over up to len one-wave workgroups, in every
+ *                         mode: such a batch cannot fill the chip, and the
+ *                         split cuts its latency (0 = default: the number of
+ *                         compute units; SLH_SPLIT_NEVER = never) */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;
     uint32_t keep_chains;
+    uint32_t split_max_blocks;
 } slh_tuning;
+#define SLH_SPLIT_NEVER 0xFFFFFFFFu
 
 /* Set or read the knobs of parameter set `param` on a context.  Setting
  * waits for the context's pending work.  Errors: SLH_EINVAL. */

@@ -76,6 +76,7 @@ struct Tuning {
   uint32_t fg = 0;          // FORS trees per workgroup (0 = default of the set)
   uint32_t wgs_per_cu = 0;  // fused mode: persistent workgroups per CU (0 = occupancy limit)
   uint32_t keep = 1;        // keep signing-leaf chain values for the WOTS gather
+  uint32_t split = 0;       // split_max_blocks (0 = the CU count)
 };
 
 struct GraphKey {
@@ -269,6 +270,7 @@ struct Plan {
   static constexpr uint32_t TPB = kLeavesPerBlock >> Q::unit_hp;  // trees (or units) per TREE block
   size_t n = 0;
   bool fused = false, dedup = false, keep = true;
+  uint32_t parts = 0;  // > 0: TREE blocks' chains split over this many workgroups (small batches)
   uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0, table = 0;
   size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
   size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, o_troots = 0, o_uroots = 0, total = 0;
@@ -282,6 +284,15 @@ struct Plan {
     const size_t trees = n * Q::d;
     ntb = uint32_t((trees * Q::tree_units + TPB - 1) / TPB);
     nfg = uint32_t((n * Q::k * Q::fors_units + fg - 1) / fg);
+    // With no more TREE blocks than CUs the batch cannot fill the chip and
+    // its time is one block's chain latency: split each block's chains over
+    // up to len one-wave workgroups, about 8 waves per CU in all (the
+    // per-phase path; the same bytes in every mode).
+    const uint32_t split_max = t.split == SLH_SPLIT_NEVER ? 0u : (t.split ? t.split : uint32_t(cus));
+    if (ntb <= split_max) {
+      parts = std::max<uint32_t>(1u, std::min<uint32_t>(Q::len, 8u * uint32_t(cus) / std::max(1u, ntb)));
+      fused = false;
+    }
     if (fused) {
       const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg));
       grid = std::min<uint32_t>(per_cu * uint32_t(cus), ntb + nfg);
@@ -430,9 +441,15 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, const DevItem* h_items, const u
       // at most kMaxTreeBlocks blocks per launch, reusing the staging
       for (uint32_t b0 = 0; b0 < pl.ntb; b0 += kMaxTreeBlocks) {
         const uint32_t nb = std::min(kMaxTreeBlocks, pl.ntb - b0), first = b0 * Plan<ID>::TPB;
-        hipLaunchKernelGGL((k_tree<ID, kSignTrees>), dim3(nb), dim3(kTreeThreads), 0, s, c->keys, recs,
-                           std::min(units - first, nb * Plan<ID>::TPB), sigs, stage, spill, 0u, nullptr, db.ulist,
-                           db.ucount, db.lown, db.nodes, first, uroots);
+        const uint32_t nu = std::min(units - first, nb * Plan<ID>::TPB);
+        if (pl.parts) {
+          hipLaunchKernelGGL((k_tree_chains<ID, kSignTrees>), dim3(nb, pl.parts), dim3(64), 0, s, c->keys, recs, nu,
+                             sigs, stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, first, uroots);
+          hipLaunchKernelGGL((k_tree_finish<ID, kSignTrees>), dim3(nb), dim3(64), 0, s, c->keys, recs, nu, sigs,
+                             stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, first, uroots);
+        } else
+          hipLaunchKernelGGL((k_tree<ID, kSignTrees>), dim3(nb), dim3(kTreeThreads), 0, s, c->keys, recs, nu, sigs,
+                             stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, first, uroots);
       }
       if constexpr (Q::tree_units > 1)
         hipLaunchKernelGGL((k_tree_top<ID, kSignTrees>), dim3((trees + 63) / 64), dim3(64), 0, s, c->keys, recs,
@@ -554,8 +571,11 @@ int keygen_impl(const uint8_t* seed, uint8_t* pk, uint8_t* sk) {
   e = hipMemcpy(dk, &hk, sizeof hk, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_key_midstates, dim3(1), dim3(64), 0, 0, dk, 0u, 1u);
-    hipLaunchKernelGGL((k_tree<ID, kKeygenTree>), dim3(UT), dim3(kTreeThreads), 0, 0, dk, nullptr, UT, nullptr,
-                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr, nullptr, 0u, uroots);
+    // one tree: its chains split over len one-wave workgroups per unit
+    hipLaunchKernelGGL((k_tree_chains<ID, kKeygenTree>), dim3(UT, Q::len), dim3(64), 0, 0, dk, nullptr, UT, nullptr,
+                       stage, nullptr, 0u, root, nullptr, nullptr, nullptr, 0u, uroots);
+    hipLaunchKernelGGL((k_tree_finish<ID, kKeygenTree>), dim3(UT), dim3(64), 0, 0, dk, nullptr, UT, nullptr, stage,
+                       nullptr, 0u, root, nullptr, nullptr, nullptr, nullptr, 0u, uroots);
     if constexpr (UT > 1)
       hipLaunchKernelGGL((k_tree_top<ID, kKeygenTree>), dim3(1), dim3(64), 0, 0, dk, nullptr, 1u, nullptr, 0u, root,
                          0u, uroots);
@@ -1227,6 +1247,7 @@ int slh_ctx_set_tuning(slh_ctx* c, uint32_t param, const slh_tuning* t) {
   c->tune[param].fg = fg;
   c->tune[param].wgs_per_cu = t->wgs_per_cu;
   c->tune[param].keep = t->keep_chains;
+  c->tune[param].split = t->split_max_blocks;
   return SLH_OK;
 }
 
@@ -1236,6 +1257,7 @@ int slh_ctx_get_tuning(const slh_ctx* c, uint32_t param, slh_tuning* t) {
   t->fors_trees_per_group = c->tune[param].fg;
   t->wgs_per_cu = c->tune[param].wgs_per_cu;
   t->keep_chains = c->tune[param].keep;
+  t->split_max_blocks = c->tune[param].split;
   return SLH_OK;
 }
 

@@ -614,7 +614,7 @@ struct TreeList {
   __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : first + i; }
 };
 
-template <int ID, int KIND>
+template <int ID, int KIND, bool SPLIT = false>
 __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
@@ -640,10 +640,12 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
   } else if (J.spill && int32_t(kp) == J.sign_leaf) {
     keep = J.spill;
   }
-  // wave 0: chunks 0 .. W0-1; waves 1..3: chunks W0 + (wave - 1) + 3 i
-  const int c0 = wave == 0 ? 0 : W0 + wave - 1;
-  const int cend = wave == 0 ? W0 : LEN;
-  const int cstep = wave == 0 ? 1 : 3;
+  // a four-wave block: wave 0 chunks 0 .. W0-1, waves 1..3 chunks
+  // W0 + (wave - 1) + 3 i; a split block (one wave per workgroup, part
+  // blockIdx.y of gridDim.y): chunks part, part + parts, ...
+  const int c0 = SPLIT ? int(blockIdx.y) : (wave == 0 ? 0 : W0 + wave - 1);
+  const int cend = SPLIT ? LEN : (wave == 0 ? W0 : LEN);
+  const int cstep = SPLIT ? int(gridDim.y) : (wave == 0 ? 1 : 3);
   for (int c = c0; c < cend; c += cstep) {
     uint32_t x[NW];
     wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keep ? keep + c * 16 * NW : nullptr, x);
@@ -731,6 +733,36 @@ __global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict_
   __syncthreads();
   if ((threadIdx.x >> 6) == 0)
     tree_finish<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
+}
+
+// The two phases of k_tree as separate launches, for batches too small to
+// spread their blocks over the CUs: k_tree_chains runs the chains of block
+// blockIdx.x split over gridDim.y one-wave workgroups (part q takes chunks
+// q, q + gridDim.y, ...), so one block's chains run on many CUs at once;
+// k_tree_finish (one wave per block) then runs T_len and the XMSS levels.
+template <int ID, int KIND>
+__global__ __launch_bounds__(64) void k_tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                                    uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ stage,
+                                                    uint32_t* __restrict__ spill, uint32_t key_slot,
+                                                    uint32_t* root_out, const uint32_t* ulist,
+                                                    const uint32_t* ucount, const uint32_t* lown, uint32_t first,
+                                                    uint32_t* uroots) {
+  const TreeList tl{ulist, ucount, lown, first, uroots};
+  if (blockIdx.x * (kLeavesPerBlock >> P<ID>::unit_hp) >= tl.count(ntrees)) return;
+  uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
+  tree_chains<ID, KIND, true>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl);
+}
+template <int ID, int KIND>
+__global__ __launch_bounds__(64) void k_tree_finish(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
+                                                    uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ stage,
+                                                    uint32_t* __restrict__ spill, uint32_t key_slot,
+                                                    uint32_t* root_out, const uint32_t* ulist,
+                                                    const uint32_t* ucount, const uint32_t* lown, uint32_t* nodes,
+                                                    uint32_t first, uint32_t* uroots) {
+  const TreeList tl{ulist, ucount, lown, first, uroots};
+  if (blockIdx.x * (kLeavesPerBlock >> P<ID>::unit_hp) >= tl.count(ntrees)) return;
+  const uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
+  tree_finish<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
 }
 
 // XMSS trees built in units (the small sets): one lane per tree combines the

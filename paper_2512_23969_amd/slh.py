@@ -43,7 +43,7 @@ class SlhError(RuntimeError):
 
 class slh_tuning(ctypes.Structure):
     _fields_ = [("fors_trees_per_group", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
-                ("keep_chains", ctypes.c_uint32)]
+                ("keep_chains", ctypes.c_uint32), ("split_max_blocks", ctypes.c_uint32)]
 
 
 class slh_serve_config(ctypes.Structure):
@@ -65,6 +65,7 @@ ITEM_EXT_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<
                            ("prehash", "<u4")])
 assert ITEM_EXT_DTYPE.itemsize == 56
 RND_NONE = 0xFFFFFFFFFFFFFFFF
+SPLIT_NEVER = 0xFFFFFFFF  # slh_tuning.split_max_blocks: never split small batches
 PREHASH_NONE, PREHASH_SHA256, PREHASH_SHA512 = 0, 1, 2
 
 VERIFY_DTYPE = np.dtype([("param", "<u4"), ("pad", "<u4"), ("msg_off", "<u8"), ("msg_len", "<u8"),
@@ -216,8 +217,8 @@ class Context:
         _check(lib.slh_ctx_cache_keys(self.h, int(first_slot), int(count), int(layers)), self.h)
 
     def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0,
-                   keep_chains: int = 1):
-        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains)
+                   keep_chains: int = 1, split_max_blocks: int = 0):
+        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks)
         _check(lib.slh_ctx_set_tuning(self.h, int(param), ctypes.byref(t)), self.h)
 
     def get_tuning(self, param: int) -> dict:
@@ -407,8 +408,9 @@ class Server:
         self._check(lib.slh_serve_add_keys(self.h, int(param), blob, len(blob) // skb, ctypes.byref(first)))
         return first.value
 
-    def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0, keep_chains: int = 1):
-        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains)
+    def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0, keep_chains: int = 1,
+                   split_max_blocks: int = 0):
+        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks)
         self._check(lib.slh_serve_set_tuning(self.h, int(param), ctypes.byref(t)))
 
     def replay(self, reqs: np.ndarray, msgs: bytes, skip: int = 0):

@@ -72,10 +72,12 @@ def test_dedup_matches_oracle(slh, param):
     with slh.Context(0) as ctx:
         first = ctx.add_keys(param, [sk for _, sk in keys])
         d = oracle.params(NAMES[param]).d
-        for keep in (1, 0):
-            ctx.set_tuning(param, slh.FORS_GROUPS[param][1], 0, keep)
+        # split 0: this small batch takes the split per-phase path; never:
+        # the requested kernels (the fused one in the fused modes)
+        for keep, split in ((1, 0), (1, slh.SPLIT_NEVER), (0, slh.SPLIT_NEVER)):
+            ctx.set_tuning(param, slh.FORS_GROUPS[param][1], 0, keep, split)
             for mode in DEDUP_MODES:
-                print(NAMES[param], mode, "keep", keep, flush=True)
+                print(NAMES[param], mode, "keep", keep, "split", split, flush=True)
                 ctx.dedup_stats(reset=True)
                 got = slh.sign_messages(ctx, [param] * len(msgs), [first + k for k in kidx], msgs,
                                         slh.MODES[mode])

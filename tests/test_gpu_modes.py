@@ -35,12 +35,17 @@ def _check(param, got, want, what):
         assert g == w, "%s item %d: %s" % (what, i, describe_diff(param, g, w))
 
 
+@pytest.mark.parametrize("split", [0, "never"])
 @pytest.mark.parametrize("mode", ["fused", "graph", "graph-plain"])
-def test_modes_single_set(slh, keys, mode):
+def test_modes_single_set(slh, keys, mode, split):
+    """Small batches take the split per-phase path by default; with the split
+    off they run the requested kernels (the fused one in fused modes)."""
     with slh.Context(0) as ctx:
         for p in (1, 2, 3):
             pk, sk = keys[p]
             slot = ctx.add_keys(p, sk)
+            if split == "never":
+                ctx.set_tuning(p, split_max_blocks=slh.SPLIT_NEVER)
             msgs = workloads.messages(60 + p, 5 + p, 32)
             print(mode, NAMES[p], flush=True)
             got = slh.sign_messages(ctx, [p] * len(msgs), [slot] * len(msgs), msgs, slh.MODES[mode])
@@ -87,14 +92,14 @@ def test_every_tuning_variant(slh, keys, param):
         slot = ctx.add_keys(param, sk)
         for fg in slh.FORS_GROUPS[param]:
             for keep in (1, 0):
-                for wpc in (0, 1):
-                    ctx.set_tuning(param, fg, wpc, keep)
+                for wpc, split in ((0, slh.SPLIT_NEVER), (1, slh.SPLIT_NEVER), (0, 0), (0, 1)):
+                    ctx.set_tuning(param, fg, wpc, keep, split)
                     assert ctx.get_tuning(param) == {"fors_trees_per_group": fg, "wgs_per_cu": wpc,
-                                                     "keep_chains": keep}
+                                                     "keep_chains": keep, "split_max_blocks": split}
                     for mode in ("plain", "fused"):
-                        print(NAMES[param], fg, keep, wpc, mode, flush=True)
+                        print(NAMES[param], fg, keep, wpc, split, mode, flush=True)
                         got = slh.sign_messages(ctx, [param] * 7, [slot] * 7, msgs, slh.MODES[mode])
-                        _check(param, got, want, "fg%d keep%d wpc%d %s" % (fg, keep, wpc, mode))
+                        _check(param, got, want, "fg%d keep%d wpc%d split%d %s" % (fg, keep, wpc, split, mode))
 
 
 def test_tuning_rejects_uncompiled_variants(slh):
