@@ -175,10 +175,10 @@ def cpu_baseline(name, workloads, seconds=15.0):
 # summaries are in profiles/.  Absent where not measured for the current
 # kernel.
 TRAFFIC = {  # (param, kernel) -> bytes per launch
-    (1, "k_fused"): (195253 * 2 + 1213971) * 1024,
-    (7, "k_tree"): (199082 * 2 + 1197261) * 1024,
-    (2, "k_tree"): (433164 * 2 + 2611460) * 1024,
-    (3, "k_tree"): (1172762 * 2 + 4684838) * 1024,
+    (1, "k_fused"): (196340 * 2 + 1213936) * 1024,
+    (2, "k_tree"): (433141 * 2 + 2611425) * 1024,
+    (3, "k_tree"): (1172799 * 2 + 4684870) * 1024,
+    (7, "k_tree"): (199075 * 2 + 1197263) * 1024,
 }
 
 
