@@ -182,6 +182,41 @@ TRAFFIC = {  # (param, kernel) -> bytes per launch
 }
 
 
+def latency_bench(slh, workloads, reps=20):
+    """Small-batch latency: key generation, and one slh_sign_batch call plus
+    synchronisation for batches of 1, 16 and 64 messages of 256 bytes of one
+    set (fused mode; such batches take the split per-phase path), median of
+    `reps` calls after warm-up."""
+    import torch
+    out = {"keygen_ms": {}, "sign_ms": {}}
+    ctx = slh.Context(0)
+    for p in (1, 2, 3, 7):
+        ts = []
+        for i in range(5):
+            t0 = time.perf_counter()
+            slh.keygen(p, workloads.key_seed(p, 2000 + i))
+            ts.append(time.perf_counter() - t0)
+        out["keygen_ms"][slh.NAMES[p]] = round(1e3 * sorted(ts)[2], 3)
+        slot = ctx.add_keys(p, slh.keygen(p, workloads.key_seed(p, 2000))[1])
+        for batch in (1, 16, 64):
+            msgs = workloads.messages(90 + p, batch, 256)
+            items, blob, total = slh.pack_batch([p] * batch, [slot] * batch, msgs)
+            d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+            d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
+            for _ in range(3):
+                ctx.sign_batch(items, d_m, d_s, mode=slh.MODES["fused"])
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                ctx.sign_batch(items, d_m, d_s, mode=slh.MODES["fused"])
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            out["sign_ms"]["%s/%d" % (slh.NAMES[p], batch)] = round(1e3 * sorted(ts)[reps // 2], 3)
+    ctx.close()
+    return out
+
+
 def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lanes=4):
     """Serving workload: n requests, parameter set 50/30/20 % 128f/192f/256f,
     256 device-resident keys (128/77/51), log-normal message lengths (median
@@ -410,6 +445,8 @@ def main():
     if res["dedup"]:
         line["dedup"] = {"trees_per_step": res["dedup"][0], "distinct_trees_per_step": res["dedup"][1]}
     if args.all:
+        log("bench: small-batch latency")
+        line["latency"] = latency_bench(slh, workloads)
         # every batch-4096 workload in the plain per-phase path and in the
         # batched modes (fused persistent kernel; hipGraph-captured pipeline;
         # tree dedup), the small sets at batch 1024 and the SHAKE sets

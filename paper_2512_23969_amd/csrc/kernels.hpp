@@ -812,8 +812,10 @@ __global__ void k_tree_top(const DevKey* __restrict__ keys, WorkRec* __restrict_
 // with the grid, not the batch.  The counter is zeroed by k_prelude of the
 // same batch; every workgroup leaves once the counter passes the end.
 //
-// Waves per SIMD the fused kernel is compiled for (bounds its VGPRs): four
-// for 128f (at most 128 VGPRs, like the plain TREE kernel), three otherwise.
+// Waves per SIMD the fused kernel is compiled for (bounds its VGPRs to 168).
+// Three for every set: a four-wave build (128 VGPRs, a few spills) ran no
+// faster, and the persistent grid gains nothing beyond three workgroups per
+// CU.
 template <int ID>
 struct FusedOcc {
   static constexpr int waves = 3;
