@@ -323,8 +323,8 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *                         the per-phase path with each block's WOTS+ chains
  *                         split over up to len one-wave workgroups, in every
  *                         mode: such a batch cannot fill the chip, and the
- *                         split cuts its latency (0 = default: the number of
- *                         compute units; SLH_SPLIT_NEVER = never) */
+ *                         split cuts its latency (0 = default: 1.5 x the
+ *                         number of compute units; SLH_SPLIT_NEVER = never) */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;

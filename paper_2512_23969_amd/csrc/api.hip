@@ -76,7 +76,7 @@ struct Tuning {
   uint32_t fg = 0;          // FORS trees per workgroup (0 = default of the set)
   uint32_t wgs_per_cu = 0;  // fused mode: persistent workgroups per CU (0 = occupancy limit)
   uint32_t keep = 1;        // keep signing-leaf chain values for the WOTS gather
-  uint32_t split = 0;       // split_max_blocks (0 = the CU count)
+  uint32_t split = 0;       // split_max_blocks (0 = 1.5 x the CU count)
 };
 
 struct GraphKey {
@@ -284,11 +284,13 @@ struct Plan {
     const size_t trees = n * Q::d;
     ntb = uint32_t((trees * Q::tree_units + TPB - 1) / TPB);
     nfg = uint32_t((n * Q::k * Q::fors_units + fg - 1) / fg);
-    // With no more TREE blocks than CUs the batch cannot fill the chip and
-    // its time is one block's chain latency: split each block's chains over
-    // up to len one-wave workgroups, about 8 waves per CU in all (the
-    // per-phase path; the same bytes in every mode).
-    const uint32_t split_max = t.split == SLH_SPLIT_NEVER ? 0u : (t.split ? t.split : uint32_t(cus));
+    // With few TREE blocks the batch cannot fill the chip and its time is
+    // one block's chain latency: split each block's chains over up to len
+    // one-wave workgroups, about 8 waves per CU in all (the per-phase path;
+    // the same bytes in every mode).  Measured on MI355X, the split wins up
+    // to about 1.4 blocks per CU, ties to 2 and loses above.
+    const uint32_t split_max =
+        t.split == SLH_SPLIT_NEVER ? 0u : (t.split ? t.split : 3u * uint32_t(cus) / 2u);
     if (ntb <= split_max) {
       parts = std::max<uint32_t>(1u, std::min<uint32_t>(Q::len, 8u * uint32_t(cus) / std::max(1u, ntb)));
       fused = false;
