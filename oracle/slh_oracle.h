@@ -1,6 +1,6 @@
 /*
  * slh_oracle.h -- plain CPU reference of SPHINCS+ / SLH-DSA signing with the
- * SHA2 "simple" instantiation.
+ * SHA2 and SHAKE "simple" instantiations.
  *
  * TEST INFRASTRUCTURE ONLY.  This library exists so that the tests, the smoke
  * check and the CPU baseline of the benchmark can compare the GPU library
@@ -16,10 +16,12 @@
  *     fors_sign, then d layers of merkle_sign).  The paper reorders that
  *     work for the GPU but computes the same signature.
  *   - The exact arithmetic is the scheme's own: FIPS 205 (SLH-DSA) internal
- *     functions with the SHA2 instantiation of its Section 11.2, SHA-256 and
- *     SHA-512 from FIPS 180-4, HMAC from FIPS 198-1 and MGF1 from RFC 8017.
+ *     functions with the SHA2 instantiation of its Section 11.2 (SHA-256 and
+ *     SHA-512 from FIPS 180-4, HMAC from FIPS 198-1, MGF1 from RFC 8017) or
+ *     the SHAKE instantiation of its Section 11.1 (Keccak-f[1600] and
+ *     SHAKE256 from FIPS 202), for the parameter sets of its Table 2.
  *
- * Readings taken where the paper is silent (each is listed in the design doc):
+ * Readings taken where the paper is silent:
  *   - FIPS 205 internal functions (no context prefix, raw message M).
  *   - FORS indices via base_2b, most-significant bit first.
  *   - n = 24 and n = 32 use SHA-512 for H, T_l, H_msg and PRF_msg; F and PRF

@@ -12,7 +12,7 @@ NAMES = {1: "128f", 2: "192f", 3: "256f", 4: "128s", 5: "192s", 6: "256s",
 
 
 def host_threads() -> int:
-    # the GPU machine gives this process a share of 16 cores; keep within it
+    # at most 16 host threads: the share of host cores a one-GPU machine gives one process
     return max(1, min(16, os.cpu_count() or 1))
 
 
