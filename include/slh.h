@@ -117,7 +117,9 @@ typedef struct slh_ctx slh_ctx;
  *                   (per batch shape, buffers and tuning) and replayed with a
  *                   single hipGraphLaunch; combine with SLH_MODE_FUSED for the
  *                   batched fused pipeline.  Per-phase timing is not recorded
- *                   inside graphs.
+ *                   inside graphs.  A context keeps up to 8 graphs and
+ *                   drops them all when keys are added, tuning changes, or
+ *                   its working memory, staging or tree cache is reallocated.
  *   SLH_MODE_DEDUP  within-batch dedup of XMSS trees (combines with the
  *                   others): messages of one key whose hypertree paths share
  *                   a tree at some layer (FIPS 205 Algorithm 12: the layer's
@@ -186,7 +188,8 @@ int slh_ctx_reserve(slh_ctx *ctx, uint32_t count, uint32_t mode);
  * root of those layers from the cache and only recomputes their WOTS+
  * chains (Algorithm 10 with the cached nodes).  Memory per key:
  * (2^(h' layers) - 1) / (2^h' - 1) trees of (2^(h'+1) - 1) n bytes, outside
- * the context's HBM budget.  layers: 1..6 (128f, 192f), 1..4 (256f).
+ * the context's HBM budget.  layers: 1..6 (128f, 192f and their SHAKE
+ * twins), 1..4 (256f, SHAKE-256f).
  * Synchronous.  Errors: SLH_EINVAL (range outside the table, mixed sets, a
  * key cached already, layers out of range), SLH_ENOMEM, SLH_EDEVICE. */
 int slh_ctx_cache_keys(slh_ctx *ctx, uint32_t first_slot, uint32_t count, uint32_t layers);
@@ -444,7 +447,9 @@ int slh_serve_set_tuning(slh_server *s, uint32_t param, const slh_tuning *t);
  * scheduler at its arrival time, signatures are written to sigs (host,
  * sigs_bytes long) at sig_off, latencies (seconds) to latency_s[i] if not
  * null, and the summary to *stats if not null.  Returns when every request
- * has completed.  Errors: SLH_EINVAL (bad request; nothing is served),
+ * has completed.  Errors: SLH_EINVAL (a request of an unknown set, with a
+ * key slot that is missing or holds another set's key, or outside the
+ * buffers; nothing is served),
  * SLH_EBUSY (online scheduler running), SLH_EDEVICE. */
 int slh_serve_replay(slh_server *s, const slh_serve_request *reqs, uint64_t n, const uint8_t *msgs,
                      uint64_t msgs_bytes, uint8_t *sigs, uint64_t sigs_bytes, double *latency_s,
@@ -453,7 +458,9 @@ int slh_serve_replay(slh_server *s, const slh_serve_request *reqs, uint64_t n, c
 /* Online use: start a scheduler thread, submit requests as they arrive
  * (the message is copied; `tag` identifies the result), poll completed
  * results, stop (waits until every submitted request has completed).
- * slh_serve_submit returns SLH_EBUSY when queue_limit requests wait.
+ * slh_serve_submit returns SLH_EBUSY when queue_limit requests wait, and
+ * SLH_EINVAL (nothing queued) for an unknown set, a key slot that is missing
+ * or holds another set's key, or a message longer than msg_bytes.
  * slh_serve_poll copies up to `max` results: tags[i], the signature at
  * sigs + i * sig_stride (sig_stride >= 49856), latency_s[i] if not null;
  * *n is the number copied.  Submit and poll may be called from any thread. */

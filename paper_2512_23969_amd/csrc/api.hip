@@ -867,6 +867,9 @@ int slh_ctx_add_keys(slh_ctx* c, uint32_t param, const uint8_t* sks, uint32_t co
   if (uint64_t(c->nkeys) + count > (1u << 24)) return fail(c, SLH_EINVAL, "too many keys");
   HIPCHK(c, hipSetDevice(c->device));
   if (c->pending) HIPCHK(c, hipEventSynchronize(c->done));
+  // captured graphs hold the key table's address (which a reallocation
+  // below frees) and working-memory chunks sized for the sets that had keys
+  drop_graphs(c);
   if (c->nkeys + count > c->cap) {
     uint32_t ncap = std::max<uint32_t>(64, c->cap);
     while (ncap < c->nkeys + count) ncap *= 2;

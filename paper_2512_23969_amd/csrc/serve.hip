@@ -42,6 +42,14 @@ uint32_t sig_bytes_of(uint32_t param) {
   return slh_params(param, &s) == SLH_OK ? s.sig_bytes : 0;
 }
 
+// Most upper layers slh_ctx_cache_keys caches for a set: 6 for the fast
+// sets with h' = 3, 4 for those with h' = 4, none for the small sets.
+uint32_t cache_limit(uint32_t param) {
+  slh_sizes z;
+  if (slh_params(param, &z) != SLH_OK) return 0;
+  return z.hp == 3 ? 6u : (z.hp == 4 ? 4u : 0u);
+}
+
 struct Req {
   uint32_t param, slot;
   const uint8_t* msg;   // host bytes (owned by the caller or by `own`)
@@ -76,6 +84,7 @@ struct slh_server {
   int device = 0;
   slh_serve_config cfg{};
   std::vector<Lane> lanes;
+  std::vector<uint32_t> key_param;  // parameter set of every key slot (same on every lane)
   std::string err;
   // scheduler state
   std::deque<Req> pending;
@@ -361,8 +370,8 @@ int slh_serve_add_keys(slh_server* s, uint32_t param, const uint8_t* sks, uint32
     if (rc) return lane_error(s, s->lanes[i], rc);
     if (i == 0) first = f;
     else if (f != first) return sfail(s, SLH_EDEVICE, "lane key tables diverged");
-    if (s->cfg.cache_layers) {
-      const uint32_t lim = param == SLH_SHA2_256F ? 4u : 6u;
+    const uint32_t lim = cache_limit(param);
+    if (s->cfg.cache_layers && lim) {
       rc = slh_ctx_cache_keys(s->lanes[i].ctx, f, count, std::min(s->cfg.cache_layers, lim));
       if (rc) return lane_error(s, s->lanes[i], rc);
     }
@@ -370,6 +379,7 @@ int slh_serve_add_keys(slh_server* s, uint32_t param, const uint8_t* sks, uint32
     rc = slh_ctx_reserve(s->lanes[i].ctx, s->cfg.max_batch, s->cfg.mode);
     if (rc) return lane_error(s, s->lanes[i], rc);
   }
+  s->key_param.resize(size_t(first) + count, param);
   *first_slot = first;
   return SLH_OK;
 }
@@ -393,6 +403,8 @@ int slh_serve_replay(slh_server* s, const slh_serve_request* reqs, uint64_t n, c
     const slh_serve_request& r = reqs[i];
     const uint32_t sb = sig_bytes_of(r.param);
     if (!sb) return sfail(s, SLH_EINVAL, "request " + std::to_string(i) + ": unknown parameter set");
+    if (r.key_slot >= s->key_param.size() || s->key_param[r.key_slot] != r.param)
+      return sfail(s, SLH_EINVAL, "request " + std::to_string(i) + ": key slot missing or of another parameter set");
     if (r.msg_len > msgs_bytes || r.msg_off > msgs_bytes - r.msg_len || (r.msg_len && !msgs))
       return sfail(s, SLH_EINVAL, "request " + std::to_string(i) + ": message outside the buffer");
     if (r.msg_len > s->lanes[0].msg_cap)
@@ -507,6 +519,9 @@ int slh_serve_submit(slh_server* s, uint32_t param, uint32_t key_slot, const uin
   if (!sig_bytes_of(param)) return SLH_EINVAL;
   if (len > s->lanes[0].msg_cap) return SLH_EINVAL;
   if (!s->running || s->stopping) return sfail(s, SLH_EINVAL, "server not started");
+  // key_param only changes while the scheduler is stopped
+  if (key_slot >= s->key_param.size() || s->key_param[key_slot] != param)
+    return sfail(s, SLH_EINVAL, "key slot missing or of another parameter set");
   if (s->worker_error) return int(s->worker_error);
   Req q;
   q.param = param;

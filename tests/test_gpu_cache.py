@@ -98,15 +98,19 @@ def test_cache_arguments(slh):
         ctx.cache_keys(b, 1, 4)
 
 
-def test_server_with_cache(slh):
-    """Replay through a server whose lanes cache the keys' upper layers."""
+@pytest.mark.parametrize("cache_layers", [3, 5])
+def test_server_with_cache(slh, cache_layers):
+    """Replay through a server whose lanes cache the keys' upper layers; the
+    layer count is clamped to each set's limit (4 for the h' = 4 sets, none
+    for the small sets)."""
     import torch  # noqa: F401
-    params = [1, 2, 3, 1, 1, 3, 2, 1]
-    keysets = {p: oracle_keys(p, [workloads.key_seed(p, 600)]) for p in (1, 2, 3)}
+    params = [1, 2, 3, 1, 1, 3, 2, 1] + ([9, 4, 9] if cache_layers == 5 else [])
+    sets = sorted(set(params))
+    keysets = {p: oracle_keys(p, [workloads.key_seed(p, 600)]) for p in sets}
     rng = np.random.default_rng(23)
     msgs = [rng.bytes(int(rng.integers(1, 300))) for _ in params]
-    with slh.Server(0, lanes=2, mode=slh.MODES["fused-dedup"], cache_layers=3) as srv:
-        slots = {p: srv.add_keys(p, keysets[p][0][1]) for p in (1, 2, 3)}
+    with slh.Server(0, lanes=2, mode=slh.MODES["fused-dedup"], cache_layers=cache_layers) as srv:
+        slots = {p: srv.add_keys(p, keysets[p][0][1]) for p in sets}
         reqs, blob = slh.trace(params, [slots[p] for p in params], msgs, [0.0] * len(params))
         sigs, lat, st = srv.replay(reqs, blob)
     want = oracle_sign_many([(p, keysets[p][0][1], m) for p, m in zip(params, msgs)])

@@ -130,3 +130,37 @@ def test_reserve_then_sign(slh, keys):
                 assert got[i] == want[i], "count %d item %d: %s" % (count, i, describe_diff(p, got[i], want[i]))
         with pytest.raises(slh.SlhError):
             ctx.reserve(8, 64)
+
+
+def test_graph_after_key_table_grows(slh, keys):
+    """Adding keys can move the device key table; a batch signed in graph mode
+    before and after that (same items, same buffers) still matches the oracle,
+    so no captured graph keeps the old table's address."""
+    import torch
+    p = 1
+    sk = keys[p][1]
+    with slh.Context(0) as ctx:
+        slot0 = ctx.add_keys(p, sk)
+        msgs = workloads.messages(90, 5, 32)
+        want = oracle_sign_many([(p, sk, m) for m in msgs])
+        for grow in (0, 1, 2):
+            if grow:
+                # 100 copies of the key: the table (64 slots at first) is reallocated
+                first = ctx.add_keys(p, b"".join([sk] * 100))
+                slot = first + 99
+            else:
+                slot = slot0
+            items, blob, total = slh.pack_batch([p] * 5, [slot] * 5, msgs)
+            d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+            d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
+            for rep in range(2):
+                print("graph after growth", grow, rep, flush=True)
+                ctx.sign_batch(items, (d_m.data_ptr(), len(blob)), d_s, slh.MODES["graph"])
+                torch.cuda.synchronize()
+                host = d_s.cpu().numpy().tobytes()
+                sb = slh.sizes(p)["sig_bytes"]
+                for i, it in enumerate(items):
+                    o = int(it["sig_off"])
+                    assert host[o:o + sb] == want[i], "growth %d replay %d item %d" % (grow, rep, i)
+                d_s.zero_()
+                torch.cuda.synchronize()

@@ -107,21 +107,48 @@ def test_online_submit_poll_two_threads(slh, keyset):
 def test_replay_rejects_bad_requests(slh, keyset):
     with slh.Server(0, lanes=1, max_batch=8) as srv:
         slot = srv.add_keys(1, keyset[1][0][1])
+        # a SHAKE-128f key: same sizes as SHA2-128f, another set
+        other = srv.add_keys(7, slh.keygen(7, workloads.key_seed(7, 41))[1])
         reqs, blob = slh.trace([1, 1], [slot, slot], [b"a", b"b"], [0.0, 0.0])
-        bad = reqs.copy()
-        bad[1]["msg_off"] = 10 ** 9
-        with pytest.raises(slh.SlhError):
-            srv.replay(bad, blob)
-        bad = reqs.copy()
-        bad[0]["param"] = 9
-        with pytest.raises(slh.SlhError):
-            srv.replay(bad, blob)
-        bad = reqs.copy()
-        bad[1]["arrival_s"] = -1.0
-        with pytest.raises(slh.SlhError):
-            srv.replay(bad, blob)
+        for field, value in (("msg_off", 10 ** 9), ("param", 13), ("key_slot", other + 1),
+                             ("key_slot", other), ("arrival_s", -1.0)):
+            bad = reqs.copy()
+            bad[1][field] = value
+            print("bad request", field, value, flush=True)
+            with pytest.raises(slh.SlhError):
+                srv.replay(bad, blob)
         sigs, lat, st = srv.replay(reqs, blob)  # still serves afterwards
         assert st["completed"] == 2
+
+
+def test_online_submit_rejects_bad_key_slots(slh, keyset):
+    """A request naming a missing key slot, or a slot holding another set's
+    key, is refused at submission; the server keeps serving the others."""
+    import time
+    sk = keyset[1][0][1]
+    msgs = [b"x" * 10, b"y" * 20]
+    with slh.Server(0, lanes=1, max_batch=8) as srv:
+        slot = srv.add_keys(1, sk)
+        other = srv.add_keys(7, slh.keygen(7, workloads.key_seed(7, 41))[1])
+        srv.start()
+        try:
+            for s_bad in (other + 1, other):
+                with pytest.raises(slh.SlhError):
+                    srv.submit(1, s_bad, b"z", 99)
+            for i, m in enumerate(msgs):
+                srv.submit(1, slot, m, i)
+            got = {}
+            t_end = time.time() + 60
+            while len(got) < len(msgs) and time.time() < t_end:
+                for tag, sig, _ in srv.poll():
+                    got[tag] = sig[:slh.sizes(1)["sig_bytes"]]
+                time.sleep(0.001)
+        finally:
+            srv.stop()
+        for tag, sig, _ in srv.poll():
+            got[tag] = sig[:slh.sizes(1)["sig_bytes"]]
+    want = oracle_sign_many([(1, sk, m) for m in msgs])
+    assert [got.get(i) for i in range(len(msgs))] == want
 
 
 def test_serving_mixed_sha2_and_shake(slh):
