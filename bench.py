@@ -85,7 +85,78 @@ def verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps):
             "ms_per_batch": round(1e3 * el / steps, 3), "all_valid": int(res.sum()) == batch}
 
 
-def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None, verify=False):
+class GpuSampler:
+    """Samples the graphics clock (MHz) and socket power (W) of the GPU that
+    torch calls device 0, through amdsmi on a host thread.  The amdsmi device
+    is the one at the same PCI address; if none matches or amdsmi is missing,
+    the summary says why and holds no figures.  The firmware's metrics lag
+    the load by a fraction of a second, so the summary drops the samples of
+    the first `settle_s` seconds."""
+
+    def __init__(self, period_s=0.01, settle_s=1.0):
+        import threading
+        self.period, self.settle, self.h, self.err = period_s, settle_s, None, None
+        self.samples = []  # (seconds since start, clock MHz, power W)
+        self.stop = threading.Event()
+        self.th = None
+        try:
+            import amdsmi
+            import torch
+            amdsmi.amdsmi_init()
+            pr = torch.cuda.get_device_properties(0)
+            want = "%04x:%02x:%02x." % (int(pr.pci_domain_id), int(pr.pci_bus_id), int(pr.pci_device_id))
+            for h in amdsmi.amdsmi_get_processor_handles():
+                if amdsmi.amdsmi_get_gpu_device_bdf(h).lower().startswith(want):
+                    self.h = h
+            if self.h is None:
+                self.err = "no amdsmi device at PCI address " + want
+            self.amdsmi = amdsmi
+        except Exception as e:  # telemetry is optional; the benchmark is not
+            self.err = repr(e)
+
+    def _loop(self):
+        a = self.amdsmi
+        t0 = time.perf_counter()
+        while not self.stop.is_set():
+            try:
+                c = a.amdsmi_get_clock_info(self.h, a.AmdSmiClkType.GFX)
+                w = a.amdsmi_get_power_info(self.h)
+                c = c.get("clk", c.get("cur_clk"))
+                w = w.get("current_socket_power", w.get("socket_power"))
+                if isinstance(c, (int, float)) and isinstance(w, (int, float)):
+                    self.samples.append((time.perf_counter() - t0, float(c), float(w)))
+            except Exception as e:
+                self.err = repr(e)
+                return
+            self.stop.wait(self.period)
+
+    def __enter__(self):
+        import threading
+        if self.h is not None:
+            self.th = threading.Thread(target=self._loop, daemon=True)
+            self.th.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        if self.th:
+            self.th.join()
+
+    def summary(self):
+        def st(v):
+            return {"mean": round(sum(v) / len(v), 1), "min": min(v), "max": max(v)} if v else None
+        kept = [x for x in self.samples if x[0] >= self.settle]
+        out = {"source": "amdsmi every %d ms over further untimed steps of the same workload, first %.1f s "
+                         "dropped" % (round(1e3 * self.period), self.settle),
+               "samples": len(kept), "gfx_clock_mhz": st([x[1] for x in kept]),
+               "socket_power_w": st([x[2] for x in kept])}
+        if self.err:
+            out["error"] = self.err
+        return out
+
+
+def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None, verify=False,
+        telemetry_s=1.0):
     import torch
     from paper_2512_23969_amd import autotune
     ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
@@ -107,15 +178,29 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     torch.cuda.synchronize()
     ctx.phase_times(reset=True)
     ctx.profile(True)
+    # per-step GPU time from events on the stream the steps run on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev[0].record(stream)
     for i in range(steps):
         ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.profile(False)
+    step_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
     phases = ctx.phase_times(reset=True)
     trees, distinct = ctx.dedup_stats(reset=True)
+    # clock and power under this load: further steps, outside the timed region
+    sampler = GpuSampler()
+    with sampler:
+        if sampler.h is not None:
+            t2 = time.perf_counter()
+            while time.perf_counter() - t2 < sampler.settle + telemetry_s:
+                for _ in range(4):
+                    ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
+                torch.cuda.synchronize()
     ver = verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps) if verify else None
     ctx.close()
     elapsed = t1 - t0
@@ -131,6 +216,9 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         # (trees needed, distinct trees computed) per step, dedup modes only
         "dedup": (trees // (warmup + steps), distinct // (warmup + steps)) if trees else None,
         "verify": ver,
+        "step_ms": {"median": round(step_ms[len(step_ms) // 2], 4), "min": round(step_ms[0], 4),
+                    "max": round(step_ms[-1], 4)},
+        "gpu": sampler.summary(),
     }
 
 
@@ -298,6 +386,7 @@ def roofline(param, res):
     achieved = ops / avg_s / 1e12
     peak = acc.VALU_PEAK_OPS / 1e12
     c = acc.per_signature(param)
+    clk = (res["gpu"]["gfx_clock_mhz"] or {}).get("mean")
     units = {h: int(sum(c[h][p] * scale.get(p, 1.0) for p in parts) * per_launch_msgs)
              for h in ("sha256", "sha512", "keccak") if sum(c[h].values())}
     return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": round(peak, 3),
@@ -310,7 +399,13 @@ def roofline(param, res):
             # the same work at the rate each hash's instruction mix reaches in
             # isolation (calibration probe): 1.0 = as fast as that mix runs
             "mix_ceiling_frac": round(acc.mix_ceiling_seconds(units) / avg_s, 4),
-            "single_rate_frac": round(ops / avg_s / acc.VALU_SINGLE_RATE_OPS, 4)}
+            "single_rate_frac": round(ops / avg_s / acc.VALU_SINGLE_RATE_OPS, 4),
+            # the same fractions against the peak at the graphics clock sampled
+            # during the steps (the published peak assumes 2.4 GHz)
+            "clock_mhz": clk,
+            "frac_at_measured_clock": round(achieved / peak * 2400.0 / clk, 4) if clk else None,
+            "mix_ceiling_frac_at_measured_clock":
+                round(acc.mix_ceiling_seconds(units) / avg_s * 2400.0 / clk, 4) if clk else None}
 
 
 def phase_rooflines(param, res, msg_bytes=32):
@@ -352,7 +447,9 @@ def summary(acc, r, mode):
            "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
            "roofline": roofline(prm, r) if "graph" not in mode else None,
            "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]},
-           "phase_roofline": phase_rooflines(prm, r)}
+           "phase_roofline": phase_rooflines(prm, r), "step_ms": r["step_ms"],
+           "gfx_clock_mhz": (r["gpu"]["gfx_clock_mhz"] or {}).get("mean"),
+           "socket_power_w": (r["gpu"]["socket_power_w"] or {}).get("mean")}
     if r["dedup"]:
         trees, distinct = r["dedup"]
         out["dedup"] = {"trees_per_step": trees, "distinct_trees_per_step": distinct,
@@ -425,6 +522,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(res["ms_per_step"], 4),
+        "step_ms": res["step_ms"],
+        "gpu_telemetry": dict(res["gpu"], joules_per_signature=(
+            round(res["gpu"]["socket_power_w"]["mean"] / res["sig_per_s"], 6)
+            if res["gpu"]["socket_power_w"] else None)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
