@@ -81,3 +81,56 @@ def test_full_batch(slh, name):
         ctx.verify_batch(vit[batch:], d_m, d_s_bad, d_pk, res2)
         torch.cuda.synchronize()
         assert int(res2.sum()) == 0
+
+
+@pytest.mark.parametrize("param,batch,nkeys", [(1, 32768, 1), (3, 8192, 64)])
+def test_batch_beyond_config(slh, param, batch, nkeys):
+    """Batches past the benchmarked size (8x for 128f, 2x for 256f with 64
+    keys) under a 2 GiB working-memory budget, which the context meets by
+    signing the batch in several chunks (about 200 KB of kept chain values
+    per 128f signature, 580 KB per 256f one); every mode gives the same
+    bytes, sampled signatures equal the oracle's and the whole batch verifies
+    on the GPU."""
+    import torch
+    cfg = 40 + param
+    keys = [slh.keygen(param, workloads.key_seed(param, 100 + i)) for i in range(nkeys)]
+    kidx = workloads.key_assignment(cfg, batch, nkeys) if nkeys > 1 else [0] * batch
+    msgs = workloads.messages(cfg, batch, 32)
+    with slh.Context(0, hbm_budget=2 << 30) as ctx:
+        first = ctx.add_keys(param, [sk for _, sk in keys])
+        items, blob, total = slh.pack_batch([param] * batch, [first + k for k in kidx], msgs)
+        d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
+        outs = {}
+        for mode in ("plain", "fused", "fused-dedup"):
+            d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
+            print("batch", batch, slh.NAMES[param], mode, flush=True)
+            ctx.profile(mode == "plain")
+            ctx.sign_batch(items, d_m, d_s, mode=slh.MODES[mode])
+            torch.cuda.synchronize()
+            if mode == "plain":
+                ctx.profile(False)
+                tree_ms, tree_launches, tree_msgs = ctx.phase_times(reset=True)["tree"]
+                assert tree_launches >= 2 and tree_msgs == batch, (tree_launches, tree_msgs)
+            outs[mode] = d_s
+        for mode in ("fused", "fused-dedup"):
+            assert torch.equal(outs[mode], outs["plain"]), mode
+        host = outs["plain"].cpu().numpy().tobytes()
+        sb = slh.sizes(param)["sig_bytes"]
+        sample = workloads.sample_indices(cfg, batch, 16)
+        want = oracle_sign_many([(param, keys[kidx[i]][1], msgs[i]) for i in sample])
+        for i, w in zip(sample, want):
+            got = host[int(items[i]["sig_off"]):int(items[i]["sig_off"]) + sb]
+            assert got == w, "item %d: %s" % (i, describe_diff(param, got, w))
+        pks = b"".join(pk for pk, _ in keys)
+        d_pk = torch.frombuffer(bytearray(pks), dtype=torch.uint8).cuda()
+        npk = 2 * slh.sizes(param)["n"]
+        vit = np.zeros(batch, dtype=slh.VERIFY_DTYPE)
+        vit["param"] = param
+        vit["msg_off"] = items["msg_off"]
+        vit["msg_len"] = items["msg_len"]
+        vit["sig_off"] = items["sig_off"]
+        vit["pk_off"] = np.asarray(kidx, dtype=np.uint64) * npk
+        res = torch.zeros(batch, dtype=torch.int32, device="cuda")
+        ctx.verify_batch(vit, d_m, outs["plain"], d_pk, res)
+        torch.cuda.synchronize()
+        assert int(res.sum()) == batch
