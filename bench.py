@@ -10,6 +10,7 @@ batch-4096 workloads, reported under "extra".
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
 import os
 import sys
@@ -193,9 +194,9 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     phases = ctx.phase_times(reset=True)
     trees, distinct = ctx.dedup_stats(reset=True)
     # clock and power under this load: further steps, outside the timed region
-    sampler = GpuSampler()
-    with sampler:
-        if sampler.h is not None:
+    sampler = GpuSampler() if telemetry_s > 0 else None
+    with sampler or contextlib.nullcontext():
+        if sampler is not None and sampler.h is not None:
             t2 = time.perf_counter()
             while time.perf_counter() - t2 < sampler.settle + telemetry_s:
                 for _ in range(4):
@@ -218,7 +219,8 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         "verify": ver,
         "step_ms": {"median": round(step_ms[len(step_ms) // 2], 4), "min": round(step_ms[0], 4),
                     "max": round(step_ms[-1], 4)},
-        "gpu": sampler.summary(),
+        "gpu": sampler.summary() if sampler is not None else {"source": "off", "gfx_clock_mhz": None,
+                                                               "socket_power_w": None},
     }
 
 
@@ -480,6 +482,9 @@ def main():
     ap.add_argument("--serve-cache-layers", type=int, default=0,
                     help="upper hypertree layers cached per key on the server's lanes (dedup modes)")
     ap.add_argument("--serve-lanes", type=int, default=4, help="in-flight batches of the signing server")
+    ap.add_argument("--telemetry-s", type=float, default=1.0,
+                    help="seconds of further untimed steps (after a 1 s settle) over which amdsmi samples the "
+                         "clock and power; 0 = none (profiler runs)")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0 = keep the environment's). The serving leg "
                          "keeps 4 lanes x 4 streams busy; with 16 hardware queues none of them share one")
@@ -510,7 +515,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log("bench: workload", args.workload)
     res = run(slh, workloads, args.workload, args.steps, args.warmup, args.mode, args.tune, args.tune_out,
-              verify=True)
+              verify=True, telemetry_s=args.telemetry_s)
     param = res["cfg"]["param"]
     c256, c512 = acc.compressions_per_signature(param)
     ckf = acc.permutations_per_signature(param)
@@ -570,7 +575,7 @@ def main():
                 log("bench: workload", name, mode)
                 r = run(slh, workloads, name, steps_c, args.warmup, mode,
                         args.tune and mode == "plain" and name != args.workload, args.tune_out,
-                        verify=mode == "plain")
+                        verify=mode == "plain", telemetry_s=args.telemetry_s)
                 extra["%s/%s" % (name, mode)] = summary(acc, r, mode)
                 if r["verify"]:
                     extra["%s/verify" % name] = r["verify"]
