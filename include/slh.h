@@ -12,10 +12,14 @@
  * slh_verify_internal (Algorithm 20).  The SHAKE sets (ids 7..12) use the
  * SHAKE256 instantiation of FIPS 205 Section 11.1 on the same trees.
  *
- * Parameter sets (the paper's Table 1):
+ * Parameter sets (the paper's Table 1; the small sets from FIPS 205 Table 2):
  *   SLH_SHA2_128F  n=16 h=66 d=22 a=6 k=33 w=16   signature 17088 bytes
  *   SLH_SHA2_192F  n=24 h=66 d=22 a=8 k=33 w=16   signature 35664 bytes
  *   SLH_SHA2_256F  n=32 h=68 d=17 a=9 k=35 w=16   signature 49856 bytes
+ *   SLH_SHA2_128S  n=16 h=63 d=7  a=12 k=14 w=16  signature  7856 bytes
+ *   SLH_SHA2_192S  n=24 h=63 d=7  a=14 k=17 w=16  signature 16224 bytes
+ *   SLH_SHA2_256S  n=32 h=64 d=8  a=14 k=22 w=16  signature 29792 bytes
+ *   SLH_SHAKE_*    the same six shapes and sizes with SHAKE256
  *
  * Byte encodings are those of FIPS 205:
  *   seed = SK.seed | SK.prf | PK.seed                 (3n bytes)
