@@ -34,7 +34,7 @@ constexpr int kForsThreads = 256;
 // ------------------------------------------------------------------ keys
 // Chaining values after the PK.seed block, one lane per key.  Keys of the
 // SHAKE sets (parameter ids 7..12) keep PK.seed itself in the mid256 slot.
-__global__ void k_key_midstates(DevKey* keys, uint32_t first, uint32_t count) {
+static __global__ void k_key_midstates(DevKey* keys, uint32_t first, uint32_t count) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   DevKey& K = keys[first + i];
@@ -70,7 +70,7 @@ __global__ void k_key_midstates(DevKey* keys, uint32_t first, uint32_t count) {
 
 // Cache placement of keys first .. first+count-1: `layers` cached layers,
 // key i's trees at byte offset off0 + i * per_key.
-__global__ void k_set_cache(DevKey* keys, uint32_t first, uint32_t count, uint32_t layers, uint64_t off0,
+static __global__ void k_set_cache(DevKey* keys, uint32_t first, uint32_t count, uint32_t layers, uint64_t off0,
                             uint64_t per_key) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -94,7 +94,7 @@ struct ExtJob {
 };
 constexpr int kEncodeThreads = 256;
 
-__global__ __launch_bounds__(kEncodeThreads) void k_encode_ext(const ExtJob* __restrict__ jobs,
+static __global__ __launch_bounds__(kEncodeThreads) void k_encode_ext(const ExtJob* __restrict__ jobs,
                                                                const uint8_t* __restrict__ in,
                                                                uint8_t* __restrict__ out) {
   const ExtJob J = jobs[blockIdx.x];
@@ -953,7 +953,7 @@ struct DedupSlot {
 };
 constexpr unsigned long long kDedupEmpty = ~0ull;
 
-__global__ void k_dedup_init(DedupSlot* table, uint32_t size, uint32_t* lown, uint32_t nlown, uint32_t* ucount) {
+static __global__ void k_dedup_init(DedupSlot* table, uint32_t size, uint32_t* lown, uint32_t nlown, uint32_t* ucount) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < size) {
     table[i].key = kDedupEmpty;
@@ -1034,7 +1034,7 @@ __global__ void k_dedup_resolve(const WorkRec* __restrict__ recs, uint32_t nmsg,
 
 // Running totals of eligible-or-not trees and distinct trees computed (one
 // lane; stream order makes plain adds safe).
-__global__ void k_dedup_stats(uint32_t trees, const uint32_t* ucount, unsigned long long* stats) {
+static __global__ void k_dedup_stats(uint32_t trees, const uint32_t* ucount, unsigned long long* stats) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     stats[0] += trees;
     stats[1] += *ucount;
