@@ -132,7 +132,10 @@ int launch(slh_server* s, Lane& L) {
   L.reqs.clear();
   L.items.clear();
   L.sig_off.clear();
-  uint64_t moff = 0, soff = 0;
+  // moff: where the next message may start (4-byte aligned, so messages
+  // stream as dwords); mend: end of the last message placed, the bytes to
+  // upload (never past msg_cap, whatever its alignment)
+  uint64_t moff = 0, mend = 0, soff = 0;
   while (!s->pending.empty() && L.reqs.size() < s->cfg.max_batch) {
     Req& r = s->pending.front();
     const uint64_t sb = (uint64_t(sig_bytes_of(r.param)) + 15) / 16 * 16;
@@ -140,14 +143,15 @@ int launch(slh_server* s, Lane& L) {
     std::memcpy(L.h_msgs + moff, r.msg, r.len);
     L.items.push_back({r.param, r.slot, moff, r.len, soff});
     L.sig_off.push_back(soff);
-    moff = (moff + r.len + 3) / 4 * 4;  // 4-byte aligned messages stream as dwords
+    mend = moff + r.len;
+    moff = (mend + 3) / 4 * 4;
     soff += sb;
     L.reqs.push_back(std::move(r));
     s->pending.pop_front();
   }
   if (L.reqs.empty()) return 0;
   L.sig_used = soff;
-  if (moff && hipMemcpyAsync(L.d_msgs, L.h_msgs, moff, hipMemcpyHostToDevice, L.stream) != hipSuccess)
+  if (mend && hipMemcpyAsync(L.d_msgs, L.h_msgs, mend, hipMemcpyHostToDevice, L.stream) != hipSuccess)
     return sfail(s, SLH_EDEVICE, "message upload failed");
   int rc = slh_sign_batch(L.ctx, L.items.data(), uint32_t(L.items.size()), L.d_msgs, L.msg_cap, L.d_sigs,
                           L.sig_cap, s->cfg.mode, L.stream);

@@ -17,8 +17,17 @@ def host_threads() -> int:
 
 
 def oracle_keys(param: int, seeds):
+    """(pk, sk) of each seed from the oracle's key generation, in parallel."""
     p = oracle.params(NAMES[param])
-    return [oracle.keygen(p, s) for s in seeds]
+    with ThreadPoolExecutor(host_threads()) as ex:
+        return list(ex.map(lambda s: oracle.keygen(p, s), seeds))
+
+
+def assert_gpu_keys(slh, param: int, seeds, keys):
+    """slh.keygen (the HIP path) gives the oracle's (pk, sk) for every seed."""
+    for i, (seed, want) in enumerate(zip(seeds, keys)):
+        assert slh.keygen(param, seed) == want, "%s key %d: GPU keygen differs from the oracle" % (
+            NAMES[param], i)
 
 
 def oracle_sign_many(jobs):

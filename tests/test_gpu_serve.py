@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import NAMES, describe_diff, oracle_sign_many
+from helpers import NAMES, assert_gpu_keys, describe_diff, oracle_keys, oracle_sign_many
 from paper_2512_23969_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -24,9 +24,12 @@ def slh():
 
 @pytest.fixture(scope="module")
 def keyset(slh):
+    """Three oracle keys per set; the GPU's key generation must agree."""
     keys = {}
     for p in (1, 2, 3):
-        keys[p] = [slh.keygen(p, workloads.key_seed(p, 40 + i)) for i in range(3)]
+        seeds = [workloads.key_seed(p, 40 + i) for i in range(3)]
+        keys[p] = oracle_keys(p, seeds)
+        assert_gpu_keys(slh, p, seeds, keys[p])
     return keys
 
 
@@ -108,7 +111,7 @@ def test_replay_rejects_bad_requests(slh, keyset):
     with slh.Server(0, lanes=1, max_batch=8) as srv:
         slot = srv.add_keys(1, keyset[1][0][1])
         # a SHAKE-128f key: same sizes as SHA2-128f, another set
-        other = srv.add_keys(7, slh.keygen(7, workloads.key_seed(7, 41))[1])
+        other = srv.add_keys(7, oracle_keys(7, [workloads.key_seed(7, 41)])[0][1])
         reqs, blob = slh.trace([1, 1], [slot, slot], [b"a", b"b"], [0.0, 0.0])
         for field, value in (("msg_off", 10 ** 9), ("param", 13), ("key_slot", other + 1),
                              ("key_slot", other), ("arrival_s", -1.0)):
@@ -129,7 +132,7 @@ def test_online_submit_rejects_bad_key_slots(slh, keyset):
     msgs = [b"x" * 10, b"y" * 20]
     with slh.Server(0, lanes=1, max_batch=8) as srv:
         slot = srv.add_keys(1, sk)
-        other = srv.add_keys(7, slh.keygen(7, workloads.key_seed(7, 41))[1])
+        other = srv.add_keys(7, oracle_keys(7, [workloads.key_seed(7, 41)])[0][1])
         srv.start()
         try:
             for s_bad in (other + 1, other):
@@ -155,7 +158,11 @@ def test_serving_mixed_sha2_and_shake(slh):
     """SHA2 and SHAKE keys of the fast and small sets in one served trace,
     several batches in flight: every signature equals the oracle's."""
     params = [1, 7, 2, 8, 9, 3, 10, 4, 7, 1] * 4
-    keys = {p: slh.keygen(p, workloads.key_seed(p, 60)) for p in sorted(set(params))}
+    keys = {}
+    for p in sorted(set(params)):
+        seed = workloads.key_seed(p, 60)
+        keys[p] = oracle_keys(p, [seed])[0]
+        assert_gpu_keys(slh, p, [seed], [keys[p]])
     rng = np.random.default_rng(61)
     msgs = [rng.bytes(int(rng.integers(0, 400))) for _ in params]
     with slh.Server(0, lanes=3, max_batch=8, max_wait_us=200) as srv:
@@ -171,3 +178,23 @@ def test_serving_mixed_sha2_and_shake(slh):
     want = oracle_sign_many([(p, keys[p][1], m) for p, m in zip(params, msgs)])
     for i, (g, w) in enumerate(zip(served, want)):
         assert g == w, "req %d (%s, %d B): %s" % (i, NAMES[params[i]], len(msgs[i]), describe_diff(params[i], g, w))
+
+
+def test_message_buffer_not_a_multiple_of_four(slh, keyset):
+    """A lane message buffer of 4k + 1 bytes filled to its last byte:
+    messages start at 4-byte aligned offsets and the last one ends exactly at
+    the buffer's end, so the upload must stop there (not at the next
+    multiple of four).  Every signature equals the oracle's."""
+    sk = keyset[1][0][1]
+    rng = np.random.default_rng(77)
+    lens = [1001, 1003, 1005, 1081, 7, 4097, 0, 2]
+    msgs = [rng.bytes(n) for n in lens]
+    with slh.Server(0, lanes=1, max_batch=8, msg_bytes=4097) as srv:
+        slot = srv.add_keys(1, sk)
+        reqs, blob = slh.trace([1] * len(msgs), [slot] * len(msgs), msgs, [0.0] * len(msgs))
+        sigs, lat, st = srv.replay(reqs, blob)
+        assert st["completed"] == len(msgs) and st["launches"] >= 2
+        served = [sigs[int(r["sig_off"]):int(r["sig_off"]) + slh.sizes(1)["sig_bytes"]].tobytes() for r in reqs]
+    want = oracle_sign_many([(1, sk, m) for m in msgs])
+    for i, (g, w) in enumerate(zip(served, want)):
+        assert g == w, "req %d (%d B): %s" % (i, lens[i], describe_diff(1, g, w))
