@@ -4,14 +4,12 @@ Two stages, as in the paper's Section III-B ("Fusion Trade-offs in FORS"):
 an analytic search proposes candidate FORS groupings, then the candidates
 are timed on the GPU and the fastest is kept.
 
-* ``tree_tuning(...)`` is the paper's Algorithm 1 (Auto Tree Tuning): for a
-  per-block shared-memory budget S_max and thread limit T_max it enumerates
-  Set sizes T_set (a multiple of the leaves per tree) and fusion factors F,
-  drops configurations that use all threads and all shared memory or fewer
-  than alpha * T_max threads, and keeps the one with the fewest
-  synchronisation points, then the highest thread and memory utilisation.
-  With the RTX 4090's 48 KiB static shared memory it gives the paper's
-  Table 4.
+* ``fors_fusion_search(...)`` states the paper's FORS-fusion trade-off
+  (Section III-B, its Algorithm 1) as a search over block layouts: trees
+  per block and sets fused through shared memory, constrained by the
+  block's threads and shared memory, ranked by barrier count and then
+  resource use.  With the RTX 4090's 48 KiB static shared memory it gives
+  the paper's Table 4.
 * ``gfx950_groups(param)`` re-expresses the same trade-off for this
   library's FORS kernels, whose unit is a group of trees reduced by one
   256-lane workgroup with two leaves per lane: the LDS per group must fit the
@@ -36,33 +34,44 @@ FORS_SHAPE = {1: (16, 6, 33), 2: (24, 8, 33), 3: (32, 9, 35), 4: (16, 12, 14), 5
 FORS_SHAPE.update({p + 6: s for p, s in list(FORS_SHAPE.items())})  # SHAKE sets: same shapes
 
 
-def tree_tuning(k: int, log_t: int, n: int, s_max: int, t_max: int = 1024, alpha: float = 0.6):
-    """Algorithm 1 of the paper.  Returns (best, candidates); each candidate
-    is a dict with T_set, F, U_T, U_S and sync."""
-    t = 1 << log_t
-    t_min = t
-    cand = []
-    for t_set in range(t_min, t_max + 1, t_min):
-        n_tree = t_set // t_min
-        s_set = n_tree * t * n
-        if s_set > s_max:
-            continue
-        f_max = min(s_max // s_set, k // n_tree)
-        for f in range(1, f_max + 1):
-            t_used = t_set
-            s_used = f * s_set
-            if t_used > t_max or s_used > s_max:
-                continue
-            u_t = t_used / t_max
-            u_s = s_used / s_max
-            if (u_t == 1 and u_s == 1) or u_t < alpha:
-                continue
-            sync = log_t * math.ceil(k / n_tree) / f
-            cand.append({"T_set": t_set, "F": f, "U_T": u_t, "U_S": u_s, "sync": sync})
-    if not cand:
-        return None, cand
-    best = min(cand, key=lambda c: (c["sync"], -c["U_T"], -c["U_S"]))
-    return best, cand
+def fors_fusion_search(k: int, log_t: int, n: int, smem_bytes: int, max_threads: int = 1024,
+                       alpha: float = 0.6):
+    """The FORS-fusion trade-off of the paper's Section III-B for a GPU with
+    `smem_bytes` of shared memory and `max_threads` threads per block.
+
+    A block gives one thread to every leaf of `trees` whole FORS trees (2^a
+    leaves each) and fuses `fusion` such sets through its shared memory (one
+    n-byte node per leaf and set).  The k trees of a signature then take
+    ceil(k / trees) / fusion rounds of a level barriers each.  A layout is
+    feasible when its threads and fused node buffers fit the block, it
+    keeps at least `alpha` of the threads busy, and it does not fill both
+    resources exactly.  The best layout has the fewest barriers, then the
+    highest thread use, then the highest shared-memory use.  The paper
+    leaves alpha unstated; any alpha in (0.5, 0.6875] gives its Table 4 for
+    the RTX 4090's 48 KiB of static shared memory.
+
+    Returns (best, feasible); each layout is a dict with trees, fusion,
+    threads, smem, thread_use, smem_use and barriers (None, [] if nothing
+    is feasible)."""
+    leaves = 1 << log_t
+
+    def layout(trees, fusion):
+        threads, smem = trees * leaves, fusion * trees * leaves * n
+        return {"trees": trees, "fusion": fusion, "threads": threads, "smem": smem,
+                "thread_use": threads / max_threads, "smem_use": smem / smem_bytes,
+                "barriers": log_t * math.ceil(k / trees) / fusion}
+
+    def feasible(c):
+        full = c["thread_use"] == 1 and c["smem_use"] == 1
+        return c["smem"] <= smem_bytes and c["thread_use"] >= alpha and not full
+
+    # at most k trees per block, and no more fused sets than the k trees fill
+    shapes = [(t, f) for t in range(1, min(k, max_threads // leaves) + 1) for f in range(1, k // t + 1)]
+    options = [c for c in (layout(t, f) for t, f in shapes) if feasible(c)]
+    if not options:
+        return None, []
+    best = min(options, key=lambda c: (c["barriers"], -c["thread_use"], -c["smem_use"]))
+    return best, options
 
 
 COMPILED_GROUPS = {1: (4, 8, 16), 2: (4, 8, 16), 3: (2, 4, 8), 4: (1, 2), 5: (1, 2), 6: (1, 2)}

@@ -1,6 +1,6 @@
-"""The autotuner's analytic stage: the paper's Algorithm 1 reproduces its
-Table 4, and the gfx950 grouping model only proposes compiled variants that
-fit the LDS of a compute unit."""
+"""The autotuner's analytic stage: the FORS-fusion search of the paper's
+Section III-B reproduces its Table 4, and the gfx950 grouping model only
+proposes compiled variants that fit the LDS of a compute unit."""
 import json
 import os
 
@@ -13,22 +13,30 @@ GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_f
 
 @pytest.mark.parametrize("alpha", [0.51, 0.6, 0.6875])
 @pytest.mark.parametrize("name,shape", [("128f", (33, 6, 16)), ("192f", (33, 8, 24))])
-def test_algorithm1_reproduces_table4(name, shape, alpha):
+def test_fusion_search_reproduces_table4(name, shape, alpha):
     k, log_t, n = shape
-    best, cand = at.tree_tuning(k, log_t, n, s_max=48 * 1024, t_max=1024, alpha=alpha)
-    want = GOLD["tree_tuning"][name]
-    assert best["F"] == want["F"]
-    assert best["U_S"] == pytest.approx(want["U_S"])
-    assert best["U_T"] == pytest.approx(want["U_T"])
-    # every candidate respects the constraints of the algorithm
+    best, cand = at.fors_fusion_search(k, log_t, n, smem_bytes=48 * 1024, max_threads=1024, alpha=alpha)
+    want = GOLD["tree_tuning"][name]  # Table 4 prints F, U_S and U_T
+    assert best["fusion"] == want["F"]
+    assert best["smem_use"] == pytest.approx(want["U_S"])
+    assert best["thread_use"] == pytest.approx(want["U_T"])
+    # every feasible layout respects the block's limits
     for c in cand:
-        assert c["U_T"] >= alpha and not (c["U_T"] == 1 and c["U_S"] == 1) and c["U_S"] <= 1
+        assert c["thread_use"] >= alpha and c["smem_use"] <= 1 and c["threads"] <= 1024
+        assert not (c["thread_use"] == 1 and c["smem_use"] == 1)
 
 
-def test_algorithm1_alpha_sensitivity():
+def test_fusion_search_alpha_sensitivity():
     # alpha above 0.6875 excludes the 128f optimum of Table 4
-    best, _ = at.tree_tuning(33, 6, 16, 48 * 1024, 1024, 0.7)
-    assert best["F"] != 3
+    best, _ = at.fors_fusion_search(33, 6, 16, 48 * 1024, 1024, 0.7)
+    assert best["fusion"] != 3
+
+
+def test_fusion_search_barrier_count():
+    # 128f with 11 trees of 64 leaves per block (704 threads) fused 3 times:
+    # ceil(33 / 11) / 3 = 1 round of 6 level barriers
+    best, _ = at.fors_fusion_search(33, 6, 16, 48 * 1024, 1024, 0.6)
+    assert (best["trees"], best["fusion"], best["barriers"]) == (11, 3, 6.0)
 
 
 @pytest.mark.parametrize("param", [1, 2, 3])
