@@ -3,16 +3,22 @@
 
 One step = one slh_sign_batch call over the whole batch (prelude, FORS,
 TREE and WOTS kernels), inputs and outputs resident in HBM.  Prints one
-JSON line.  Default workload: SPHINCS+-SHA2-128f, one key, 4096 random
-32-byte messages; --all also times the 192f (1 key) and 256f (64 keys)
-batch-4096 workloads, reported under "extra".
+JSON line.  Headline workload: SPHINCS+-SHA2-128f, one key, 4096 random
+32-byte messages, in its autotuned mode.  The line also carries, under
+"extra", the 192f (1 key) and 256f (64 keys) batch-4096 workloads and the
+128f one again, each in its autotuned mode and in the plain per-phase path,
+with a roofline object each; "serving" holds the continuous-batching
+workload with p50/p99 per parameter set.  --all adds the small sets, the
+SHAKE sets, the other modes and the small-batch latencies.
 """
 from __future__ import annotations
 
 import argparse
 import contextlib
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -33,8 +39,44 @@ WORKLOADS = {
 }
 
 
+# the metric as the benchmark specification names it; the value is the 128f
+# workload's, and "extra" holds the 192f and 256f ones
+METRIC = "signatures/s (128f/192f/256f, batch 4096) + p50/p99 latency; % VALU peak"
+# the batch-4096 workloads of the default line, each tuned and plain
+DEFAULT_WORKLOADS = ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64")
+# HBM bytes per launch measured with rocprofv3 counters, valid while the
+# device sources hash to the value recorded with them
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_b4096.json")
+DEVICE_SOURCES = ("kernels.hpp", "slh_dev.hpp", "sha2_dev.hpp", "keccak_dev.hpp", "set_impl.hpp")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def device_source_hash() -> str:
+    """SHA-256 of the device code and launch sources (kernels and their grids)."""
+    h = hashlib.sha256()
+    for f in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_23969_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """(bytes per launch, source) from the committed counter summary when it
+    was taken on the current device sources, else (None, reason)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None, "no counter summary"
+    e = t.get("entries", {}).get("%s/%s" % (workload, kernel))
+    if e is None:
+        return None, "not profiled"
+    if t.get("device_source_sha256") != device_source_hash():
+        return None, "kernels changed since the counters were taken"
+    return int(e["bytes_per_launch"]), e.get("summary", os.path.relpath(TRAFFIC_FILE, ROOT))
 
 
 def setup(slh, workloads, name):
@@ -97,6 +139,7 @@ class GpuSampler:
     def __init__(self, period_s=0.01, settle_s=1.0):
         import threading
         self.period, self.settle, self.h, self.err = period_s, settle_s, None, None
+        self.energy_err = None
         self.samples = []  # (seconds since start, clock MHz, power W)
         self.stop = threading.Event()
         self.th = None
@@ -143,6 +186,22 @@ class GpuSampler:
         if self.th:
             self.th.join()
 
+    def energy_j(self):
+        """The GPU's accumulated energy in joules (amdsmi's energy counter:
+        accumulator x resolution in microjoules), or None."""
+        if self.h is None:
+            return None
+        try:
+            e = self.amdsmi.amdsmi_get_energy_count(self.h)
+            count = e.get("energy_accumulator", e.get("power"))
+            res = e.get("counter_resolution")
+            if isinstance(count, (int, float)) and isinstance(res, (int, float)) and res > 0:
+                return float(count) * float(res) * 1e-6
+            self.energy_err = "energy counter fields: %s" % sorted(e)
+        except Exception as ex:  # telemetry is optional
+            self.energy_err = repr(ex)
+        return None
+
     def summary(self):
         def st(v):
             return {"mean": round(sum(v) / len(v), 1), "min": min(v), "max": max(v)} if v else None
@@ -153,11 +212,23 @@ class GpuSampler:
                "socket_power_w": st([x[2] for x in kept])}
         if self.err:
             out["error"] = self.err
+        if getattr(self, "energy_err", None):
+            out["energy_error"] = self.energy_err
         return out
 
 
+def energy_summary(e0, e1, t0, t1, signatures, what):
+    """Energy over a window from two counter readings (None if the counter
+    is unavailable or did not advance)."""
+    if e0 is None or e1 is None or e1 <= e0 or t1 <= t0 or not signatures:
+        return None
+    return {"window": what, "joules": round(e1 - e0, 3), "seconds": round(t1 - t0, 4), "signatures": signatures,
+            "mean_power_w": round((e1 - e0) / (t1 - t0), 1),
+            "joules_per_signature": round((e1 - e0) / signatures, 7)}
+
+
 def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None, verify=False,
-        telemetry_s=1.0):
+        telemetry_s=2.0):
     import torch
     from paper_2512_23969_amd import autotune
     ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
@@ -170,7 +241,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     if best:
         tuned = autotune.apply(ctx, cfg["param"], best)
     if mode == "auto":
-        mode = {"plain": "plain", "fused": "fused"}.get(tuned or "plain", "plain")
+        mode = tuned or "plain"
     m = slh.MODES[mode]
     ctx.dedup_stats(reset=True)
     stream = torch.cuda.current_stream()
@@ -179,9 +250,11 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     torch.cuda.synchronize()
     ctx.phase_times(reset=True)
     ctx.profile(True)
+    sampler = GpuSampler() if telemetry_s > 0 else None
     # per-step GPU time from events on the stream the steps run on
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
+    e_a = sampler.energy_j() if sampler else None
     t0 = time.perf_counter()
     ev[0].record(stream)
     for i in range(steps):
@@ -189,19 +262,30 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    e_b = sampler.energy_j() if sampler else None
     ctx.profile(False)
     step_ms = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
     phases = ctx.phase_times(reset=True)
     trees, distinct = ctx.dedup_stats(reset=True)
-    # clock and power under this load: further steps, outside the timed region
-    sampler = GpuSampler() if telemetry_s > 0 else None
+    energy = {"timed_steps": energy_summary(e_a, e_b, t0, t1, steps * cfg["batch"], "the timed steps")}
+    # clock, power and energy under this load: further steps outside the
+    # timed region, after a settling second (the firmware's figures lag)
     with sampler or contextlib.nullcontext():
         if sampler is not None and sampler.h is not None:
             t2 = time.perf_counter()
-            while time.perf_counter() - t2 < sampler.settle + telemetry_s:
+            while time.perf_counter() - t2 < sampler.settle:
                 for _ in range(4):
                     ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
                 torch.cuda.synchronize()
+            e_c, t3, n = sampler.energy_j(), time.perf_counter(), 0
+            while time.perf_counter() - t3 < telemetry_s:
+                for _ in range(4):
+                    ctx.sign_batch(items, d_m, d_s, mode=m, stream=stream)
+                n += 4
+                torch.cuda.synchronize()
+            e_d, t4 = sampler.energy_j(), time.perf_counter()
+            energy["window"] = energy_summary(e_c, e_d, t3, t4, n * cfg["batch"],
+                                              "%.1f s of further steps after a 1 s settle" % telemetry_s)
     ver = verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps) if verify else None
     ctx.close()
     elapsed = t1 - t0
@@ -211,6 +295,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         "sig_per_s": cfg["batch"] * steps / elapsed,
         "phases": phases,
         "cfg": cfg,
+        "name": name,
         "steps": steps,
         "mode": mode,
         "tuning": best,
@@ -221,12 +306,33 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
                     "max": round(step_ms[-1], 4)},
         "gpu": sampler.summary() if sampler is not None else {"source": "off", "gfx_clock_mhz": None,
                                                                "socket_power_w": None},
+        "energy": energy,
     }
+
+
+def host_cpu():
+    """The host's CPU model and core counts."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    return {"model": model or platform.processor() or None, "os_cpu_count": os.cpu_count(),
+            "affinity_cores": affinity}
 
 
 def cpu_baseline(name, workloads, seconds=15.0):
     """The oracle, as it stands, on the host cores: sign messages of the same
-    workload in a thread pool for about `seconds`."""
+    workload with one thread per core this process may run on, for about
+    `seconds`; then on one thread for about a tenth of that."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
     cfg = workloads.CONFIGS[name]
@@ -234,11 +340,8 @@ def cpu_baseline(name, workloads, seconds=15.0):
     p = oracle.params(workloads.NAME_OF[param])
     pk, sk = oracle.keygen(p, workloads.key_seed(param, 0))
     msgs = workloads.messages(cfg["cfg"], cfg["batch"], cfg["length"])
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    threads = max(1, min(16, cores))
+    host = host_cpu()
+    threads = host["affinity_cores"]
     done = 0
     t0 = time.perf_counter()
     with ThreadPoolExecutor(threads) as ex:
@@ -247,29 +350,16 @@ def cpu_baseline(name, workloads, seconds=15.0):
             list(ex.map(lambda m: oracle.sign(p, m, sk), chunk))
             done += len(chunk)
     el = time.perf_counter() - t0
-    # one thread on the following messages, for about a tenth of the time
     one, t1 = 0, time.perf_counter()
     while time.perf_counter() - t1 < seconds / 10 and one < 64:
         oracle.sign(p, msgs[(done + one) % len(msgs)], sk)
         one += 1
     el1 = time.perf_counter() - t1
     return {"value": done / el, "unit": "signatures/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d messages of the %s workload, key 0, %d host threads, %.1f s"
-                      % (done, name, threads, el),
+            "sample": "first %d messages of the %s workload, key 0, %d host threads (one per core of the "
+                      "process's affinity), %.1f s" % (done, name, threads, el),
+            "host": host,
             "single_thread": {"value": one / el1, "sample": "%d messages, 1 thread, %.1f s" % (one, el1)}}
-
-
-# HBM bytes per launch of the dominant kernel at batch 4096, from rocprofv3
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB per dispatch (a 1 GiB device copy
-# reads 524 300 KiB of FETCH_SIZE and 1 048 576 KiB of WRITE_SIZE); the
-# summaries are in profiles/.  Absent where not measured for the current
-# kernel.
-TRAFFIC = {  # (param, kernel) -> bytes per launch
-    (1, "k_fused"): (196340 * 2 + 1213936) * 1024,
-    (2, "k_tree"): (433141 * 2 + 2611425) * 1024,
-    (3, "k_tree"): (1172799 * 2 + 4684870) * 1024,
-    (7, "k_tree"): (199075 * 2 + 1197263) * 1024,
-}
 
 
 def latency_bench(slh, workloads, reps=20):
@@ -304,6 +394,25 @@ def latency_bench(slh, workloads, reps=20):
                 ts.append(time.perf_counter() - t0)
             out["sign_ms"]["%s/%d" % (slh.NAMES[p], batch)] = round(1e3 * sorted(ts)[reps // 2], 3)
     ctx.close()
+    return out
+
+
+def percentile(v, q):
+    """The library's percentile: the element at rank round(q (len - 1)) of the sorted values."""
+    return v[min(len(v) - 1, int(q * (len(v) - 1) + 0.5))]
+
+
+def per_set_latency(slh, params, lat, skip):
+    """p50 / p99 latency (ms) of each parameter set's requests after the first `skip`."""
+    import numpy as np
+    p = np.asarray(params[skip:])
+    lat = np.asarray(lat[skip:])
+    out = {}
+    for prm in sorted(set(params)):
+        v = np.sort(lat[p == prm])
+        if len(v):
+            out[slh.NAMES[prm]] = {"requests": int(len(v)), "p50_ms": round(float(percentile(v, 0.5)) * 1e3, 3),
+                                   "p99_ms": round(float(percentile(v, 0.99)) * 1e3, 3)}
     return out
 
 
@@ -359,10 +468,12 @@ def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lan
     for f in rates:
         arr = workloads.poisson_arrivals(n, f * sat)
         r, blob = slh.trace(params, ks, msgs, arr)
-        _, lat, st = srv.replay(r, blob, skip=min(1000, n // 10))
+        skip = min(1000, n // 10)
+        _, lat, st = srv.replay(r, blob, skip=skip)
         pt = {"load": f, "offered_sig_per_s": round(f * sat, 1), "sig_per_s": round(st["sig_per_s"], 1),
               "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
-              "mean_batch": round(st["mean_batch"], 1)}
+              "mean_batch": round(st["mean_batch"], 1),
+              "per_set": per_set_latency(slh, params, lat, skip)}
         out["points"].append(pt)
         log("serve: %s" % pt)
     srv.close()
@@ -372,7 +483,11 @@ def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lan
 def roofline(param, res):
     """Roofline of the dominant kernel: k_fused (FORS + TREE) in the fused
     modes, k_tree in the plain mode.  Kernel time from the library's HIP
-    events around that kernel on the benchmark's stream."""
+    events around that kernel on the benchmark's stream.  `achieved` prices
+    each compression at the textbook instruction count (one VALU operation
+    per FIPS 180-4 primitive: 1384 per SHA-256, 4144 per SHA-512 block on
+    32-bit lanes; 4320 per Keccak-f permutation); `isa_frac` prices it at
+    the instructions the compiled kernels issue per compression."""
     from paper_2512_23969_amd import accounting as acc
     phase, kernel, parts = ("fused", "k_fused", ("fors", "tree")) if res["phases"]["fused"][1] else \
         ("tree", "k_tree", ("tree",))
@@ -382,8 +497,8 @@ def roofline(param, res):
     per_launch_msgs = msgs / launches
     # with tree dedup only the distinct trees are computed
     scale = {"tree": res["dedup"][1] / res["dedup"][0] if res.get("dedup") else 1.0}
-    ops = sum(acc.ops_per_signature(param, p) * scale.get(p, 1.0) for p in parts) * per_launch_msgs
-    tb = sum(acc.ops_per_signature(param, p, textbook=True) * scale.get(p, 1.0) for p in parts) * per_launch_msgs
+    ops = sum(acc.ops_per_signature(param, p, textbook=True) * scale.get(p, 1.0) for p in parts) * per_launch_msgs
+    isa = sum(acc.ops_per_signature(param, p) * scale.get(p, 1.0) for p in parts) * per_launch_msgs
     avg_s = ms / launches / 1000.0
     achieved = ops / avg_s / 1e12
     peak = acc.VALU_PEAK_OPS / 1e12
@@ -391,17 +506,20 @@ def roofline(param, res):
     clk = (res["gpu"]["gfx_clock_mhz"] or {}).get("mean")
     units = {h: int(sum(c[h][p] * scale.get(p, 1.0) for p in parts) * per_launch_msgs)
              for h in ("sha256", "sha512", "keccak") if sum(c[h].values())}
+    traffic, source = profiled_traffic(res.get("name", ""), kernel)
     return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": round(peak, 3),
             "unit": "TOP/s (32-bit VALU lane-ops)", "frac": round(achieved / peak, 4),
-            "traffic": TRAFFIC.get((param, kernel)),
+            "traffic": traffic, "traffic_source": source,
             "avg_launch_ms": round(ms / launches, 4),
             "units_per_launch": units,
-            "ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512, "keccak": acc.OPS_KECCAK},
-            "textbook_frac": round(tb / avg_s / acc.VALU_PEAK_OPS, 4),
+            "ops_per_unit": {"sha256": acc.TEXTBOOK_SHA256, "sha512": acc.TEXTBOOK_SHA512,
+                             "keccak": acc.TEXTBOOK_KECCAK},
+            "isa_ops_per_unit": {"sha256": acc.OPS_SHA256, "sha512": acc.OPS_SHA512, "keccak": acc.OPS_KECCAK},
+            "isa_frac": round(isa / avg_s / acc.VALU_PEAK_OPS, 4),
             # the same work at the rate each hash's instruction mix reaches in
             # isolation (calibration probe): 1.0 = as fast as that mix runs
             "mix_ceiling_frac": round(acc.mix_ceiling_seconds(units) / avg_s, 4),
-            "single_rate_frac": round(ops / avg_s / acc.VALU_SINGLE_RATE_OPS, 4),
+            "single_rate_frac": round(isa / avg_s / acc.VALU_SINGLE_RATE_OPS, 4),
             # the same fractions against the peak at the graphics clock sampled
             # during the steps (the published peak assumes 2.4 GHz)
             "clock_mhz": clk,
@@ -444,14 +562,21 @@ def phase_rooflines(param, res, msg_bytes=32):
 
 
 def summary(acc, r, mode):
+    """The figures of one workload and mode for the line's "extra" object."""
     prm = r["cfg"]["param"]
-    out = {"value": round(r["sig_per_s"], 1), "ms_per_step": round(r["ms_per_step"], 3), "mode": mode,
-           "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm) / acc.VALU_PEAK_OPS, 4),
+    out = {"workload": r["name"], "value": round(r["sig_per_s"], 1), "unit": "signatures/s",
+           "ms_per_step": round(r["ms_per_step"], 3), "steps": r["steps"], "mode": mode, "tuning": r["tuning"],
+           "compressions_per_s": compressions_per_s(acc, prm, r["sig_per_s"]),
+           "useful_valu_frac": round(r["sig_per_s"] * acc.ops_per_signature(prm, textbook=True)
+                                     / acc.VALU_PEAK_OPS, 4),
            "roofline": roofline(prm, r) if "graph" not in mode else None,
            "phase_ms_per_step": {k: round(v[0] / r["steps"], 3) for k, v in r["phases"].items() if v[1]},
            "phase_roofline": phase_rooflines(prm, r), "step_ms": r["step_ms"],
            "gfx_clock_mhz": (r["gpu"]["gfx_clock_mhz"] or {}).get("mean"),
-           "socket_power_w": (r["gpu"]["socket_power_w"] or {}).get("mean")}
+           "socket_power_w": (r["gpu"]["socket_power_w"] or {}).get("mean"),
+           "energy": r["energy"]}
+    if r["verify"]:
+        out["verify"] = r["verify"]
     if r["dedup"]:
         trees, distinct = r["dedup"]
         out["dedup"] = {"trees_per_step": trees, "distinct_trees_per_step": distinct,
@@ -459,6 +584,12 @@ def summary(acc, r, mode):
                         "note": "identical signatures; work per signature below the paper's, "
                                 "so not the headline value"}
     return out
+
+
+def compressions_per_s(acc, param, sig_per_s):
+    c256, c512 = acc.compressions_per_signature(param)
+    return {"sha256": round(sig_per_s * c256, 0), "sha512": round(sig_per_s * c512, 0),
+            "keccak_f": round(sig_per_s * acc.permutations_per_signature(param), 0)}
 
 
 def main():
@@ -473,7 +604,10 @@ def main():
                          "within-batch tree dedup)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner first and store its result")
     ap.add_argument("--tune-out", default=None, help="tuning cache file (default: the package's tuning.json)")
-    ap.add_argument("--all", action="store_true", help="also time the 192f and 256f workloads")
+    ap.add_argument("--only", action="store_true",
+                    help="time the --workload alone (no 192f/256f/plain legs; profiler runs)")
+    ap.add_argument("--all", action="store_true",
+                    help="also time the small and SHAKE sets, the other modes and small-batch latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-n", type=int, default=100000, help="requests of the serving workload (0 = skip)")
@@ -482,9 +616,9 @@ def main():
     ap.add_argument("--serve-cache-layers", type=int, default=0,
                     help="upper hypertree layers cached per key on the server's lanes (dedup modes)")
     ap.add_argument("--serve-lanes", type=int, default=4, help="in-flight batches of the signing server")
-    ap.add_argument("--telemetry-s", type=float, default=1.0,
-                    help="seconds of further untimed steps (after a 1 s settle) over which amdsmi samples the "
-                         "clock and power; 0 = none (profiler runs)")
+    ap.add_argument("--telemetry-s", type=float, default=2.0,
+                    help="seconds of further untimed steps (after a 1 s settle) over which amdsmi reads the "
+                         "clock, power and energy counter; 0 = none (profiler runs)")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0 = keep the environment's). The serving leg "
                          "keeps 4 lanes x 4 streams busy; with 16 hardware queues none of them share one")
@@ -513,14 +647,12 @@ def main():
     from paper_2512_23969_amd import slh, workloads
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log("bench: workload", args.workload)
+    log("bench: workload", args.workload, args.mode)
     res = run(slh, workloads, args.workload, args.steps, args.warmup, args.mode, args.tune, args.tune_out,
               verify=True, telemetry_s=args.telemetry_s)
     param = res["cfg"]["param"]
-    c256, c512 = acc.compressions_per_signature(param)
-    ckf = acc.permutations_per_signature(param)
     line = {
-        "metric": "signatures/s (SPHINCS+-%s, batch %d)" % (acc.full_name(param), res["cfg"]["batch"]),
+        "metric": METRIC,
         "value": round(res["sig_per_s"], 1),
         "unit": "signatures/s",
         "n_gpus": 1,
@@ -528,22 +660,21 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(res["ms_per_step"], 4),
         "step_ms": res["step_ms"],
-        "gpu_telemetry": dict(res["gpu"], joules_per_signature=(
-            round(res["gpu"]["socket_power_w"]["mean"] / res["sig_per_s"], 6)
-            if res["gpu"]["socket_power_w"] else None)),
+        "gpu_telemetry": res["gpu"],
+        "energy": res["energy"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic (seeded random keys and 32-byte messages)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "parameter_set": "SPHINCS+-" + acc.full_name(param),
                    "batch": res["cfg"]["batch"], "keys": res["cfg"]["keys"], "msg_bytes": 32,
                    "mode": res["mode"], "tuning": res["tuning"],
                    "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
-        "compressions_per_s": {"sha256": round(res["sig_per_s"] * c256, 0),
-                               "sha512": round(res["sig_per_s"] * c512, 0),
-                               "keccak_f": round(res["sig_per_s"] * ckf, 0)},
-        "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param) / acc.VALU_PEAK_OPS, 4),
+        "compressions_per_s": compressions_per_s(acc, param, res["sig_per_s"]),
+        "useful_valu_frac": round(res["sig_per_s"] * acc.ops_per_signature(param, textbook=True)
+                                  / acc.VALU_PEAK_OPS, 4),
         "phase_ms_per_step": {k: round(v[0] / max(1, args.steps), 4) for k, v in res["phases"].items() if v[1]},
         "roofline": roofline(param, res),
         "phase_roofline": phase_rooflines(param, res),
@@ -551,34 +682,54 @@ def main():
     }
     if res["dedup"]:
         line["dedup"] = {"trees_per_step": res["dedup"][0], "distinct_trees_per_step": res["dedup"][1]}
+    extra = {}
+    steps_c = max(3, args.steps // 2)
+    if not args.only:
+        # every batch-4096 SHA2 fast-set workload in its autotuned mode and in
+        # the plain per-phase path, the reference the batched modes are
+        # measured against
+        from paper_2512_23969_amd import autotune
+        for name in DEFAULT_WORKLOADS:
+            cfg = workloads.CONFIGS[name]
+            tuned_mode = ((autotune.lookup(cfg["param"], cfg["batch"]) or {}).get("best") or {}).get("mode", "plain")
+            got = {}
+            for mode in dict.fromkeys((tuned_mode, "plain")):
+                if name == args.workload and mode == res["mode"]:
+                    got[mode] = summary(acc, res, mode)
+                    continue
+                log("bench: workload", name, mode)
+                r = run(slh, workloads, name, steps_c, args.warmup, mode, verify=True, telemetry_s=args.telemetry_s)
+                got[mode] = summary(acc, r, mode)
+            for mode, v in got.items():
+                extra["%s/%s" % (name, mode)] = v
+            tuned = [m for m in got if m != "plain"]
+            if tuned and "plain" in got:
+                extra["%s/tuned_vs_plain" % name] = {
+                    "tuned_mode": tuned[0], "ratio": round(got[tuned[0]]["value"] / got["plain"]["value"], 4)}
     if args.all:
         log("bench: small-batch latency")
         line["latency"] = latency_bench(slh, workloads)
-        # every batch-4096 workload in the plain per-phase path and in the
-        # batched modes (fused persistent kernel; hipGraph-captured pipeline;
-        # tree dedup), the small sets at batch 1024 and the SHAKE sets
-        extra = {}
-        steps_c = max(3, args.steps // 2)
+        # the other modes of the batch-4096 workloads (hipGraph-captured
+        # pipeline, tree dedup), the small sets at batch 1024 and the SHAKE sets
         for name in ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64", "s1_128s_1024", "s2_192s_1024",
                      "s3_256s_1024", "k1_shake128f_4096", "k2_shake192f_4096", "k3_shake256f_4096x64",
                      "k4_shake128s_1024"):
-            # the small sets take the per-phase path in every mode
             if name.startswith("s") or name.startswith("k4"):
-                modes = ("plain",)
+                modes = ("plain",)  # the small sets take the per-phase path in every mode
             elif name.startswith("k"):
                 modes = ("plain", "fused", "dedup")
             else:
-                modes = ("plain", "fused", "graph", "dedup", "fused-dedup")
+                modes = ("fused", "graph", "dedup", "fused-dedup")
             for mode in modes:
-                if name == args.workload and mode == res["mode"]:
+                key = "%s/%s" % (name, mode)
+                if key in extra or (name == args.workload and mode == res["mode"]):
                     continue
                 log("bench: workload", name, mode)
                 r = run(slh, workloads, name, steps_c, args.warmup, mode,
                         args.tune and mode == "plain" and name != args.workload, args.tune_out,
                         verify=mode == "plain", telemetry_s=args.telemetry_s)
-                extra["%s/%s" % (name, mode)] = summary(acc, r, mode)
-                if r["verify"]:
-                    extra["%s/verify" % name] = r["verify"]
+                extra[key] = summary(acc, r, mode)
+    if extra:
         line["extra"] = extra
     if args.serve_n:
         log("bench: serving")

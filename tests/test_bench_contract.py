@@ -27,8 +27,11 @@ def test_roofline_of_the_fused_kernel(param):
     msgs, ms = 4096, 14.0
     r = bench.roofline(param, _res(param, {"fused": ms, "prelude": 0.05, "wots": 0.13}, msgs, clock=2300.0))
     assert r["kernel"] == "k_fused" and r["bound"] == "alu" and r["unit"].startswith("TOP/s")
-    ops = (acc.ops_per_signature(param, "fors") + acc.ops_per_signature(param, "tree")) * msgs
+    # achieved prices every unit at the textbook count; isa_frac at the compiled count
+    ops = (acc.ops_per_signature(param, "fors", textbook=True) + acc.ops_per_signature(param, "tree", textbook=True)) * msgs
     assert r["achieved"] == pytest.approx(ops / (ms / 1e3) / 1e12, rel=1e-3)
+    isa = (acc.ops_per_signature(param, "fors") + acc.ops_per_signature(param, "tree")) * msgs
+    assert r["isa_frac"] == pytest.approx(isa / (ms / 1e3) / acc.VALU_PEAK_OPS, abs=1e-4)
     assert r["peak"] == pytest.approx(acc.VALU_PEAK_OPS / 1e12, rel=1e-4)
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], abs=1e-4)
     assert r["avg_launch_ms"] == pytest.approx(ms)
@@ -82,3 +85,34 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_energy_summary_and_per_set_percentiles():
+    e = bench.energy_summary(100.0, 112.0, 0.0, 2.0, 8192, "window")
+    assert e["mean_power_w"] == 6.0 and e["joules_per_signature"] == pytest.approx(12.0 / 8192, abs=1e-7)
+    # a counter that did not advance (or is missing) gives no figure
+    assert bench.energy_summary(100.0, 100.0, 0.0, 2.0, 8192, "w") is None
+    assert bench.energy_summary(None, 1.0, 0.0, 2.0, 8192, "w") is None
+
+    class _Slh:
+        NAMES = {1: "128f", 2: "192f"}
+    params = [1, 2] * 50
+    lat = [0.001 * (i + 1) for i in range(100)]
+    out = bench.per_set_latency(_Slh, params, lat, skip=10)
+    assert out["128f"]["requests"] == 45 and out["192f"]["requests"] == 45
+    # 128f holds the odd ranks 11, 13, ..., 99 (ms): the median is the 23rd of 45
+    assert out["128f"]["p50_ms"] == pytest.approx(55.0) and out["128f"]["p99_ms"] == pytest.approx(99.0)
+
+
+def test_traffic_only_from_counters_on_the_current_kernels(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.profiled_traffic("c2_128f_4096", "k_fused") == (None, "no counter summary")
+    import json
+    f.write_text(json.dumps({"device_source_sha256": bench.device_source_hash(),
+                             "entries": {"c2_128f_4096/k_fused": {"bytes_per_launch": 123, "summary": "x.md"}}}))
+    assert bench.profiled_traffic("c2_128f_4096", "k_fused") == (123, "x.md")
+    assert bench.profiled_traffic("c3_192f_4096", "k_tree")[0] is None
+    f.write_text(json.dumps({"device_source_sha256": "0" * 64,
+                             "entries": {"c2_128f_4096/k_fused": {"bytes_per_launch": 123}}}))
+    assert bench.profiled_traffic("c2_128f_4096", "k_fused")[0] is None
