@@ -215,6 +215,42 @@ int slh_sign_batch(slh_ctx *ctx, const slh_item *items, uint32_t count, const ui
                    uint64_t msgs_bytes, uint8_t *sigs, uint64_t sigs_bytes, uint32_t mode,
                    void *stream);
 
+/* slh_sign_batch for callers that cannot allocate memory: code that runs
+ * while a HIP graph is being captured, tight serving loops, harnesses that
+ * forbid hipMalloc.  The call allocates no device or pinned host memory and
+ * frees none (no hipMalloc, hipHostMalloc, hipFree or library allocator),
+ * and its host bookkeeping stays in buffers the context set up when it was
+ * created.  It signs exactly what slh_sign_batch signs, with the same
+ * kernels, and gives the same bytes.
+ *   items, count, msgs, msgs_bytes, sigs, sigs_bytes, stream
+ *               as in slh_sign_batch; count <= SLH_NOALLOC_MAX_ITEMS
+ *   mode        SLH_MODE_PLAIN, SLH_MODE_FUSED and SLH_MODE_DEDUP (bit
+ *               flags); SLH_MODE_GRAPH is refused (a graph is allocated)
+ * Working memory: one library-owned device array of
+ * SLH_NOALLOC_SCRATCH_BYTES on every GPU the library runs on (reserved when
+ * the library's code is loaded onto that GPU, held until the process ends).
+ * The batch's requests are copied into it, and each parameter set of the
+ * batch is signed in turn in chunks that fit the rest of it, on `stream`.
+ * With the default tuning a chunk holds up to about 900 / 410 / 230
+ * requests of 128f / 192f / 256f in SLH_MODE_PLAIN (with keep_chains = 0
+ * about 2700 / 1230 / 460); a set whose single request does not fit in the
+ * chosen mode and tuning is refused with SLH_EINVAL before anything is
+ * launched.
+ * The array is shared by every call on that GPU, from any context or
+ * stream, and keeps the previous call's contents (the kernels clear what
+ * they need): calls that overlap in time on one GPU race, and the caller
+ * must order them (one stream, or events).  Calls on one context are
+ * ordered by the library as for slh_sign_batch.  The keys must already be
+ * in the context (slh_ctx_add_keys allocates).
+ * Errors: SLH_EINVAL (as slh_sign_batch, plus count above
+ * SLH_NOALLOC_MAX_ITEMS, SLH_MODE_GRAPH, or a request too large for the
+ * array), SLH_EDEVICE. */
+#define SLH_NOALLOC_SCRATCH_BYTES (256ull << 20)
+#define SLH_NOALLOC_MAX_ITEMS 4096u
+int slh_sign_batch_noalloc(slh_ctx *ctx, const slh_item *items, uint32_t count,
+                           const uint8_t *msgs, uint64_t msgs_bytes, uint8_t *sigs,
+                           uint64_t sigs_bytes, uint32_t mode, void *stream);
+
 /* One request of the external interface (FIPS 205 Section 10; host memory,
  * 56 bytes).  Offsets index the batch's device message buffer.
  *   param, key_slot, msg_off, msg_len, sig_off   as in slh_item

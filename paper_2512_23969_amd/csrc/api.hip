@@ -22,6 +22,42 @@ namespace slh {
 thread_local std::string g_free_err;  // errors of the context-free calls
 }
 
+// Working memory of slh_sign_batch_noalloc: a fixed array in device memory,
+// one per GPU (each device that loads this code holds its own copy).  In host
+// code the name `scratch` does not denote device memory; the address of a
+// device's copy comes from hipGetSymbolAddress with that device current
+// (scratch_address) and is what every copy and kernel argument uses.
+// Layout: the batch's requests (SLH_NOALLOC_MAX_ITEMS DevItems), then the
+// working memory of one chunk.
+static __device__ __align__(256) uint8_t scratch[SLH_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kScratchItemBytes = (size_t(SLH_NOALLOC_MAX_ITEMS) * sizeof(DevItem) + kAlign - 1) / kAlign * kAlign;
+constexpr size_t kScratchWorkBytes = size_t(SLH_NOALLOC_SCRATCH_BYTES) - kScratchItemBytes;
+
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per
+// device, at the first context created on it).
+int scratch_address(int device, uint8_t** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(nullptr, SLH_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress of the no-allocation working array");
+    if (!p) return fail(nullptr, SLH_EDEVICE, "no device address for the no-allocation working array");
+    g_scratch[device] = static_cast<uint8_t*>(p);
+  }
+  *out = g_scratch[device];
+  return SLH_OK;
+}
+
+}  // namespace
+
 namespace {
 
 struct Sizes {
@@ -184,8 +220,8 @@ int validate_sign(slh_ctx* c, const slh_item* items, uint32_t count, const uint8
   if (!items || !sigs) return fail(c, SLH_EINVAL, "null items or signature buffer");
   if (mode & ~(SLH_MODE_FUSED | SLH_MODE_GRAPH | SLH_MODE_DEDUP)) return fail(c, SLH_EINVAL, "unknown mode");
   if (reinterpret_cast<uintptr_t>(sigs) % 16) return fail(c, SLH_EINVAL, "signature buffer not 16-byte aligned");
-  std::vector<std::pair<uint64_t, uint64_t>> ranges;
-  ranges.reserve(count);
+  std::vector<std::pair<uint64_t, uint64_t>>& ranges = c->ranges;
+  ranges.clear();
   for (int p = 0; p <= kSets; p++) per[p] = 0;
   for (uint32_t i = 0; i < count; i++) {
     const slh_item& it = items[i];
@@ -435,7 +471,6 @@ struct DevicePool {
   uint8_t* host = nullptr;
   size_t host_bytes = 0;
 };
-constexpr int kMaxDevices = 64;
 DevicePool g_pool[kMaxDevices];
 
 // Lock the pool of the current device and grow it to the requested sizes.
@@ -511,10 +546,17 @@ int slh_ctx_create(int device, uint64_t hbm_budget, slh_ctx** out) {
     e = hipStreamCreateWithFlags(&c->branch[b], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join[b], hipEventDisableTiming);
   }
-  if (e != hipSuccess) {
+  // what slh_sign_batch_noalloc needs on the host and the device, set up now
+  int rc = e == hipSuccess ? scratch_address(device, &c->scratch) : SLH_OK;
+  for (int k = 0; k < 2 && rc == SLH_OK && e == hipSuccess; k++)
+    rc = ensure_pinned(c, &c->slot[k].staging, &c->slot[k].staging_cap, SLH_NOALLOC_MAX_ITEMS, "sign items");
+  if (e != hipSuccess || rc != SLH_OK) {
+    const std::string msg = e != hipSuccess ? std::string("context set-up: ") + hipGetErrorString(e)
+                                            : (c->err.empty() ? g_free_err : c->err);
     slh_ctx_destroy(c);
-    return hip_fail(nullptr, e, "context set-up");
+    return fail(nullptr, e != hipSuccess ? SLH_EDEVICE : rc, msg);
   }
+  c->ranges.reserve(SLH_NOALLOC_MAX_ITEMS);
   for (int p = 1; p <= kSets; p++) c->tune[p].fg = fg_default(uint32_t(p));
   *out = c;
   return SLH_OK;
@@ -689,6 +731,43 @@ int slh_sign_batch(slh_ctx* c, const slh_item* items, uint32_t count, const uint
   int k = 0;
   if (int rc = begin_call(c, s, &k)) return rc;
   return finish_call(c, k, s, run_sign(c, k, items, nullptr, count, per, msgs, sigs, mode, s));
+}
+
+int slh_sign_batch_noalloc(slh_ctx* c, const slh_item* items, uint32_t count, const uint8_t* msgs,
+                           uint64_t msgs_bytes, uint8_t* sigs, uint64_t sigs_bytes, uint32_t mode, void* stream) {
+  if (!c) return fail(nullptr, SLH_EINVAL, "null context");
+  if (count == 0) return SLH_OK;
+  if (count > SLH_NOALLOC_MAX_ITEMS)
+    return fail(c, SLH_EINVAL, "more than SLH_NOALLOC_MAX_ITEMS requests in one call");
+  if (mode & SLH_MODE_GRAPH) return fail(c, SLH_EINVAL, "SLH_MODE_GRAPH allocates a graph; not without allocation");
+  size_t per[kSets + 1];
+  if (int rc = validate_sign(c, items, count, msgs, msgs_bytes, sigs, sigs_bytes, mode, per)) return rc;
+  for (int p = 1; p <= kSets; p++)
+    if (per[p] && set_ops(uint32_t(p)).plan_bytes(c, 1, mode) > kScratchWorkBytes)
+      return fail(c, SLH_EINVAL, "one request of parameter set " + std::to_string(p) +
+                                     " needs more working memory than the no-allocation array holds in this mode");
+  if (!c->scratch) return fail(c, SLH_EDEVICE, "no no-allocation working array on this device");
+  HIPCHK(c, hipSetDevice(c->device));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int k = 0;
+  if (int rc = begin_call(c, s, &k)) return rc;
+  // the slot's pinned item copy was sized for SLH_NOALLOC_MAX_ITEMS at creation
+  CallSlot& S = c->slot[k];
+  size_t start[kSets + 1];
+  group_items(items, nullptr, count, per, start, S.staging);
+  DevItem* d_items = reinterpret_cast<DevItem*>(c->scratch);
+  uint8_t* ws = c->scratch + kScratchItemBytes;
+  int rc = SLH_OK;
+  const hipError_t e = hipMemcpyAsync(d_items, S.staging, size_t(count) * sizeof(DevItem), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) rc = hip_fail(c, e, "upload of the requests");
+  // one parameter set after another, each in chunks that fit the array
+  for (int p = 1; p <= kSets && rc == SLH_OK; p++) {
+    if (!per[p]) continue;
+    const SetOps& ops = set_ops(uint32_t(p));
+    const size_t chunk = ops.chunk(c, per[p], mode, kScratchWorkBytes);
+    rc = ops.enqueue(c, ws, d_items + start[p], true, per[p], chunk, msgs, sigs, s, mode, false);
+  }
+  return finish_call(c, k, s, rc);
 }
 
 int slh_sign_batch_ext(slh_ctx* c, const slh_item_ext* items, uint32_t count, const uint8_t* msgs,

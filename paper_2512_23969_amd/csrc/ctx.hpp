@@ -100,6 +100,12 @@ struct slh_ctx {
   std::vector<uint32_t> key_cached;      // per key slot: cached layers
   uint8_t* xbuf = nullptr;               // device: encoded messages of the external interface
   size_t xbuf_bytes = 0;
+  // device address of this GPU's slh_sign_batch_noalloc working array
+  uint8_t* scratch = nullptr;
+  // signature ranges of the batch being validated (reserved at creation for
+  // SLH_NOALLOC_MAX_ITEMS requests, so that validating such a batch does not
+  // allocate)
+  std::vector<std::pair<uint64_t, uint64_t>> ranges;
 };
 
 namespace slh {

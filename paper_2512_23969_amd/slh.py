@@ -80,6 +80,9 @@ REQ_DTYPE = np.dtype([("param", "<u4"), ("key_slot", "<u4"), ("msg_off", "<u8"),
                       ("sig_off", "<u8"), ("arrival_s", "<f8")])
 assert REQ_DTYPE.itemsize == 40
 MAX_SIG_BYTES = 49856
+# slh_sign_batch_noalloc: requests per call and the per-GPU working array
+NOALLOC_MAX_ITEMS = 4096
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class slh_sizes(ctypes.Structure):
@@ -105,6 +108,7 @@ def _load():
     L.slh_keygen.argtypes = [u32, ctypes.c_char_p, vp, vp]
     L.slh_ctx_add_keys.argtypes = [vp, u32, ctypes.c_char_p, u32, ctypes.POINTER(u32)]
     L.slh_sign_batch.argtypes = [vp, vp, u32, vp, u64, vp, u64, u32, vp]
+    L.slh_sign_batch_noalloc.argtypes = [vp, vp, u32, vp, u64, vp, u64, u32, vp]
     L.slh_verify.argtypes = [u32, ctypes.c_char_p, sz, ctypes.c_char_p, sz, ctypes.c_char_p]
     L.slh_ctx_profile.argtypes = [vp, ctypes.c_int]
     L.slh_ctx_set_tuning.argtypes = [vp, u32, ctypes.POINTER(slh_tuning)]
@@ -267,6 +271,14 @@ class Context:
         _check(lib.slh_sign_batch(self.h, items.ctypes.data, len(items), mp, mb, sp, sb, int(mode), st),
                self.h)
 
+    def sign_batch_noalloc(self, items: np.ndarray, msgs, sigs, mode: int = MODE_PLAIN, stream=None):
+        """As sign_batch, through the entry point that allocates nothing (working
+        memory in the library's fixed per-GPU array; at most NOALLOC_MAX_ITEMS items)."""
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        mp, mb = _ptr(msgs)
+        sp, sb = _ptr(sigs)
+        _check(lib.slh_sign_batch_noalloc(self.h, items.ctypes.data, len(items), mp, mb, sp, sb, int(mode),
+                                          _stream_handle(stream)), self.h)
 
     def verify_batch_ext(self, items: np.ndarray, msgs, sigs, pks, results, stream=None):
         """Enqueue verification through the external interface (VERIFY_EXT_DTYPE items)."""
