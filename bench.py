@@ -102,9 +102,8 @@ def setup(slh, workloads, name):
     return ctx, items, d_m, d_s, cfg, msgs, kidx
 
 
-def verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps):
-    """Batched GPU verification of the batch just signed: every signature
-    must verify; throughput over `steps` launches."""
+def verify_inputs(slh, ctx, items, d_m, d_s, cfg, kidx):
+    """(items, msgs, sigs, pks, results) verifying the batch's signatures."""
     import numpy as np
     import torch
     param, batch = cfg["param"], cfg["batch"]
@@ -117,6 +116,15 @@ def verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps):
     vit["sig_off"] = items["sig_off"]
     vit["pk_off"] = np.asarray(kidx, dtype=np.uint64) * npk
     res = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    return vit, d_m, d_s, d_pk, res
+
+
+def verify_leg(slh, ctx, items, d_m, d_s, cfg, kidx, steps):
+    """Batched GPU verification of the batch just signed: every signature
+    must verify; throughput over `steps` launches."""
+    import torch
+    batch = cfg["batch"]
+    vit, d_m, d_s, d_pk, res = verify_inputs(slh, ctx, items, d_m, d_s, cfg, kidx)
     ctx.verify_batch(vit, d_m, d_s, d_pk, res)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -234,7 +242,11 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
     ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
     path = tune_out or autotune.DEFAULT_CACHE
     if tune:
-        best, _ = autotune.tune_and_store(slh, ctx, cfg["param"], items, d_m, d_s, cfg["batch"], path, log=log)
+        # the verification stage needs this batch signed first
+        ctx.sign_batch(items, d_m, d_s)
+        torch.cuda.synchronize()
+        best, _ = autotune.tune_and_store(slh, ctx, cfg["param"], items, d_m, d_s, cfg["batch"], path, log=log,
+                                          verify=verify_inputs(slh, ctx, items, d_m, d_s, cfg, kidx))
     else:
         best = (autotune.lookup(cfg["param"], cfg["batch"], path) or {}).get("best")
     tuned = None

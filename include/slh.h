@@ -351,10 +351,14 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
 #define SLH_NPHASES 5
 
 /* Per-parameter-set knobs of the signing kernels (the autotuner's search
- * space; the paper tunes its FORS fusion per GPU with Algorithm 1).
+ * space: the paper tunes its FORS fusion per GPU with Algorithm 1 and the
+ * Relax-FORS buffer, Section III-B, orders FORS_Sign, TREE_Sign and
+ * WOTS+_Sign as a task graph, Section III-F, and picks native or PTX code
+ * per kernel, Section III-C).  Every setting gives the same bytes.
  *   fors_trees_per_group  FORS trees reduced together by one workgroup:
  *                         4, 8 or 16 for 128f and 192f, 2, 4 or 8 for 256f
- *                         (0 = default: 8, 8, 4)
+ *                         (0 = default: 8, 8, 4); 1 or 2 FORS units of 2^12
+ *                         leaves for the small sets (0 = 1)
  *   wgs_per_cu            fused mode: persistent workgroups per compute unit
  *                         (0 = as many as fit, at most 64)
  *   keep_chains           1: the TREE phase keeps every value of the signing
@@ -367,14 +371,59 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *                         split over up to len one-wave workgroups, in every
  *                         mode: such a batch cannot fill the chip, and the
  *                         split cuts its latency (0 = default: 1.5 x the
- *                         number of compute units; SLH_SPLIT_NEVER = never) */
+ *                         number of compute units; SLH_SPLIT_NEVER = never)
+ *   fors_leaves_per_lane  FORS leaves one lane builds and reduces in
+ *                         registers before the LDS levels: 2 or 4 (0 = 2;
+ *                         the fast sets; the small sets take 2)
+ *   fors_threads          lanes of a FORS workgroup of the per-phase path:
+ *                         128, 256 or 512 (0 = 256; the fused kernel's
+ *                         workgroups have 256; fast sets only)
+ *   tree_waves            waves of a TREE block of the per-phase path (64
+ *                         hypertree leaves): 2, 4 or 8 (0 = 4; fast sets)
+ *   layer_order           SLH_LAYERS_PARALLEL: every hypertree layer of every
+ *                         signature in one TREE launch (the layers are
+ *                         independent once idx_tree is known), WOTS+ then a
+ *                         gather (keep_chains = 1) or a recomputation;
+ *                         SLH_LAYERS_IN_ORDER: FORS first, then one TREE
+ *                         launch per layer, whose signing leaves write their
+ *                         WOTS+ signature while their chains pass the digits
+ *                         of that layer's message (known once the layer
+ *                         below is done): nothing kept, nothing recomputed,
+ *                         no WOTS phase.  In-order signing takes the
+ *                         per-phase path in every mode except the dedup
+ *                         modes, which keep the parallel order (fast sets)
+ *   variant_tree, variant_fors, variant_verify
+ *                         instruction variant of the SHA-2 arithmetic in the
+ *                         TREE, FORS and verification kernels of the SHA2
+ *                         fast sets: SLH_VARIANT_DEFAULT (v_bitop3 logic,
+ *                         three-input and fused 64-bit adds),
+ *                         SLH_VARIANT_NO_BITOP3 (two-input XORs and v_bfi),
+ *                         SLH_VARIANT_SPLIT_ADDS (two-input adds, 64-bit adds
+ *                         as carry pairs).  A variant other than the default
+ *                         exists for the default shape of its kernel
+ *                         (tree_waves 4; fors_leaves_per_lane 2 and
+ *                         fors_threads 256); the fused kernel has the
+ *                         default only */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;
     uint32_t keep_chains;
     uint32_t split_max_blocks;
+    uint32_t fors_leaves_per_lane;
+    uint32_t fors_threads;
+    uint32_t tree_waves;
+    uint32_t layer_order;
+    uint32_t variant_tree;
+    uint32_t variant_fors;
+    uint32_t variant_verify;
+    uint32_t reserved; /* 0 */
 } slh_tuning;
 #define SLH_SPLIT_NEVER 0xFFFFFFFFu
+#define SLH_LAYERS_PARALLEL 0u
+#define SLH_LAYERS_IN_ORDER 1u
+#define SLH_VARIANT_DEFAULT 0u
+#define SLH_VARIANT_NO_BITOP3 1u
+#define SLH_VARIANT_SPLIT_ADDS 2u
 
 /* Set or read the knobs of parameter set `param` on a context.  Setting
  * waits for the context's pending work.  Errors: SLH_EINVAL. */

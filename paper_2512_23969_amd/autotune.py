@@ -14,17 +14,19 @@ are timed on the GPU and the fastest is kept.
   library's FORS kernels, whose unit is a group of trees reduced by one
   256-lane workgroup with two leaves per lane: the LDS per group must fit the
   160 KiB of a CU, and the groups are ranked by barrier count per message.
-* ``tune(...)`` times every compiled variant (execution mode, FORS trees per
-  group, persistent workgroups per CU) on a real batch and returns the
-  fastest; results are cached in a JSON file keyed by GPU architecture,
-  parameter set and batch size.
+* ``tune(...)`` times the compiled variants on a real batch, kernel by
+  kernel (the FORS shape and instruction variant from the FORS kernel's own
+  HIP events; TREE block size, layer order, kept or recomputed chains and
+  the TREE instruction variant from whole steps; then the per-phase path
+  against the fused persistent kernel; then the verification kernel's
+  variant) and keeps the fastest; results are cached in a JSON file keyed
+  by GPU architecture, parameter set and batch size.
 """
 from __future__ import annotations
 
 import json
 import math
 import os
-import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuning.json")
@@ -132,43 +134,177 @@ def lookup(param: int, batch: int, path: str = DEFAULT_CACHE):
     return c.get(cache_key(_arch(), param, batch))
 
 
-def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 3, modes=("plain", "fused"),
-         wgs=(0, 1, 2, 3), log=None):
-    """Time every compiled variant on this batch; returns (best, table)."""
+# Knobs the empirical stage searches, per parameter-set family (slh.h
+# slh_tuning): fast sets have every FORS and TREE shape and both layer
+# orders; the SHA2 fast sets also the instruction variants; the small sets
+# only the FORS group size and keep_chains.
+LPLS = (2, 4)
+FORS_THREADS = (128, 256, 512)
+TREE_WAVES = (2, 4, 8)
+VARIANTS = (1, 2)  # SLH_VARIANT_NO_BITOP3, SLH_VARIANT_SPLIT_ADDS (0 is the default)
+WGS_PER_CU = (0, 1, 2, 3)
+KNOB_DEFAULTS = {"fors_trees_per_group": 0, "wgs_per_cu": 0, "keep_chains": 1, "split_max_blocks": 0,
+                 "fors_leaves_per_lane": 2, "fors_threads": 256, "tree_waves": 4, "layer_order": 0,
+                 "variant_tree": 0, "variant_fors": 0, "variant_verify": 0}
+
+
+def _fast(param):
+    return (param - 1) % 6 < 3
+
+
+def _sha2_fast(param):
+    return param <= 3
+
+
+def _median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def _events_ms(torch, stream, run, reps):
+    """Median and minimum over `reps` calls of run() of the GPU time between
+    HIP events recorded on `stream` around each call (after one warm-up)."""
+    run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        run()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    return _median(t), min(t)
+
+
+def _phase_ms(slh, ctx, run, phases, reps):
+    """Median over `reps` calls of the summed GPU time of `phases` (the
+    library's per-kernel HIP events), after one warm-up."""
     import torch
-    table = []
-    for mode in modes:
+    run()
+    torch.cuda.synchronize()
+    ctx.phase_times(reset=True)
+    ctx.profile(True)
+    per = []
+    for _ in range(reps):
+        run()
+        pt = ctx.phase_times(reset=True)
+        per.append(sum(pt[p][0] for p in phases))
+    ctx.profile(False)
+    return _median(per), min(per)
+
+
+def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 7, log=None, verify=None):
+    """Time the compiled variants on this batch, one kernel at a time as the
+    paper does (its per-kernel choice of code, Section III-C), then the
+    execution mode; returns (best, stages).
+
+      1. FORS kernel (per-phase path, its own HIP events): trees per group x
+         leaves per lane x workgroup lanes, and the instruction variants;
+      2. TREE and WOTS+ (whole step, HIP events): block waves x layer order
+         (parallel with kept or recomputed chains, or in order), and the
+         instruction variants;
+      3. mode: the per-phase path with the winners of 1-2 against the fused
+         persistent kernel (trees per group x leaves per lane x persistent
+         workgroups per CU x keep_chains);
+      4. verification (if `verify` = (items, msgs, sigs, pks, results) is
+         given): the instruction variants of the verify kernel.
+    Every point is the median of `reps` timed runs after a warm-up."""
+    import torch
+    stream = torch.cuda.current_stream()
+    stages = {"fors": [], "tree": [], "mode": [], "verify": []}
+
+    def knobs(**kw):
+        k = dict(KNOB_DEFAULTS)
+        k.update(kw)
+        return k
+
+    def setk(k):
+        ctx.set_tuning(param, **{f: v for f, v in k.items() if f in KNOB_DEFAULTS})
+
+    def say(stage, row):
+        stages[stage].append(row)
+        if log:
+            log("tune %s %s %s" % (param, stage, row))
+
+    def sign(mode):
+        return lambda: ctx.sign_batch(items, d_msgs, d_sigs, mode=slh.MODES[mode], stream=stream)
+
+    # 1. FORS
+    fors = []
+    for fg in slh.FORS_GROUPS[param]:
+        shapes = [(l, t, 0) for l in LPLS for t in FORS_THREADS] if _fast(param) else [(2, 256, 0)]
+        if _sha2_fast(param):
+            shapes += [(2, 256, v) for v in VARIANTS]
+        for lpl, ft, var in shapes:
+            k = knobs(fors_trees_per_group=fg, fors_leaves_per_lane=lpl, fors_threads=ft, variant_fors=var)
+            setk(k)
+            med, mn = _phase_ms(slh, ctx, sign("plain"), ("fors",), reps)
+            row = dict(k, ms=round(med, 4), min_ms=round(mn, 4))
+            say("fors", row)
+            fors.append(row)
+    fb = min(fors, key=lambda r: r["ms"])
+    base = knobs(**{f: fb[f] for f in ("fors_trees_per_group", "fors_leaves_per_lane", "fors_threads",
+                                        "variant_fors")})
+    # 2. TREE and WOTS+ (layer order, keep, block waves, variants)
+    tree = []
+    orders = [(0, 1), (0, 0), (1, 0)] if _fast(param) else [(0, 1), (0, 0)]
+    for order, keep in orders:
+        for waves in (TREE_WAVES if _fast(param) else (4,)):
+            for var in (0,) + (VARIANTS if _sha2_fast(param) and waves == 4 else ()):
+                k = dict(base, layer_order=order, keep_chains=keep, tree_waves=waves, variant_tree=var)
+                setk(k)
+                med, mn = _events_ms(torch, stream, sign("plain"), reps)
+                row = dict(k, mode="plain", ms=round(med, 4), min_ms=round(mn, 4))
+                say("tree", row)
+                tree.append(row)
+    best = min(tree, key=lambda r: r["ms"])
+    say("mode", dict(best))
+    # 3. the fused persistent kernel (parallel layers; workgroups of 256 lanes)
+    if _fast(param):
         for fg in slh.FORS_GROUPS[param]:
-            for wpc in (wgs if mode == "fused" else (0,)):
-                ctx.set_tuning(param, fg, wpc, 1)
-                m = slh.MODES[mode]
-                ctx.sign_batch(items, d_msgs, d_sigs, mode=m)  # warm-up
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    ctx.sign_batch(items, d_msgs, d_sigs, mode=m)
-                torch.cuda.synchronize()
-                ms = (time.perf_counter() - t0) * 1000.0 / reps
-                row = {"mode": mode, "fors_trees_per_group": fg, "wgs_per_cu": wpc, "keep_chains": 1,
-                       "ms": round(ms, 4)}
-                table.append(row)
-                if log:
-                    log("tune %s %s" % (param, row))
-    best = min(table, key=lambda r: r["ms"])
-    return best, table
+            for lpl in LPLS:
+                for wpc in WGS_PER_CU:
+                    for keep in (1, 0):
+                        k = knobs(fors_trees_per_group=fg, fors_leaves_per_lane=lpl, wgs_per_cu=wpc,
+                                  keep_chains=keep)
+                        setk(k)
+                        med, mn = _events_ms(torch, stream, sign("fused"), reps)
+                        row = dict(k, mode="fused", ms=round(med, 4), min_ms=round(mn, 4))
+                        say("mode", row)
+                        if row["ms"] < best["ms"]:
+                            best = row
+    # 4. verification
+    best = dict(best)
+    if verify is not None:
+        vitems, vm, vs, vpk, vres = verify
+        vbest = None
+        for var in ((0,) + VARIANTS if _sha2_fast(param) else (0,)):
+            setk(knobs(variant_verify=var))
+            med, mn = _events_ms(torch, stream, lambda: ctx.verify_batch(vitems, vm, vs, vpk, vres, stream=stream),
+                                 reps)
+            row = {"variant_verify": var, "ms": round(med, 4), "min_ms": round(mn, 4)}
+            say("verify", row)
+            if vbest is None or row["ms"] < vbest["ms"]:
+                vbest = row
+        best["variant_verify"] = vbest["variant_verify"]
+    apply(ctx, param, best)
+    return best, stages
 
 
-def tune_and_store(slh, ctx, param, items, d_msgs, d_sigs, batch, path: str = DEFAULT_CACHE, log=None):
-    best, table = tune(slh, ctx, param, items, d_msgs, d_sigs, log=log)
+def tune_and_store(slh, ctx, param, items, d_msgs, d_sigs, batch, path: str = DEFAULT_CACHE, log=None,
+                   verify=None, reps: int = 7):
+    best, stages = tune(slh, ctx, param, items, d_msgs, d_sigs, reps=reps, log=log, verify=verify)
     c = load_cache(path)
-    c[cache_key(_arch(), param, batch)] = {"best": best, "table": table,
-                                            "analytic": gfx950_groups(param)}
+    c[cache_key(_arch(), param, batch)] = {
+        "best": best, "stages": stages, "analytic": gfx950_groups(param),
+        "timing": "median of %d runs after a warm-up: HIP events around each call on the signing stream "
+                  "(the FORS stage: the library's events around the FORS kernel)" % reps}
     with open(path, "w") as f:
         json.dump(c, f, indent=1, sort_keys=True)
-    return best, table
+    return best, stages
 
 
 def apply(ctx, param: int, setting: dict):
     """Set the tuned knobs on a context; returns the tuned mode name."""
-    ctx.set_tuning(param, setting["fors_trees_per_group"], setting["wgs_per_cu"], setting["keep_chains"])
-    return setting["mode"]
+    ctx.set_tuning(param, **{f: setting.get(f, v) for f, v in KNOB_DEFAULTS.items()})
+    return setting.get("mode", "plain")

@@ -287,9 +287,7 @@ int run_sign(slh_ctx* c, int k, const slh_item* items, const uint64_t* rnd, uint
     key.n[p] = per[p];
     key.ws[p] = c->ws[p];
     key.ws_bytes[p] = c->ws_bytes[p];
-    key.fg[p] = c->tune[p].fg;
-    key.wpc[p] = c->tune[p].wgs_per_cu;
-    key.keep[p] = c->tune[p].keep;
+    key.tune[p] = c->tune[p];
   }
   key.n[0] = mode & (SLH_MODE_FUSED | SLH_MODE_DEDUP);
   key.msgs = msgs;
@@ -452,8 +450,8 @@ int run_verify(slh_ctx* c, int k, const slh_verify_item* items, uint32_t count, 
     if (!per[p]) continue;
     // 16 lanes per signature give 1024 signatures one wave per SIMD; below
     // kVerifyWideMax signatures 32 lanes each keep more of the chip busy
-    set_ops(uint32_t(p)).verify(d + start[p], uint32_t(per[p]), per[p] <= kVerifyWideMax, msgs, sigs, pks,
-                                results, s);
+    set_ops(uint32_t(p)).verify(d + start[p], uint32_t(per[p]), per[p] <= kVerifyWideMax, c->tune[p].vverify,
+                                msgs, sigs, pks, results, s);
   }
   HIPCHK(c, hipGetLastError());
   return SLH_OK;
@@ -848,30 +846,80 @@ int slh_verify_batch_ext(slh_ctx* c, const slh_verify_item_ext* items, uint32_t 
   return finish_call(c, k, s, rc);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Knobs of set `param` from a caller's slh_tuning (0 = default), checked
+// against the compiled kernels; on error *msg says why.
+bool resolve_tuning(uint32_t param, const slh_tuning& t, Tuning* out, std::string* msg) {
+  Tuning r;
+  r.fg = t.fors_trees_per_group ? t.fors_trees_per_group : fg_default(param);
+  if (!fg_ok(param, r.fg)) return *msg = "no compiled FORS variant with that many trees per group", false;
+  if (t.wgs_per_cu > 64) return *msg = "wgs_per_cu above 64", false;
+  if (t.keep_chains > 1) return *msg = "keep_chains must be 0 or 1", false;
+  r.wgs_per_cu = t.wgs_per_cu;
+  r.keep = t.keep_chains;
+  r.split = t.split_max_blocks;
+  r.lpl = t.fors_leaves_per_lane ? t.fors_leaves_per_lane : 2u;
+  r.fors_threads = t.fors_threads ? t.fors_threads : uint32_t(kForsThreads);
+  r.tree_waves = t.tree_waves ? t.tree_waves : 4u;
+  r.inorder = t.layer_order;
+  r.vtree = t.variant_tree;
+  r.vfors = t.variant_fors;
+  r.vverify = t.variant_verify;
+  if (r.lpl != 2 && r.lpl != 4) return *msg = "fors_leaves_per_lane must be 2 or 4", false;
+  if (r.fors_threads != 128 && r.fors_threads != 256 && r.fors_threads != 512)
+    return *msg = "fors_threads must be 128, 256 or 512", false;
+  if (r.tree_waves != 2 && r.tree_waves != 4 && r.tree_waves != 8) return *msg = "tree_waves must be 2, 4 or 8", false;
+  if (r.inorder > SLH_LAYERS_IN_ORDER) return *msg = "unknown layer_order", false;
+  if (r.vtree > SLH_VARIANT_SPLIT_ADDS || r.vfors > SLH_VARIANT_SPLIT_ADDS || r.vverify > SLH_VARIANT_SPLIT_ADDS)
+    return *msg = "unknown instruction variant", false;
+  if (t.reserved) return *msg = "reserved field must be 0", false;
+  if (!fast_set(param) && (r.lpl != 2 || r.fors_threads != uint32_t(kForsThreads) || r.tree_waves != 4 || r.inorder))
+    return *msg = "the small parameter sets have the default kernel shapes and layer order only", false;
+  if (!sha2_fast_set(param) && (r.vtree || r.vfors || r.vverify))
+    return *msg = "instruction variants exist for the SHA2 fast sets only", false;
+  if (r.vtree && r.tree_waves != 4) return *msg = "TREE instruction variants exist at tree_waves 4 only", false;
+  if (r.vfors && (r.lpl != 2 || r.fors_threads != uint32_t(kForsThreads)))
+    return *msg = "FORS instruction variants exist at 2 leaves per lane and 256 lanes only", false;
+  *out = r;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 int slh_ctx_set_tuning(slh_ctx* c, uint32_t param, const slh_tuning* t) {
   Sizes sz;
   if (!c) return fail(nullptr, SLH_EINVAL, "null context");
   if (!t || !sizes_of(param, &sz)) return fail(c, SLH_EINVAL, "unknown parameter set or null tuning");
-  const uint32_t fg = t->fors_trees_per_group ? t->fors_trees_per_group : fg_default(param);
-  if (!fg_ok(param, fg)) return fail(c, SLH_EINVAL, "no compiled FORS variant with that many trees per group");
-  if (t->wgs_per_cu > 64) return fail(c, SLH_EINVAL, "wgs_per_cu above 64");
-  if (t->keep_chains > 1) return fail(c, SLH_EINVAL, "keep_chains must be 0 or 1");
+  Tuning r;
+  std::string msg;
+  if (!resolve_tuning(param, *t, &r, &msg)) return fail(c, SLH_EINVAL, msg);
   if (int rc = wait_all(c)) return rc;
   drop_graphs(c);
-  c->tune[param].fg = fg;
-  c->tune[param].wgs_per_cu = t->wgs_per_cu;
-  c->tune[param].keep = t->keep_chains;
-  c->tune[param].split = t->split_max_blocks;
+  c->tune[param] = r;
   return SLH_OK;
 }
 
 int slh_ctx_get_tuning(const slh_ctx* c, uint32_t param, slh_tuning* t) {
   Sizes sz;
   if (!c || !t || !sizes_of(param, &sz)) return fail(nullptr, SLH_EINVAL, "null argument or unknown parameter set");
-  t->fors_trees_per_group = c->tune[param].fg;
-  t->wgs_per_cu = c->tune[param].wgs_per_cu;
-  t->keep_chains = c->tune[param].keep;
-  t->split_max_blocks = c->tune[param].split;
+  const Tuning& r = c->tune[param];
+  *t = slh_tuning{};
+  t->fors_trees_per_group = r.fg;
+  t->wgs_per_cu = r.wgs_per_cu;
+  t->keep_chains = r.keep;
+  t->split_max_blocks = r.split;
+  t->fors_leaves_per_lane = r.lpl;
+  t->fors_threads = r.fors_threads;
+  t->tree_waves = r.tree_waves;
+  t->layer_order = r.inorder;
+  t->variant_tree = r.vtree;
+  t->variant_fors = r.vfors;
+  t->variant_verify = r.vverify;
   return SLH_OK;
 }
 
@@ -928,7 +976,7 @@ int slh_verify(uint32_t param, const uint8_t* msg, size_t msg_len, const uint8_t
   hipError_t e = hipMemcpyAsync(P->dev, P->host, o_res, hipMemcpyHostToDevice, P->stream);
   if (e != hipSuccess) return hip_fail(nullptr, e, "verify upload");
   int* d_res = reinterpret_cast<int*>(P->dev + o_res);
-  set_ops(param).verify(reinterpret_cast<const VerifyItem*>(P->dev), 1u, true, P->dev + o_msg, P->dev + o_sig,
+  set_ops(param).verify(reinterpret_cast<const VerifyItem*>(P->dev), 1u, true, 0u, P->dev + o_msg, P->dev + o_sig,
                         P->dev + o_pk, d_res, P->stream);
   e = hipGetLastError();
   int* h_res = reinterpret_cast<int*>(P->host + o_res);

@@ -23,12 +23,18 @@ constexpr int kBranches = 3;  // branch streams per context
 constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Knobs of one parameter set (see slh_tuning in slh.h).
+// Knobs of one parameter set (see slh_tuning in slh.h), all resolved (no
+// "0 = default" left).
 struct Tuning {
   uint32_t fg = 0;          // FORS trees per workgroup (0 = default of the set)
   uint32_t wgs_per_cu = 0;  // fused mode: persistent workgroups per CU (0 = occupancy limit)
   uint32_t keep = 1;        // keep signing-leaf chain values for the WOTS gather
   uint32_t split = 0;       // split_max_blocks (0 = 1.5 x the CU count)
+  uint32_t lpl = 2;         // FORS leaves per lane
+  uint32_t fors_threads = kForsThreads;  // lanes of a per-phase FORS workgroup
+  uint32_t tree_waves = 4;  // waves of a per-phase TREE block
+  uint32_t inorder = 0;     // layers signed in order
+  uint32_t vtree = 0, vfors = 0, vverify = 0;  // SHA-2 instruction variants
 };
 
 struct GraphKey {
@@ -38,7 +44,7 @@ struct GraphKey {
   const void* staging;  // pinned item copy the captured upload reads
   uint8_t* ws[kSets + 1];
   size_t ws_bytes[kSets + 1];
-  uint32_t fg[kSets + 1], wpc[kSets + 1], keep[kSets + 1];
+  Tuning tune[kSets + 1];
   bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof o) == 0; }
 };
 
@@ -182,6 +188,10 @@ inline uint32_t fg_default(uint32_t param) {
   param = shape_of(param);
   return param >= 4 ? 1u : (param == 3 ? 4u : 8u);
 }
+// Fast sets (whole XMSS and FORS trees): the shape knobs and in-order layers
+// apply; SHA2 fast sets: the instruction variants too.
+inline bool fast_set(uint32_t param) { return shape_of(param) <= 3; }
+inline bool sha2_fast_set(uint32_t param) { return param <= 3; }
 
 // Most cached layers per parameter set: at most 2^16 trees per key.
 // (the small sets' trees are built in units; they are not cached)
@@ -207,8 +217,8 @@ struct SetOps {
   size_t keygen_bytes;
   int (*keygen)(uint8_t* dev, hipStream_t s);
   int (*cache)(slh_ctx* c, uint32_t first, uint32_t count, uint32_t layers, hipStream_t s);
-  void (*verify)(const VerifyItem* items, uint32_t count, bool wide, const uint8_t* msgs, const uint8_t* sigs,
-                 const uint8_t* pks, int* results, hipStream_t s);
+  void (*verify)(const VerifyItem* items, uint32_t count, bool wide, uint32_t variant, const uint8_t* msgs,
+                 const uint8_t* sigs, const uint8_t* pks, int* results, hipStream_t s);
 };
 constexpr size_t kKeygenRootOff = 256;
 

@@ -327,23 +327,33 @@ struct ForsShape {
 };
 
 // One group of FG units (flat unit ids group*FG ...; unit u of tree ft is
-// ft * UNITS + u).  `node` is LDS of FG * PAIRS * NW words.  All threads of
-// the workgroup must call it.
-template <int ID, int FG>
+// ft * UNITS + u), reduced by a workgroup of FT lanes.  LPL (leaves per
+// lane, the paper's Relax-FORS per-thread buffer, Section III-B): each lane
+// task builds LPL = 2 or 4 sibling leaves and reduces them in registers to
+// one node of level log2(LPL); those nodes go to LDS.  `node` is LDS of
+// FG * BASE * NW words.  All threads of the workgroup must call it.
+template <int ID, int LPL>
+struct ForsLeaves {
+  static_assert(LPL == 2 || LPL == 4, "two or four leaves per lane");
+  static constexpr int L0 = LPL == 4 ? 2 : 1;                 // level of the nodes that go to LDS
+  static constexpr int BASE = 1 << (P<ID>::unit_a - L0);      // such nodes per unit
+};
+
+template <int ID, int FG, int LPL = 2, int FT = kForsThreads, int V = 0>
 __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, const WorkRec* __restrict__ recs,
                            uint32_t nunits, uint8_t* sigs, uint32_t* __restrict__ roots, uint32_t group,
                            uint32_t* node) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, A = Q::a, KT = Q::k, AU = Q::unit_a, UNITS = ForsShape<ID>::UNITS;
-  constexpr int PAIRS = ForsShape<ID>::PAIRS;
+  constexpr int L0 = ForsLeaves<ID, LPL>::L0, BASE = ForsLeaves<ID, LPL>::BASE;
   const uint32_t fu0 = group * FG;
 
-  // pair phase
-  for (int q = threadIdx.x; q < FG * PAIRS; q += kForsThreads) {
-    const uint32_t fu = fu0 + q / PAIRS;
+  // leaf phase: one task per level-L0 node
+  for (int q = threadIdx.x; q < FG * BASE; q += FT) {
+    const uint32_t fu = fu0 + q / BASE;
     if (fu >= nunits) break;  // q only grows, so the rest of this lane's tasks are out too
     const uint32_t ft = fu / UNITS, u = fu % UNITS;
-    const uint32_t j = (u << (AU - 1)) + q % PAIRS;  // pair index within the tree
+    const uint32_t j = (u << (AU - L0)) + q % BASE;  // level-L0 node index within the tree
     const uint32_t msg = ft / KT, t = ft - msg * KT;
     const WorkRec& W = recs[msg];
     const DevKey& K = keys[W.key_slot];
@@ -351,42 +361,55 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
     const uint32_t kp = W.idx_leaf;
     const uint32_t idx = W.indices[t];
     uint8_t* tsig = sigs + W.sig_off + Q::n + t * (A + 1) * Q::n;
-    uint32_t mid[8], sks[NW], sk[NW], lr[2 * NW];
+    uint32_t mid[8], sks[NW];
     load_words<8>(K.mid256, mid);
     load_words<NW>(K.sk_seed, sks);
-    const uint32_t g0 = (t << A) + 2 * j;
-    // four hashes: PRF(leaf 2j), F(leaf 2j), PRF(leaf 2j+1), F(leaf 2j+1)
+    uint32_t lvl1[(LPL / 2) * NW];  // this task's level-1 nodes, left to right
+#pragma unroll
+    for (int pr = 0; pr < LPL / 2; pr++) {
+      const uint32_t jp = j * (LPL / 2) + pr;  // level-1 node (leaf pair) index within the tree
+      const uint32_t g0 = (t << A) + 2 * jp;
+      uint32_t sk[NW], lr[2 * NW];
+      // four hashes: PRF(leaf 2jp), F(leaf 2jp), PRF(leaf 2jp+1), F(leaf 2jp+1)
 #pragma unroll 1
-    for (int c = 0; c < 4; c++) {
-      const uint32_t g = g0 + (c >> 1);
-      const bool isF = c & 1;
-      uint32_t in[NW], out[NW];
+      for (int c = 0; c < 4; c++) {
+        const uint32_t g = g0 + (c >> 1);
+        const bool isF = c & 1;
+        uint32_t in[NW], out[NW];
 #pragma unroll
-      for (int u = 0; u < NW; u++) in[u] = isF ? sk[u] : sks[u];
-      thF<ID>(mid, make_adrs(0, tree, isF ? A_FORS_TREE : A_FORS_PRF, kp, 0, g), in, out);
-      if (!isF) {
+        for (int w = 0; w < NW; w++) in[w] = isF ? sk[w] : sks[w];
+        thF<ID, V>(mid, make_adrs(0, tree, isF ? A_FORS_TREE : A_FORS_PRF, kp, 0, g), in, out);
+        if (!isF) {
 #pragma unroll
-        for (int u = 0; u < NW; u++) sk[u] = out[u];
-        if (g == (t << A) + idx) store_be<NW>(tsig, sk);  // the selected secret value
-      } else {
+          for (int w = 0; w < NW; w++) sk[w] = out[w];
+          if (g == (t << A) + idx) store_be<NW>(tsig, sk);  // the selected secret value
+        } else {
 #pragma unroll
-        for (int u = 0; u < NW; u++) {
-          if (c == 1) lr[u] = out[u]; else lr[NW + u] = out[u];
+          for (int w = 0; w < NW; w++) {
+            if (c == 1) lr[w] = out[w]; else lr[NW + w] = out[w];
+          }
         }
       }
+      if ((idx >> 1) == jp) store_be<NW>(tsig + Q::n, (idx & 1) ? lr : lr + NW);  // auth[0]
+      thH<ID, V>(K, make_adrs(0, tree, A_FORS_TREE, kp, 1, (t << (A - 1)) + jp), lr, &lvl1[pr * NW]);
+      if (((idx >> 1) ^ 1u) == jp) store_be<NW>(tsig + 2 * Q::n, &lvl1[pr * NW]);  // auth[1]
     }
-    if ((idx >> 1) == j) store_be<NW>(tsig + Q::n, (idx & 1) ? lr : lr + NW);  // auth[0]
-    uint32_t par[NW];
-    thH<ID>(K, make_adrs(0, tree, A_FORS_TREE, kp, 1, (t << (A - 1)) + j), lr, par);
-    if (((idx >> 1) ^ 1u) == j) store_be<NW>(tsig + 2 * Q::n, par);  // auth[1]
-    store_words<NW>(&node[q * NW], par);
+    if constexpr (L0 == 1) {
+      store_words<NW>(&node[q * NW], lvl1);
+    } else {
+      uint32_t par[NW];
+      thH<ID, V>(K, make_adrs(0, tree, A_FORS_TREE, kp, 2, (t << (A - 2)) + j), lvl1, par);
+      if (((idx >> 2) ^ 1u) == j) store_be<NW>(tsig + 3 * Q::n, par);  // auth[2]
+      store_words<NW>(&node[q * NW], par);
+    }
   }
   __syncthreads();
-  // level phase
+  // level phase: levels L0+1 .. AU in LDS; node q of level z is written over
+  // its left child (slot q << (z - L0))
 #pragma unroll 1
-  for (int z = 2; z <= AU; z++) {
+  for (int z = L0 + 1; z <= AU; z++) {
     const int per = 1 << (AU - z);  // nodes of level z per unit
-    for (int q = threadIdx.x; q < FG * per; q += kForsThreads) {
+    for (int q = threadIdx.x; q < FG * per; q += FT) {
       const uint32_t fu = fu0 + q / per;
       if (fu >= nunits) break;
       const uint32_t ft = fu / UNITS, u = fu % UNITS;
@@ -395,12 +418,12 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
       const WorkRec& W = recs[msg];
       const DevKey& K = keys[W.key_slot];
       const uint32_t idx = W.indices[t];
-      const int ls = (2 * q) << (z - 2), rs = (2 * q + 1) << (z - 2);
+      const int ls = (2 * q) << (z - 1 - L0), rs = (2 * q + 1) << (z - 1 - L0);
       uint32_t lr[2 * NW];
       load_words<NW>(&node[ls * NW], lr);
       load_words<NW>(&node[rs * NW], lr + NW);
       uint32_t out[NW];
-      thH<ID>(K, make_adrs(0, W.idx_tree, A_FORS_TREE, W.idx_leaf, z, (t << (A - z)) + i), lr, out);
+      thH<ID, V>(K, make_adrs(0, W.idx_tree, A_FORS_TREE, W.idx_leaf, z, (t << (A - z)) + i), lr, out);
       if (z < A && (((idx >> z) ^ 1u) == i))
         store_be<NW>(sigs + W.sig_off + Q::n + t * (A + 1) * Q::n + (1 + z) * Q::n, out);  // auth[z]
       if (z == AU) store_words<NW>(roots + size_t(fu) * NW, out);
@@ -410,12 +433,11 @@ __device__ __forceinline__ void fors_group(const DevKey* __restrict__ keys, cons
   }
 }
 
-template <int ID, int FG>
-__global__ __launch_bounds__(kForsThreads) void k_fors(const DevKey* __restrict__ keys,
-                                                       const WorkRec* __restrict__ recs, uint32_t nunits,
-                                                       uint8_t* sigs, uint32_t* __restrict__ roots) {
-  __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * P<ID>::NW];
-  fors_group<ID, FG>(keys, recs, nunits, sigs, roots, blockIdx.x, node);
+template <int ID, int FG, int LPL = 2, int FT = kForsThreads, int V = 0>
+__global__ __launch_bounds__(FT) void k_fors(const DevKey* __restrict__ keys, const WorkRec* __restrict__ recs,
+                                             uint32_t nunits, uint8_t* sigs, uint32_t* __restrict__ roots) {
+  __shared__ uint32_t node[FG * ForsLeaves<ID, LPL>::BASE * P<ID>::NW];
+  fors_group<ID, FG, LPL, FT, V>(keys, recs, nunits, sigs, roots, blockIdx.x, node);
 }
 
 // FORS trees built in units: one lane per tree combines its unit roots
@@ -504,24 +526,45 @@ __device__ __forceinline__ TreeJob sign_job(const DevKey* keys, WorkRec* recs, u
   return J;
 }
 
-// One WOTS+ chain: PRF then 15 F steps.  If `keep` is set, every value of
-// the chain (steps 0..15) is written to keep[step * NW ...].
+// Digit c of the WOTS+ message of layer `layer` of a signature: the base-16
+// digits of that layer's message (FORS pk for layer 0, root of layer j-1
+// otherwise) with the checksum digits appended (FIPS 205 Algorithm 7).
 template <int ID>
+__device__ __forceinline__ uint32_t wots_digit(const WorkRec& W, uint32_t layer, uint32_t c) {
+  using Q = P<ID>;
+  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
+  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
+  if (c < uint32_t(Q::len1)) return nib(c);
+  uint32_t csum = 0;
+  for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
+  csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
+  return (csum >> (12 - 4 * (c - Q::len1))) & 15u;
+}
+
+// One WOTS+ chain: PRF then 15 F steps.  If `keep` is set, every value of
+// the chain (steps 0..15) is written to keep[step * NW ...].  CAP (layers
+// signed in order): if `cap` is set, the value after `cap_step` steps is
+// written there as signature bytes (FIPS 205 Algorithm 7: the WOTS+
+// signature of chain c is the chain advanced by the message's digit c).
+template <int ID, int V = 0, bool CAP = false>
 __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t* sks, uint32_t layer,
                                            uint64_t tree, uint32_t kp, uint32_t c, uint32_t* keep,
-                                           uint32_t x[P<ID>::NW]) {
+                                           uint32_t x[P<ID>::NW], uint32_t cap_step = 0,
+                                           uint8_t* cap = nullptr) {
   constexpr int NW = P<ID>::NW;
-  thF<ID>(mid, make_adrs(layer, tree, A_WOTS_PRF, kp, c, 0), sks, x);
+  thF<ID, V>(mid, make_adrs(layer, tree, A_WOTS_PRF, kp, c, 0), sks, x);
   if (keep) store_words<NW>(keep, x);
+  if (CAP && cap && cap_step == 0) store_be<NW>(cap, x);
   const Adrs A0 = make_adrs(layer, tree, A_WOTS_HASH, kp, c, 0);
   for (uint32_t s = 0; s < 15; s++) {
     Adrs A = A0;
     A.tail = s << 16;
     uint32_t y[NW];
-    thF<ID>(mid, A, x, y);
+    thF<ID, V>(mid, A, x, y);
 #pragma unroll
     for (int u = 0; u < NW; u++) x[u] = y[u];
     if (keep) store_words<NW>(keep + (s + 1) * NW, x);
+    if (CAP && cap && cap_step == s + 1) store_be<NW>(cap, x);
   }
 }
 
@@ -530,9 +573,17 @@ __device__ __forceinline__ void wots_chain(const uint32_t mid[8], const uint32_t
 // about 13, 37 and 62 chain-step equivalents at 2.8 SHA-256 per SHA-512), so
 // it takes fewer of the len chunks of 16 compressions: w0 + extra / 16 =
 // (len - w0) / 3 gives 8, 11 and 14.
-template <int ID>
+// With NWAV waves per block the same balance w0 + extra / 16 =
+// (len - w0) / (NWAV - 1) gives w0 = (len - (NWAV - 1) extra / 16) / NWAV:
+// 17 / 24 / 31 chunks for two waves, 8 / 11 / 14 for four, 4 / 4 / 5 for
+// eight.
+template <int ID, int NWAV = 4>
 struct TreeSplit {
-  static constexpr int wave0 = P<ID>::len == 35 ? 8 : (P<ID>::len == 51 ? 11 : 14);
+  static_assert(NWAV == 2 || NWAV == 4 || NWAV == 8, "TREE blocks of 2, 4 or 8 waves");
+  static constexpr int L = P<ID>::len;
+  static constexpr int wave0 = NWAV == 4 ? (L == 35 ? 8 : (L == 51 ? 11 : 14))
+                             : NWAV == 2 ? (L == 35 ? 17 : (L == 51 ? 24 : 31))
+                                         : (L == 35 ? 4 : (L == 51 ? 4 : 5));
 };
 
 // What a TREE block works on: the trees of a batch's signatures, the top tree
@@ -604,17 +655,23 @@ __device__ __forceinline__ TreeJob tree_job(const DevKey* __restrict__ keys, Wor
 // Without a list, slot i is tree first + i.  For trees built in units
 // (XMSS trees above 64 leaves), slots are units (unit u of tree ft is
 // ft * tree_units + u) and each unit's root goes to uroots.
+// Layers signed in order take the trees of one layer: slot i is tree
+// first + i * stride (first = the layer, stride = d).
 struct TreeList {
   const uint32_t* ulist;
   const uint32_t* ucount;
   const uint32_t* lown;
   uint32_t first;
   uint32_t* uroots = nullptr;
+  uint32_t stride = 1;
   __device__ __forceinline__ uint32_t count(uint32_t ntrees) const { return ucount ? *ucount : ntrees; }
-  __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : first + i; }
+  __device__ __forceinline__ uint32_t at(uint32_t i) const { return ulist ? ulist[i] : first + i * stride; }
 };
 
-template <int ID, int KIND, bool SPLIT = false>
+// NWAV: waves of the block (chunk split of TreeSplit); V: instruction
+// variant; CAP: layers signed in order, the signing leaf's chains write the
+// WOTS+ signature of the layer as they pass its digits.
+template <int ID, int KIND, bool SPLIT = false, int NWAV = 4, int V = 0, bool CAP = false>
 __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
@@ -622,7 +679,7 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len, LV = 1 << Q::unit_hp, UT = Q::tree_units;
   constexpr int TPB = kLeavesPerBlock / LV;
-  constexpr int W0 = TreeSplit<ID>::wave0;
+  constexpr int W0 = TreeSplit<ID, NWAV>::wave0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tree0 = block * TPB;
   const uint32_t lt = lane / LV;
@@ -640,15 +697,22 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
   } else if (J.spill && int32_t(kp) == J.sign_leaf) {
     keep = J.spill;
   }
-  // a four-wave block: wave 0 chunks 0 .. W0-1, waves 1..3 chunks
-  // W0 + (wave - 1) + 3 i; a split block (one wave per workgroup, part
-  // blockIdx.y of gridDim.y): chunks part, part + parts, ...
+  // a block of NWAV waves: wave 0 chunks 0 .. W0-1, waves 1..NWAV-1 chunks
+  // W0 + (wave - 1) + (NWAV - 1) i; a split block (one wave per workgroup,
+  // part blockIdx.y of gridDim.y): chunks part, part + parts, ...
   const int c0 = SPLIT ? int(blockIdx.y) : (wave == 0 ? 0 : W0 + wave - 1);
   const int cend = SPLIT ? LEN : (wave == 0 ? W0 : LEN);
-  const int cstep = SPLIT ? int(gridDim.y) : (wave == 0 ? 1 : 3);
+  const int cstep = SPLIT ? int(gridDim.y) : (wave == 0 ? 1 : NWAV - 1);
+  const bool cap = CAP && int32_t(kp) == J.sign_leaf;
   for (int c = c0; c < cend; c += cstep) {
     uint32_t x[NW];
-    wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keep ? keep + c * 16 * NW : nullptr, x);
+    if constexpr (CAP) {
+      const uint32_t digit = cap ? wots_digit<ID>(recs[ft / Q::d], J.layer, uint32_t(c)) : 0u;
+      wots_chain<ID, V, true>(mid, sks, J.layer, J.tree, kp, c, nullptr, x, digit,
+                              cap ? J.sig_xmss + c * Q::n : nullptr);
+    } else {
+      wots_chain<ID, V>(mid, sks, J.layer, J.tree, kp, c, keep ? keep + c * 16 * NW : nullptr, x);
+    }
     store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
   }
 }
@@ -659,7 +723,7 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
 // nodes and the root are written where they are computed.
 // `nodes` (optional): every node of the tree is stored at
 // nodes[(ft * TreeNodes::count + off(z) + i) * NW] for the dedup scatter.
-template <int ID, int KIND>
+template <int ID, int KIND, int V = 0>
 __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, const uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
@@ -683,7 +747,7 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
       const int c = wi / NW, u = wi - c * NW;
       return st[(c * kLeavesPerBlock + lane) * NW + u];
     };
-    thT<ID, LEN>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_WOTS_PK, kp, 0, 0), get, v);
+    thT<ID, LEN, V>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_WOTS_PK, kp, 0, 0), get, v);
   } else {
 #pragma unroll
     for (int u = 0; u < NW; u++) v[u] = 0;
@@ -706,7 +770,7 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
       lr[NW + u] = __shfl_down(v[u], span, 64);
     }
     if (valid && (kl & ((span << 1) - 1)) == 0) {
-      thH<ID>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_TREE, 0, z, kp >> z), lr, v);
+      thH<ID, V>(J.key->mid256, J.key->mid512, make_adrs(J.layer, J.tree, A_TREE, 0, z, kp >> z), lr, v);
     }
   }
   if constexpr (UT == 1) {
@@ -717,22 +781,27 @@ __device__ __forceinline__ void tree_finish(const DevKey* __restrict__ keys, Wor
   }
 }
 
-template <int ID, int KIND>
-__global__ __launch_bounds__(kTreeThreads) void k_tree(const DevKey* __restrict__ keys,
-                                                       WorkRec* __restrict__ recs, uint32_t ntrees,
-                                                       uint8_t* sigs, uint32_t* __restrict__ stage,
-                                                       uint32_t* __restrict__ spill,
-                                                       uint32_t key_slot, uint32_t* root_out,
-                                                       const uint32_t* ulist, const uint32_t* ucount,
-                                                       const uint32_t* lown, uint32_t* nodes, uint32_t first,
-                                                       uint32_t* uroots) {
-  const TreeList tl{ulist, ucount, lown, first, uroots};
+// A TREE block of NWAV waves (64 NWAV lanes; the workgroup-size knob), SHA-2
+// variant V; CAP: one layer of the batch's trees (first = layer, stride = d)
+// with the WOTS+ signature captured on the way (layers signed in order).
+template <int ID, int KIND, int NWAV = 4, int V = 0, bool CAP = false>
+__global__ __launch_bounds__(64 * NWAV) void k_tree(const DevKey* __restrict__ keys,
+                                                    WorkRec* __restrict__ recs, uint32_t ntrees,
+                                                    uint8_t* sigs, uint32_t* __restrict__ stage,
+                                                    uint32_t* __restrict__ spill,
+                                                    uint32_t key_slot, uint32_t* root_out,
+                                                    const uint32_t* ulist, const uint32_t* ucount,
+                                                    const uint32_t* lown, uint32_t* nodes, uint32_t first,
+                                                    uint32_t* uroots, uint32_t stride) {
+  TreeList tl{ulist, ucount, lown, first, uroots};
+  tl.stride = stride;
   if (blockIdx.x * (kLeavesPerBlock >> P<ID>::unit_hp) >= tl.count(ntrees)) return;  // beyond the distinct trees
   uint32_t* st = stage + size_t(blockIdx.x) * P<ID>::len * kLeavesPerBlock * P<ID>::NW;
-  tree_chains<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl);
+  tree_chains<ID, KIND, false, NWAV, V, CAP>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x,
+                                             tl);
   __syncthreads();
   if ((threadIdx.x >> 6) == 0)
-    tree_finish<ID, KIND>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
+    tree_finish<ID, KIND, V>(keys, recs, ntrees, sigs, st, spill, key_slot, root_out, blockIdx.x, tl, nodes);
 }
 
 // The two phases of k_tree as separate launches, for batches too small to
@@ -821,7 +890,7 @@ struct FusedOcc {
   static constexpr int waves = 3;
 };
 
-template <int ID, int FG>
+template <int ID, int FG, int LPL = 2>
 __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg, uint8_t* sigs,
     uint32_t* __restrict__ stage, uint32_t* __restrict__ spill, uint32_t* __restrict__ roots, uint32_t* queue,
@@ -830,7 +899,7 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
   static_assert(kTreeThreads == kForsThreads, "one workgroup shape for both item kinds");
   using Q = P<ID>;
   constexpr size_t SW = size_t(Q::len) * kLeavesPerBlock * Q::NW;  // words of one staging buffer
-  __shared__ uint32_t node[FG * ForsShape<ID>::PAIRS * Q::NW];
+  __shared__ uint32_t node[FG * ForsLeaves<ID, LPL>::BASE * Q::NW];
   __shared__ uint32_t item;
   uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * SW;
   const TreeList tl{ulist, ucount, lown, 0u};
@@ -858,7 +927,7 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
       pend = it;
       cur ^= 1;
     } else {
-      fors_group<ID, FG>(keys, recs, nmsg * Q::k, sigs, roots, it - ntb, node);
+      fors_group<ID, FG, LPL>(keys, recs, nmsg * Q::k, sigs, roots, it - ntb, node);
     }
   }
   if (pend != 0xffffffffu && w0) tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u,
@@ -866,20 +935,8 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
 }
 
 // ------------------------------------------------------------------ WOTS
-// One lane per (message, layer, chain): digit of the layer's message
-// (FORS pk for layer 0, root of layer j-1 otherwise) with the checksum
-// digits appended (FIPS 205 Algorithm 7), then the chain value at that digit.
-template <int ID>
-__device__ __forceinline__ uint32_t wots_digit(const WorkRec& W, uint32_t layer, uint32_t c) {
-  using Q = P<ID>;
-  const uint32_t* M = layer == 0 ? W.fors_pk : W.roots[layer - 1];
-  auto nib = [&](int i) -> uint32_t { return (M[i >> 3] >> (28 - 4 * (i & 7))) & 15u; };
-  if (c < uint32_t(Q::len1)) return nib(c);
-  uint32_t csum = 0;
-  for (int i = 0; i < Q::len1; i++) csum += 15u - nib(i);
-  csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
-  return (csum >> (12 - 4 * (c - Q::len1))) & 15u;
-}
+// One lane per (message, layer, chain): digit of the layer's message (see
+// wots_digit), then the chain value at that digit.
 
 // Chain c of the signing leaf of job J advanced `digit` steps from its PRF
 // secret (FIPS 205 Algorithms 5 and 7).
@@ -1116,7 +1173,8 @@ __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restric
 //             the same number of F steps; each lane works through its chains
 //             step by step; the first lane then runs T_len and climbs the
 //             h' authentication levels to the layer's root.
-// The result (1 valid, 0 invalid) is written to results[res_idx].
+// The result (1 valid, 0 invalid) is written to results[res_idx].  V: the
+// instruction variant of the chain, tree and T_l hashes (sha2_dev.hpp).
 struct VerifyItem {
   uint64_t msg_off, msg_len, sig_off, pk_off, res_idx;
 };
@@ -1142,7 +1200,7 @@ __device__ __forceinline__ uint32_t verify_digit(const uint32_t* M, uint32_t csu
   return (csum >> (12 - 4 * (c - P<ID>::len1))) & 15u;
 }
 
-template <int ID, int G>
+template <int ID, int G, int V = 0>
 __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __restrict__ items,
                                                           uint32_t count, const uint8_t* msgs,
                                                           const uint8_t* sigs, const uint8_t* pks,
@@ -1219,7 +1277,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
       uint32_t x[NW], y[NW], lr[2 * NW];
       load_be<NW>(ts, x);
       uint32_t gi = (uint32_t(t) << A) + idx;
-      thF<ID>(mid256, make_adrs(0, tree, A_FORS_TREE, leaf, 0, gi), x, y);
+      thF<ID, V>(mid256, make_adrs(0, tree, A_FORS_TREE, leaf, 0, gi), x, y);
       for (int j = 0; j < A; j++) {
         uint32_t au[NW];
         load_be<NW>(ts + (1 + j) * Q::n, au);
@@ -1230,7 +1288,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
           lr[NW + u] = even ? au[u] : y[u];
         }
         gi >>= 1;
-        thH<ID>(mid256, mid512, make_adrs(0, tree, A_FORS_TREE, leaf, j + 1, gi), lr, y);
+        thH<ID, V>(mid256, mid512, make_adrs(0, tree, A_FORS_TREE, leaf, j + 1, gi), lr, y);
       }
       store_words<NW>(&vals[t * NW], y);
     }
@@ -1239,7 +1297,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
   if (valid && g == 0) {
     auto get = [&](int wi) -> uint32_t { return vals[wi]; };
     uint32_t pk[NW];
-    thT<ID, KT>(mid256, mid512, make_adrs(0, tree, A_FORS_ROOTS, leaf, 0, 0), get, pk);
+    thT<ID, KT, V>(mid256, mid512, make_adrs(0, tree, A_FORS_ROOTS, leaf, 0, 0), get, pk);
     store_words<NW>(s_cur[grp], pk);
   }
   __syncthreads();
@@ -1293,7 +1351,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
         Adrs Ad = make_adrs(layer, tree, A_WOTS_HASH, leaf, uint32_t(c), 0);
         Ad.tail = st << 16;
         uint32_t y[NW];
-        thF<ID>(mid256, Ad, x, y);
+        thF<ID, V>(mid256, Ad, x, y);
 #pragma unroll
         for (int u = 0; u < NW; u++) x[u] = y[u];
         st++;
@@ -1303,7 +1361,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     if (valid && g == 0) {
       auto get = [&](int wi) -> uint32_t { return vals[wi]; };
       uint32_t node[NW], lr[2 * NW];
-      thT<ID, LEN>(mid256, mid512, make_adrs(layer, tree, A_WOTS_PK, leaf, 0, 0), get, node);
+      thT<ID, LEN, V>(mid256, mid512, make_adrs(layer, tree, A_WOTS_PK, leaf, 0, 0), get, node);
       uint32_t ti = leaf;
       for (int j = 0; j < Q::hp; j++) {
         uint32_t au[NW];
@@ -1315,7 +1373,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
           lr[NW + u] = even ? au[u] : node[u];
         }
         ti >>= 1;
-        thH<ID>(mid256, mid512, make_adrs(layer, tree, A_TREE, 0, j + 1, ti), lr, node);
+        thH<ID, V>(mid256, mid512, make_adrs(layer, tree, A_TREE, 0, j + 1, ti), lr, node);
       }
       store_words<NW>(s_cur[grp], node);
     }

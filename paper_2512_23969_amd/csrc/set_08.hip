@@ -1,4 +1,6 @@
-// set_08.hip -- kernels and host launch code of parameter set 8 (SHAKE-192f).
+// set_08.hip -- kernels and host launch code of parameter set 8 (SHAKE-192f);
+// its FORS and TREE selectors compile in set_08_fors.hip and set_08_tree.hip.
 #include "set_impl.hpp"
 
+SLH_EXTERN_SELECTORS(8)
 SLH_DEFINE_SET_OPS(8)

@@ -32,12 +32,29 @@ void with_fg(uint32_t fg, F&& f) {
 }
 
 
-template <int ID, int FG>
+// Call f(std::integral_constant<int, LPL>) for FORS leaves per lane 2 or 4,
+// f(std::integral_constant<int, FT>) for FORS workgroups of 128, 256 or 512
+// lanes, f(std::integral_constant<int, NWAV>) for TREE blocks of 2, 4 or 8
+// waves.
+template <typename F>
+void with_lpl(uint32_t lpl, F&& f) {
+  if (lpl == 4) f(FgC<4>{}); else f(FgC<2>{});
+}
+template <typename F>
+void with_ft(uint32_t ft, F&& f) {
+  if (ft == 128) f(FgC<128>{}); else if (ft == 512) f(FgC<512>{}); else f(FgC<256>{});
+}
+template <typename F>
+void with_nwav(uint32_t nwav, F&& f) {
+  if (nwav == 2) f(FgC<2>{}); else if (nwav == 8) f(FgC<8>{}); else f(FgC<4>{});
+}
+
+template <int ID, int FG, int LPL>
 int occupancy_of() {
   static int occ = -1;
   if (occ < 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused<ID, FG>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused<ID, FG, LPL>),
                                                      kTreeThreads, 0) != hipSuccess || nb < 1)
       nb = 1;
     occ = nb;
@@ -45,13 +62,15 @@ int occupancy_of() {
   return occ;
 }
 template <int ID>
-int occupancy(uint32_t fg) {
+int occupancy(uint32_t fg, uint32_t lpl) {
   if constexpr (!whole_trees<ID>()) {
     return 1;
-  } else if constexpr (shape_of(ID) == 3) {
-    return fg == 2 ? occupancy_of<ID, 2>() : fg == 8 ? occupancy_of<ID, 8>() : occupancy_of<ID, 4>();
   } else {
-    return fg == 4 ? occupancy_of<ID, 4>() : fg == 16 ? occupancy_of<ID, 16>() : occupancy_of<ID, 8>();
+    int occ = 1;
+    with_fg<ID>(fg, [&](auto fgc) {
+      with_lpl(lpl, [&](auto l) { occ = occupancy_of<ID, decltype(fgc)::value, decltype(l)::value>(); });
+    });
+    return occ;
   }
 }
 
@@ -66,8 +85,10 @@ struct Plan {
   static constexpr uint32_t TPB = kLeavesPerBlock >> Q::unit_hp;  // trees (or units) per TREE block
   size_t n = 0;
   bool fused = false, dedup = false, keep = true;
+  bool inorder = false;  // layers signed in order: one TREE launch per layer, WOTS+ captured
   uint32_t parts = 0;  // > 0: TREE blocks' chains split over this many workgroups (small batches)
   uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0, table = 0;
+  uint32_t lpl = 2, ft = kForsThreads, nwav = 4, vtree = 0, vfors = 0;  // kernel shapes and variants
   size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
   size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, o_troots = 0, o_uroots = 0, total = 0;
   static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
@@ -77,9 +98,23 @@ struct Plan {
         dedup(whole_trees<ID>() && (mode & SLH_MODE_DEDUP) != 0),
         keep(t.keep != 0) {
     fg = t.fg ? t.fg : fg_default(ID);
+    if constexpr (whole_trees<ID>()) {
+      lpl = t.lpl;
+      ft = t.fors_threads;
+      nwav = t.tree_waves;
+      vtree = t.vtree;
+      vfors = t.vfors;
+      inorder = t.inorder != 0 && !dedup;
+    }
     const size_t trees = n * Q::d;
     ntb = uint32_t((trees * Q::tree_units + TPB - 1) / TPB);
     nfg = uint32_t((n * Q::k * Q::fors_units + fg - 1) / fg);
+    if (inorder) {
+      // per-phase path, one TREE launch per layer of n trees; nothing kept
+      fused = false;
+      keep = false;
+      ntb = uint32_t((n + TPB - 1) / TPB);
+    }
     // With few TREE blocks the batch cannot fill the chip and its time is
     // one block's chain latency: split each block's chains over up to len
     // one-wave workgroups, about 8 waves per CU in all (the per-phase path;
@@ -87,12 +122,12 @@ struct Plan {
     // to about 1.4 blocks per CU, ties to 2 and loses above.
     const uint32_t split_max =
         t.split == SLH_SPLIT_NEVER ? 0u : (t.split ? t.split : 3u * uint32_t(cus) / 2u);
-    if (ntb <= split_max) {
+    if (ntb <= split_max && !inorder) {
       parts = std::max<uint32_t>(1u, std::min<uint32_t>(Q::len, 8u * uint32_t(cus) / std::max(1u, ntb)));
       fused = false;
     }
     if (fused) {
-      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg));
+      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg, lpl));
       grid = std::min<uint32_t>(per_cu * uint32_t(cus), ntb + nfg);
     } else {
       grid = std::min(ntb, kMaxTreeBlocks);
@@ -124,13 +159,6 @@ struct Plan {
   }
 };
 
-// Make sure parameter set p has `bytes` of working memory (waits for pending
-
-template <int ID, int FG>
-void launch_fors(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* roots, hipStream_t s) {
-  hipLaunchKernelGGL((k_fors<ID, FG>), dim3(pl.nfg), dim3(kForsThreads), 0, s, c->keys, recs,
-                     uint32_t(pl.n * P<ID>::k * P<ID>::fors_units), sigs, roots);
-}
 // Dedup buffers of a chunk (all null without dedup).
 struct DedupBufs {
   DedupSlot* table = nullptr;
@@ -141,10 +169,72 @@ struct DedupBufs {
   uint32_t* nodes = nullptr;
 };
 
-template <int ID, int FG>
+// Arguments of one launch of the TREE kernel over signing trees.
+struct TreeLaunch {
+  uint32_t nblocks, ntrees, first, stride;
+  uint8_t* sigs;
+  WorkRec* recs;
+  uint32_t* stage;
+  uint32_t* spill;
+  const DedupBufs* db;
+  uint32_t* uroots;
+};
+
+// The FORS kernel of the plan's shape (trees per group, leaves per lane,
+// workgroup lanes) and instruction variant.  The fast sets' instantiations
+// of these two selectors compile in translation units of their own
+// (set_<id>_fors.hip, set_<id>_tree.hip; SLH_EXTERN_SELECTORS).
+template <int ID>
+void launch_fors_sel(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* roots, hipStream_t s) {
+  const uint32_t nunits = uint32_t(pl.n * P<ID>::k * P<ID>::fors_units);
+  with_fg<ID>(pl.fg, [&](auto fgc) {
+    constexpr int FG = decltype(fgc)::value;
+    auto go = [&](auto lpl, auto ft, auto var) {
+      constexpr int LPL = decltype(lpl)::value, FT = decltype(ft)::value, V = decltype(var)::value;
+      hipLaunchKernelGGL((k_fors<ID, FG, LPL, FT, V>), dim3(pl.nfg), dim3(FT), 0, s, c->keys, recs, nunits, sigs,
+                         roots);
+    };
+    if constexpr (!whole_trees<ID>()) {
+      go(FgC<2>{}, FgC<kForsThreads>{}, FgC<0>{});
+    } else {
+      if constexpr (ID <= 3) {  // SHA2 fast sets: the instruction variants, at the default shape
+        if (pl.vfors == 1) return go(FgC<2>{}, FgC<kForsThreads>{}, FgC<1>{});
+        if (pl.vfors == 2) return go(FgC<2>{}, FgC<kForsThreads>{}, FgC<2>{});
+      }
+      with_lpl(pl.lpl, [&](auto l) { with_ft(pl.ft, [&](auto f) { go(l, f, FgC<0>{}); }); });
+    }
+  });
+}
+
+// The TREE kernel (signing trees) of the plan's block size and instruction
+// variant; `cap`: one layer of the batch, WOTS+ captured (layers in order).
+template <int ID>
+void launch_tree_sel(slh_ctx* c, const Plan<ID>& pl, bool cap, const TreeLaunch& a, hipStream_t s) {
+  auto go = [&](auto nw, auto var, auto cp) {
+    constexpr int NWAV = decltype(nw)::value, V = decltype(var)::value;
+    constexpr bool CAP = decltype(cp)::value;
+    hipLaunchKernelGGL((k_tree<ID, kSignTrees, NWAV, V, CAP>), dim3(a.nblocks), dim3(64 * NWAV), 0, s, c->keys,
+                       a.recs, a.ntrees, a.sigs, a.stage, a.spill, 0u, nullptr, a.db->ulist, a.db->ucount,
+                       a.db->lown, a.db->nodes, a.first, a.uroots, a.stride);
+  };
+  if constexpr (!whole_trees<ID>()) {
+    go(FgC<4>{}, FgC<0>{}, std::false_type{});
+  } else {
+    auto with_cap = [&](auto nw, auto var) {
+      if (cap) go(nw, var, std::true_type{}); else go(nw, var, std::false_type{});
+    };
+    if constexpr (ID <= 3) {  // SHA2 fast sets: the instruction variants, at four waves
+      if (pl.vtree == 1) return with_cap(FgC<4>{}, FgC<1>{});
+      if (pl.vtree == 2) return with_cap(FgC<4>{}, FgC<2>{});
+    }
+    with_nwav(pl.nwav, [&](auto nw) { with_cap(nw, FgC<0>{}); });
+  }
+}
+
+template <int ID, int FG, int LPL>
 void launch_fused(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
                   uint32_t* roots, uint32_t* queue, const DedupBufs& db, hipStream_t s) {
-  hipLaunchKernelGGL((k_fused<ID, FG>), dim3(pl.grid), dim3(kTreeThreads), 0, s, c->keys, recs, uint32_t(pl.n),
+  hipLaunchKernelGGL((k_fused<ID, FG, LPL>), dim3(pl.grid), dim3(kTreeThreads), 0, s, c->keys, recs, uint32_t(pl.n),
                      sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist, db.ucount, db.lown, db.nodes);
 }
 
@@ -152,6 +242,9 @@ void launch_fused(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, 
 // the pinned host copy of the chunk's requests (uploaded into the working
 // memory), or with `src_on_device` their device copy, read in place.
 // `timing` is false while a graph is captured.
+//   parallel layers: prelude -> FORS -> TREE (all layers) -> FORS pk, WOTS+
+//   layers in order: prelude -> FORS, FORS pk -> TREE layer 0 -> ... ->
+//                    TREE layer d-1 (each writes its layer's WOTS+ part)
 template <int ID>
 int launch_chunk(slh_ctx* c, const Plan<ID>& pl, uint8_t* base, const DevItem* src, bool src_on_device,
                  const uint8_t* msgs, uint8_t* sigs, hipStream_t s, bool timing) {
@@ -192,55 +285,76 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, uint8_t* base, const DevItem* s
       }
     }
   }
+  const uint32_t* troots =
+      Q::fors_units > 1 ? reinterpret_cast<const uint32_t*>(base + pl.o_troots) : roots;  // FORS tree roots
   if constexpr (whole_trees<ID>()) {
     if (pl.fused) {
       PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
       with_fg<ID>(pl.fg, [&](auto fgc) {
-        launch_fused<ID, decltype(fgc)::value>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
+        with_lpl(pl.lpl, [&](auto l) {
+          launch_fused<ID, decltype(fgc)::value, decltype(l)::value>(c, pl, sigs, recs, stage, spill, roots, queue,
+                                                                     db, s);
+        });
       });
     }
   }
   if (!pl.fused) {
     {
       PhaseTimer t(c, s, SLH_PHASE_FORS, n, timing);
-      with_fg<ID>(pl.fg, [&](auto fgc) { launch_fors<ID, decltype(fgc)::value>(c, pl, sigs, recs, roots, s); });
+      launch_fors_sel<ID>(c, pl, sigs, recs, roots, s);
       if constexpr (Q::fors_units > 1) {
         const uint32_t nft = n * Q::k;
         hipLaunchKernelGGL((k_fors_top<ID>), dim3((nft + 63) / 64), dim3(64), 0, s, c->keys, recs, nft, sigs, roots,
                            reinterpret_cast<uint32_t*>(base + pl.o_troots));
       }
+      // layers in order: layer 0 signs the FORS public key, so T_k comes first
+      if (pl.inorder)
+        hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, troots);
     }
     {
       PhaseTimer t(c, s, SLH_PHASE_TREE, n, timing);
       uint32_t* uroots = Q::tree_units > 1 ? reinterpret_cast<uint32_t*>(base + pl.o_uroots) : nullptr;
-      const uint32_t units = trees * Q::tree_units;
-      // at most kMaxTreeBlocks blocks per launch, reusing the staging
-      for (uint32_t b0 = 0; b0 < pl.ntb; b0 += kMaxTreeBlocks) {
-        const uint32_t nb = std::min(kMaxTreeBlocks, pl.ntb - b0), first = b0 * Plan<ID>::TPB;
-        const uint32_t nu = std::min(units - first, nb * Plan<ID>::TPB);
-        if (pl.parts) {
-          hipLaunchKernelGGL((k_tree_chains<ID, kSignTrees>), dim3(nb, pl.parts), dim3(64), 0, s, c->keys, recs, nu,
-                             sigs, stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, first, uroots);
-          hipLaunchKernelGGL((k_tree_finish<ID, kSignTrees>), dim3(nb), dim3(64), 0, s, c->keys, recs, nu, sigs,
-                             stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, first, uroots);
-        } else
-          hipLaunchKernelGGL((k_tree<ID, kSignTrees>), dim3(nb), dim3(kTreeThreads), 0, s, c->keys, recs, nu, sigs,
-                             stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, first, uroots);
+      if (pl.inorder) {
+        // one launch per layer over the n trees of that layer (tree of
+        // message m: flat id m * d + layer), at most kMaxTreeBlocks blocks
+        for (uint32_t layer = 0; layer < uint32_t(Q::d); layer++)
+          for (uint32_t b0 = 0; b0 < pl.ntb; b0 += kMaxTreeBlocks) {
+            const uint32_t nb = std::min(kMaxTreeBlocks, pl.ntb - b0), m0 = b0 * Plan<ID>::TPB;
+            const uint32_t nt = std::min(n - m0, nb * Plan<ID>::TPB);
+            launch_tree_sel<ID>(c, pl, true,
+                                TreeLaunch{nb, nt, layer + m0 * uint32_t(Q::d), uint32_t(Q::d), sigs, recs, stage,
+                                           nullptr, &db, nullptr},
+                                s);
+          }
+      } else {
+        const uint32_t units = trees * Q::tree_units;
+        // at most kMaxTreeBlocks blocks per launch, reusing the staging
+        for (uint32_t b0 = 0; b0 < pl.ntb; b0 += kMaxTreeBlocks) {
+          const uint32_t nb = std::min(kMaxTreeBlocks, pl.ntb - b0), first = b0 * Plan<ID>::TPB;
+          const uint32_t nu = std::min(units - first, nb * Plan<ID>::TPB);
+          if (pl.parts) {
+            hipLaunchKernelGGL((k_tree_chains<ID, kSignTrees>), dim3(nb, pl.parts), dim3(64), 0, s, c->keys, recs,
+                               nu, sigs, stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, first, uroots);
+            hipLaunchKernelGGL((k_tree_finish<ID, kSignTrees>), dim3(nb), dim3(64), 0, s, c->keys, recs, nu, sigs,
+                               stage, spill, 0u, nullptr, db.ulist, db.ucount, db.lown, db.nodes, first, uroots);
+          } else {
+            launch_tree_sel<ID>(c, pl, false, TreeLaunch{nb, nu, first, 1u, sigs, recs, stage, spill, &db, uroots},
+                                s);
+          }
+        }
+        if constexpr (Q::tree_units > 1)
+          hipLaunchKernelGGL((k_tree_top<ID, kSignTrees>), dim3((trees + 63) / 64), dim3(64), 0, s, c->keys, recs,
+                             trees, sigs, 0u, nullptr, 0u, uroots);
       }
-      if constexpr (Q::tree_units > 1)
-        hipLaunchKernelGGL((k_tree_top<ID, kSignTrees>), dim3((trees + 63) / 64), dim3(64), 0, s, c->keys, recs,
-                           trees, sigs, 0u, nullptr, 0u, uroots);
     }
   }
-  {
+  if (!pl.inorder) {
     PhaseTimer t(c, s, SLH_PHASE_WOTS, n, timing);
     if constexpr (whole_trees<ID>()) {
       if (pl.dedup)
         hipLaunchKernelGGL((k_dedup_scatter<ID>), dim3((trees + 255) / 256), dim3(256), 0, s, c->keys, recs, n,
                            sigs, db.rep, db.nodes, c->cache);
     }
-    const uint32_t* troots =
-        Q::fors_units > 1 ? reinterpret_cast<const uint32_t*>(base + pl.o_troots) : roots;  // tree roots
     hipLaunchKernelGGL((k_fors_pk<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, recs, n, troots);
     const uint32_t nw = n * Q::d * Q::len;
     if (pl.keep && pl.dedup) {
@@ -371,7 +485,7 @@ int cache_impl(slh_ctx* c, uint32_t first, uint32_t count, uint32_t layers, hipS
       const uint32_t n = std::min<uint32_t>(kMaxBlocks * TPB, total - t0);
       hipLaunchKernelGGL((k_tree<ID, kCacheTrees>), dim3((n + TPB - 1) / TPB), dim3(kTreeThreads), 0, s, c->keys,
                          nullptr, n, nullptr, stage, nullptr, first, nullptr, nullptr, nullptr, nullptr, nodes, t0,
-                         nullptr);
+                         nullptr, 1u);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -384,19 +498,25 @@ int cache_impl(slh_ctx* c, uint32_t first, uint32_t count, uint32_t layers, hipS
 }
 
 // Batched verification of `count` items of set ID: 16 lanes per signature,
-// or 32 (`wide`) for batches too small to give every SIMD a wave at 16.
+// or 32 (`wide`) for batches too small to give every SIMD a wave at 16;
+// `variant`: instruction variant of the hashes (SHA2 fast sets).
 template <int ID>
-void verify_launch(const VerifyItem* items, uint32_t count, bool wide, const uint8_t* msgs, const uint8_t* sigs,
-                   const uint8_t* pks, int* results, hipStream_t s) {
-  if (wide) {
-    constexpr uint32_t per_wg = kVerifyThreads / kVerifyGroupWide;
-    hipLaunchKernelGGL((k_verify<ID, kVerifyGroupWide>), dim3((count + per_wg - 1) / per_wg), dim3(kVerifyThreads),
-                       0, s, items, count, msgs, sigs, pks, results);
-  } else {
-    constexpr uint32_t per_wg = kVerifyThreads / kVerifyGroup;
-    hipLaunchKernelGGL((k_verify<ID, kVerifyGroup>), dim3((count + per_wg - 1) / per_wg), dim3(kVerifyThreads), 0,
-                       s, items, count, msgs, sigs, pks, results);
-  }
+void verify_launch(const VerifyItem* items, uint32_t count, bool wide, uint32_t variant, const uint8_t* msgs,
+                   const uint8_t* sigs, const uint8_t* pks, int* results, hipStream_t s) {
+  auto go = [&](auto g, auto var) {
+    constexpr int G = decltype(g)::value, V = decltype(var)::value;
+    constexpr uint32_t per_wg = kVerifyThreads / G;
+    hipLaunchKernelGGL((k_verify<ID, G, V>), dim3((count + per_wg - 1) / per_wg), dim3(kVerifyThreads), 0, s, items,
+                       count, msgs, sigs, pks, results);
+  };
+  auto with_var = [&](auto g) {
+    if constexpr (ID <= 3) {
+      if (variant == 1) return go(g, FgC<1>{});
+      if (variant == 2) return go(g, FgC<2>{});
+    }
+    go(g, FgC<0>{});
+  };
+  if (wide) with_var(FgC<kVerifyGroupWide>{}); else with_var(FgC<kVerifyGroup>{});
 }
 
 }  // namespace slh
@@ -410,4 +530,23 @@ void verify_launch(const VerifyItem* items, uint32_t count, bool wide, const uin
   SetOps kSetOps##ID = {&chunk_size<ID>,         &plan_bytes<ID>, &enqueue_group<ID>,                       \
                         KeygenLayout<ID>::bytes, &keygen_impl<ID>, &cache_impl<ID>,                         \
                         &verify_launch<ID>};                                                                \
+  }
+
+// The fast sets compile the FORS and TREE selectors (every kernel shape and
+// variant they launch) in translation units of their own: the set's main
+// unit declares them (SLH_EXTERN_SELECTORS, before SLH_DEFINE_SET_OPS) and
+// set_<id>_fors.hip / set_<id>_tree.hip instantiate them.
+#define SLH_EXTERN_SELECTORS(ID)                                                                              \
+  namespace slh {                                                                                           \
+  extern template void launch_fors_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*,         \
+                                           hipStream_t);                                                     \
+  extern template void launch_tree_sel<ID>(slh_ctx*, const Plan<ID>&, bool, const TreeLaunch&, hipStream_t); \
+  }
+#define SLH_DEFINE_FORS_SELECTOR(ID)                                                                         \
+  namespace slh {                                                                                           \
+  template void launch_fors_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*, hipStream_t);  \
+  }
+#define SLH_DEFINE_TREE_SELECTOR(ID)                                                                         \
+  namespace slh {                                                                                           \
+  template void launch_tree_sel<ID>(slh_ctx*, const Plan<ID>&, bool, const TreeLaunch&, hipStream_t);        \
   }

@@ -37,17 +37,75 @@ __device__ __forceinline__ uint32_t ch32(uint32_t e, uint32_t f, uint32_t g) {
 __device__ __forceinline__ uint32_t maj32(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);  // majority
 }
-__device__ __forceinline__ uint32_t bsig0_256(uint32_t a) {
-  return xor3(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
+
+// ---------------------------------------------------------------- variants
+// Instruction variants of the SHA-2 arithmetic.  The paper compiles each
+// hashing kernel twice, once from native code and once with hand-written
+// PTX, profiles both and keeps the faster per kernel (Section III-C,
+// "PTX Branch Selection at Kernel-Level", Table 5).  On gfx950 the same
+// choice is between instruction forms of the round arithmetic; a kernel
+// template takes the variant V and the autotuner picks V per kernel and
+// parameter set:
+//   V = 0            the library's forms: v_bitop3_b32 for the three-input
+//                    XORs, Ch and Maj; v_add3_u32 for three-term sums;
+//                    v_lshl_add_u64 for every SHA-512 64-bit add;
+//   V & kIsaLogic    no three-input logic op: an XOR of three as two
+//                    v_xor_b32, Ch as v_bfi_b32, Maj as v_xor_b32 + v_bfi_b32;
+//   V & kIsaAdds     no fused adds: every sum of two run-time values as one
+//                    v_add_u32 (no v_add3_u32), every 64-bit add as a
+//                    v_add_co_u32 / v_addc_co_u32 carry pair.
+// Operations whose operands are compile-time constants after inlining (the
+// padding and length words, hoisted address words) fold in every variant,
+// so the variants differ only where a kernel computes at run time.
+enum : int { kIsaLogic = 1, kIsaAdds = 2 };
+
+template <int V>
+__device__ __forceinline__ uint32_t vxor3(uint32_t a, uint32_t b, uint32_t c) {
+  if constexpr ((V & kIsaLogic) != 0) {
+    if (__builtin_constant_p(a ^ b ^ c)) return a ^ b ^ c;
+    uint32_t t, r;
+    asm("v_xor_b32 %0, %1, %2" : "=v"(t) : "v"(a), "v"(b));
+    asm("v_xor_b32 %0, %1, %2" : "=v"(r) : "v"(t), "v"(c));
+    return r;
+  } else {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+  }
 }
-__device__ __forceinline__ uint32_t bsig1_256(uint32_t e) {
-  return xor3(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25));
+template <int V>
+__device__ __forceinline__ uint32_t vch(uint32_t e, uint32_t f, uint32_t g) {
+  if constexpr ((V & kIsaLogic) != 0) {
+    if (__builtin_constant_p((e & f) | (~e & g))) return (e & f) | (~e & g);
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(e), "v"(f), "v"(g));
+    return r;
+  } else {
+    return __builtin_amdgcn_bitop3_b32(e, f, g, 0xCA);  // e ? f : g
+  }
 }
-__device__ __forceinline__ uint32_t ssig0_256(uint32_t x) {
-  return xor3(rotr32(x, 7), rotr32(x, 18), x >> 3);
+template <int V>
+__device__ __forceinline__ uint32_t vmaj(uint32_t a, uint32_t b, uint32_t c) {
+  if constexpr ((V & kIsaLogic) != 0) {
+    if (__builtin_constant_p((a & b) | (a & c) | (b & c))) return (a & b) | (a & c) | (b & c);
+    uint32_t t, r;  // majority = (a ^ b) ? c : b
+    asm("v_xor_b32 %0, %1, %2" : "=v"(t) : "v"(a), "v"(b));
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(t), "v"(c), "v"(b));
+    return r;
+  } else {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);  // majority
+  }
 }
-__device__ __forceinline__ uint32_t ssig1_256(uint32_t x) {
-  return xor3(rotr32(x, 17), rotr32(x, 19), x >> 10);
+// a + b; in the kIsaAdds variant a sum of two run-time values is one
+// v_add_u32 that the compiler cannot merge into a v_add3_u32.
+template <int V>
+__device__ __forceinline__ uint32_t vadd(uint32_t a, uint32_t b) {
+  if constexpr ((V & kIsaAdds) != 0) {
+    if (__builtin_constant_p(a) || __builtin_constant_p(b)) return a + b;
+    uint32_t r;
+    asm("v_add_u32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+  } else {
+    return a + b;
+  }
 }
 
 struct K256Table {
@@ -68,6 +126,23 @@ __device__ __forceinline__ constexpr K256Table k256() {
       0x90befffau, 0xa4506cebu, 0xbef9a3f7u, 0xc67178f2u}};
 }
 
+template <int V = 0>
+__device__ __forceinline__ uint32_t bsig0_256(uint32_t a) {
+  return vxor3<V>(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
+}
+template <int V = 0>
+__device__ __forceinline__ uint32_t bsig1_256(uint32_t e) {
+  return vxor3<V>(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25));
+}
+template <int V = 0>
+__device__ __forceinline__ uint32_t ssig0_256(uint32_t x) {
+  return vxor3<V>(rotr32(x, 7), rotr32(x, 18), x >> 3);
+}
+template <int V = 0>
+__device__ __forceinline__ uint32_t ssig1_256(uint32_t x) {
+  return vxor3<V>(rotr32(x, 17), rotr32(x, 19), x >> 10);
+}
+
 __device__ __forceinline__ void sha256_iv(uint32_t s[8]) {
   s[0] = 0x6a09e667u; s[1] = 0xbb67ae85u; s[2] = 0x3c6ef372u; s[3] = 0xa54ff53au;
   s[4] = 0x510e527fu; s[5] = 0x9b05688cu; s[6] = 0x1f83d9abu; s[7] = 0x5be0cd19u;
@@ -78,7 +153,7 @@ __device__ __forceinline__ void sha256_iv(uint32_t s[8]) {
 // message words of the block.  On return `st` holds the working variables
 // after round 63 (the caller adds the chaining value).  w[] is overwritten
 // by the message schedule.
-template <int R0 = 0>
+template <int R0 = 0, int V = 0>
 __device__ __forceinline__ void sha256_rounds(uint32_t st[8], uint32_t w[16]) {
   constexpr K256Table K = k256();
   uint32_t a = st[0], b = st[1], c = st[2], d = st[3];
@@ -87,22 +162,23 @@ __device__ __forceinline__ void sha256_rounds(uint32_t st[8], uint32_t w[16]) {
   for (int i = R0; i < 64; i++) {
     if (i >= 16) {
       // grouped so that the terms that are fixed for a chain come first
-      w[i & 15] = (w[i & 15] + ssig0_256(w[(i + 1) & 15])) + w[(i + 9) & 15] +
-                  ssig1_256(w[(i + 14) & 15]);
+      w[i & 15] = vadd<V>(vadd<V>(vadd<V>(w[i & 15], ssig0_256<V>(w[(i + 1) & 15])), w[(i + 9) & 15]),
+                          ssig1_256<V>(w[(i + 14) & 15]));
     }
-    uint32_t t1 = h + (K.v[i] + w[i & 15]) + bsig1_256(e) + ch32(e, f, g);
-    uint32_t t2 = bsig0_256(a) + maj32(a, b, c);
-    h = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = t1 + t2;
+    uint32_t t1 = vadd<V>(vadd<V>(vadd<V>(h, K.v[i] + w[i & 15]), bsig1_256<V>(e)), vch<V>(e, f, g));
+    uint32_t t2 = vadd<V>(bsig0_256<V>(a), vmaj<V>(a, b, c));
+    h = g; g = f; f = e; e = vadd<V>(d, t1); d = c; c = b; b = a; a = vadd<V>(t1, t2);
   }
   st[0] = a; st[1] = b; st[2] = c; st[3] = d; st[4] = e; st[5] = f; st[6] = g; st[7] = h;
 }
 
 // Full compression: st <- st + rounds(st, w).
+template <int V = 0>
 __device__ __forceinline__ void sha256_compress(uint32_t st[8], uint32_t w[16]) {
   uint32_t x[8];
 #pragma unroll
   for (int i = 0; i < 8; i++) x[i] = st[i];
-  sha256_rounds<0>(x, w);
+  sha256_rounds<0, V>(x, w);
 #pragma unroll
   for (int i = 0; i < 8; i++) st[i] += x[i];
 }
@@ -198,24 +274,45 @@ __device__ __forceinline__ uint64_t rot64(uint64_t x) {
     return pair64(__builtin_amdgcn_alignbit(hi, lo, R - 32), __builtin_amdgcn_alignbit(lo, hi, R - 32));
   }
 }
+template <int V = 0>
 __device__ __forceinline__ uint64_t xor3_u64(uint64_t a, uint64_t b, uint64_t c) {
-  return opaque64(pair64(xor3(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32)),
-                         xor3(uint32_t(a), uint32_t(b), uint32_t(c))));
+  return opaque64(pair64(vxor3<V>(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32)),
+                         vxor3<V>(uint32_t(a), uint32_t(b), uint32_t(c))));
 }
+template <int V = 0>
 __device__ __forceinline__ uint64_t ch_u64(uint64_t e, uint64_t f, uint64_t g) {
-  return opaque64(pair64(ch32(uint32_t(e >> 32), uint32_t(f >> 32), uint32_t(g >> 32)),
-                         ch32(uint32_t(e), uint32_t(f), uint32_t(g))));
+  return opaque64(pair64(vch<V>(uint32_t(e >> 32), uint32_t(f >> 32), uint32_t(g >> 32)),
+                         vch<V>(uint32_t(e), uint32_t(f), uint32_t(g))));
 }
+template <int V = 0>
 __device__ __forceinline__ uint64_t maj_u64(uint64_t a, uint64_t b, uint64_t c) {
-  return opaque64(pair64(maj32(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32)),
-                         maj32(uint32_t(a), uint32_t(b), uint32_t(c))));
+  return opaque64(pair64(vmaj<V>(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32)),
+                         vmaj<V>(uint32_t(a), uint32_t(b), uint32_t(c))));
+}
+// a + b on 64 bits: one v_lshl_add_u64, or (kIsaAdds, two run-time values)
+// a v_add_co_u32 / v_addc_co_u32 carry pair.
+template <int V = 0>
+__device__ __forceinline__ uint64_t add_u64(uint64_t a, uint64_t b) {
+  if constexpr ((V & kIsaAdds) != 0) {
+    if (__builtin_constant_p(a) || __builtin_constant_p(b)) return a + b;
+    uint32_t lo, hi;
+    asm("v_add_co_u32 %0, vcc, %2, %3\n\tv_addc_co_u32 %1, vcc, %4, %5, vcc"
+        : "=&v"(lo), "=v"(hi)
+        : "v"(uint32_t(a)), "v"(uint32_t(b)), "v"(uint32_t(a >> 32)), "v"(uint32_t(b >> 32))
+        : "vcc");
+    return pair64(hi, lo);
+  } else {
+    return a + b;
+  }
 }
 
 // Sixteen SHA-512 rounds with the message schedule extended in place (SCHED:
 // rounds >= 16).  Ring-buffer indices are compile-time constants, so w[]
 // stays in VGPRs; after sixteen rounds the working variables are back in
-// their original registers.  kr: the sixteen round constants.
-template <bool SCHED>
+// their original registers.  kr: the sixteen round constants (read from
+// constant memory into scalar registers, so K + W stays one add in every
+// variant).
+template <bool SCHED, int V = 0>
 __device__ __forceinline__ void sha512_16rounds(uint64_t& a, uint64_t& b, uint64_t& c, uint64_t& d, uint64_t& e,
                                                 uint64_t& f, uint64_t& g, uint64_t& h, uint64_t w[16],
                                                 const uint64_t* kr) {
@@ -223,30 +320,31 @@ __device__ __forceinline__ void sha512_16rounds(uint64_t& a, uint64_t& b, uint64
   for (int i = 0; i < 16; i++) {
     if (SCHED) {
       const uint64_t x15 = w[(i + 1) & 15], x2 = w[(i + 14) & 15];
-      const uint64_t s0 = xor3_u64(rot64<1>(x15), rot64<8>(x15), x15 >> 7);
-      const uint64_t s1 = xor3_u64(rot64<19>(x2), rot64<61>(x2), x2 >> 6);
-      w[i] = w[i] + s0 + w[(i + 9) & 15] + s1;
+      const uint64_t s0 = xor3_u64<V>(rot64<1>(x15), rot64<8>(x15), x15 >> 7);
+      const uint64_t s1 = xor3_u64<V>(rot64<19>(x2), rot64<61>(x2), x2 >> 6);
+      w[i] = add_u64<V>(add_u64<V>(add_u64<V>(w[i], s0), w[(i + 9) & 15]), s1);
     }
-    const uint64_t S1 = xor3_u64(rot64<14>(e), rot64<18>(e), rot64<41>(e));
-    const uint64_t S0 = xor3_u64(rot64<28>(a), rot64<34>(a), rot64<39>(a));
-    const uint64_t t1 = h + (kr[i] + w[i]) + S1 + ch_u64(e, f, g);
-    const uint64_t t2 = S0 + maj_u64(a, b, c);
-    h = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = t1 + t2;
+    const uint64_t S1 = xor3_u64<V>(rot64<14>(e), rot64<18>(e), rot64<41>(e));
+    const uint64_t S0 = xor3_u64<V>(rot64<28>(a), rot64<34>(a), rot64<39>(a));
+    const uint64_t t1 = add_u64<V>(add_u64<V>(add_u64<V>(h, kr[i] + w[i]), S1), ch_u64<V>(e, f, g));
+    const uint64_t t2 = add_u64<V>(S0, maj_u64<V>(a, b, c));
+    h = g; g = f; f = e; e = add_u64<V>(d, t1); d = c; c = b; b = a; a = add_u64<V>(t1, t2);
   }
 }
 
 // One SHA-512 compression: st <- st + rounds(st, w).  w[] is overwritten.
 // Rounds 0-15 are peeled; rounds 16-79 run as a loop of four 16-round
 // blocks, which keeps the code at two copies of sixteen rounds.
+template <int V = 0>
 __device__ __forceinline__ void sha512_compress(u64p st[8], u64p w16[16]) {
   uint64_t w[16];
 #pragma unroll
   for (int i = 0; i < 16; i++) w[i] = to64(w16[i]);
   uint64_t a = to64(st[0]), b = to64(st[1]), c = to64(st[2]), d = to64(st[3]);
   uint64_t e = to64(st[4]), f = to64(st[5]), g = to64(st[6]), h = to64(st[7]);
-  sha512_16rounds<false>(a, b, c, d, e, f, g, h, w, kK512);
+  sha512_16rounds<false, V>(a, b, c, d, e, f, g, h, w, kK512);
 #pragma unroll 1
-  for (int r = 16; r < 80; r += 16) sha512_16rounds<true>(a, b, c, d, e, f, g, h, w, kK512 + r);
+  for (int r = 16; r < 80; r += 16) sha512_16rounds<true, V>(a, b, c, d, e, f, g, h, w, kK512 + r);
   st[0] = mk64(to64(st[0]) + a); st[1] = mk64(to64(st[1]) + b); st[2] = mk64(to64(st[2]) + c);
   st[3] = mk64(to64(st[3]) + d); st[4] = mk64(to64(st[4]) + e); st[5] = mk64(to64(st[5]) + f);
   st[6] = mk64(to64(st[6]) + g); st[7] = mk64(to64(st[7]) + h);

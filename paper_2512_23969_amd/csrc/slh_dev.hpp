@@ -217,21 +217,21 @@ __device__ __forceinline__ void th256_words(const Adrs& A, const uint32_t* x, ui
 
 // Tweakable hash with SHA-256 over one block: out = first NOUT words of
 // SHA-256(PK.seed || 0^(64-n) || ADRSc || x).
-template <int NX, int NOUT>
+template <int NX, int NOUT, int V = 0>
 __device__ __forceinline__ void th256(const uint32_t mid[8], const Adrs& A, const uint32_t* x,
                                       uint32_t* out) {
   uint32_t w[16], st[8];
   th256_words<NX>(A, x, w);
 #pragma unroll
   for (int i = 0; i < 8; i++) st[i] = mid[i];
-  sha256_rounds<0>(st, w);
+  sha256_rounds<0, V>(st, w);
 #pragma unroll
   for (int i = 0; i < NOUT; i++) out[i] = mid[i] + st[i];
 }
 
 // Tweakable hash with SHA-512 over one block: out = first NOUT BE words of
 // SHA-512(PK.seed || 0^(128-n) || ADRSc || x).  22 + 4 NX + 17 <= 128.
-template <int NX, int NOUT>
+template <int NX, int NOUT, int V = 0>
 __device__ __forceinline__ void th512(const uint32_t mid[16], const Adrs& A, const uint32_t* x,
                                       uint32_t* out) {
   static_assert(NX <= 22, "single block");
@@ -250,7 +250,7 @@ __device__ __forceinline__ void th512(const uint32_t mid[16], const Adrs& A, con
   for (int i = 0; i < 16; i++) w[i] = u64p{v[2 * i], v[2 * i + 1]};
 #pragma unroll
   for (int i = 0; i < 8; i++) st[i] = u64p{mid[2 * i], mid[2 * i + 1]};
-  sha512_compress(st, w);
+  sha512_compress<V>(st, w);
 #pragma unroll
   for (int i = 0; i < NOUT; i++) out[i] = (i & 1) ? st[i >> 1].lo : st[i >> 1].hi;
 }
@@ -261,34 +261,36 @@ __device__ __forceinline__ void th512(const uint32_t mid[16], const Adrs& A, con
 //
 // F and PRF: SHA-256 in every SHA2 category (FIPS 205 Sections 11.2.1 and
 // 11.2.2), SHAKE256 in the SHAKE ones (Section 11.1).
-template <int ID>
+// V: instruction variant of the SHA-2 arithmetic (sha2_dev.hpp); the SHAKE
+// sets have one form.
+template <int ID, int V = 0>
 __device__ __forceinline__ void thF(const uint32_t mid256[8], const Adrs& A, const uint32_t* x,
                                     uint32_t* out) {
   if constexpr (P<ID>::shake)
     thshake<P<ID>::NW, P<ID>::NW, P<ID>::NW>(mid256, A, x, out);
   else
-    th256<P<ID>::NW, P<ID>::NW>(mid256, A, x, out);
+    th256<P<ID>::NW, P<ID>::NW, V>(mid256, A, x, out);
 }
 // H: SHA-256 for n = 16, SHA-512 for n = 24, 32; SHAKE256 for the SHAKE sets.
-template <int ID>
+template <int ID, int V = 0>
 __device__ __forceinline__ void thH(const DevKey& key, const Adrs& A, const uint32_t* lr,
                                     uint32_t* out) {
   if constexpr (P<ID>::shake)
     thshake<P<ID>::NW, 2 * P<ID>::NW, P<ID>::NW>(key.mid256, A, lr, out);
   else if constexpr (P<ID>::wide)
-    th512<2 * P<ID>::NW, P<ID>::NW>(key.mid512, A, lr, out);
+    th512<2 * P<ID>::NW, P<ID>::NW, V>(key.mid512, A, lr, out);
   else
-    th256<2 * P<ID>::NW, P<ID>::NW>(key.mid256, A, lr, out);
+    th256<2 * P<ID>::NW, P<ID>::NW, V>(key.mid256, A, lr, out);
 }
-template <int ID>
+template <int ID, int V = 0>
 __device__ __forceinline__ void thH(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
                                     const uint32_t* lr, uint32_t* out) {
   if constexpr (P<ID>::shake)
     thshake<P<ID>::NW, 2 * P<ID>::NW, P<ID>::NW>(mid256, A, lr, out);
   else if constexpr (P<ID>::wide)
-    th512<2 * P<ID>::NW, P<ID>::NW>(mid512, A, lr, out);
+    th512<2 * P<ID>::NW, P<ID>::NW, V>(mid512, A, lr, out);
   else
-    th256<2 * P<ID>::NW, P<ID>::NW>(mid256, A, lr, out);
+    th256<2 * P<ID>::NW, P<ID>::NW, V>(mid256, A, lr, out);
 }
 
 // ---------------------------------------------------------------- T_l
@@ -296,7 +298,7 @@ __device__ __forceinline__ void thH(const uint32_t* mid256, const uint32_t* mid5
 // returns BE word `word_index` of the concatenated values.  The message is
 // ADRSc (22 bytes) | values, after the PK.seed block; SHA-256 for n = 16,
 // SHA-512 for n >= 24.  Message word q >= 6 is alignbit(V[q-6], V[q-5], 16).
-template <int ID, int L, class Get>
+template <int ID, int L, int V, class Get>
 __device__ __forceinline__ void thT_sha2(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
                                          Get get, uint32_t* out) {
   constexpr int NW = P<ID>::NW;
@@ -329,13 +331,13 @@ __device__ __forceinline__ void thT_sha2(const uint32_t* mid256, const uint32_t*
       uint32_t w[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) w[j] = first_word(j);
-      sha256_compress(st, w);
+      sha256_compress<V>(st, w);
     }
     for (int b = 1; b < NBLK; b++) {
       uint32_t w[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) w[j] = tail_word(16 * b + j);
-      sha256_compress(st, w);
+      sha256_compress<V>(st, w);
     }
 #pragma unroll
     for (int i = 0; i < NW; i++) out[i] = st[i];
@@ -347,13 +349,13 @@ __device__ __forceinline__ void thT_sha2(const uint32_t* mid256, const uint32_t*
       u64p w[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) w[j] = u64p{first_word(2 * j), first_word(2 * j + 1)};
-      sha512_compress(st, w);
+      sha512_compress<V>(st, w);
     }
     for (int b = 1; b < NBLK; b++) {
       u64p w[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) w[j] = u64p{tail_word(32 * b + 2 * j), tail_word(32 * b + 2 * j + 1)};
-      sha512_compress(st, w);
+      sha512_compress<V>(st, w);
     }
 #pragma unroll
     for (int i = 0; i < NW; i++) out[i] = (i & 1) ? st[i >> 1].lo : st[i >> 1].hi;
@@ -361,13 +363,13 @@ __device__ __forceinline__ void thT_sha2(const uint32_t* mid256, const uint32_t*
 }
 
 // T_l: SHA-2 after the PK.seed block, or SHAKE256 for the SHAKE sets.
-template <int ID, int L, class Get>
+template <int ID, int L, int V = 0, class Get>
 __device__ __forceinline__ void thT(const uint32_t* mid256, const uint32_t* mid512, const Adrs& A,
                                     Get get, uint32_t* out) {
   if constexpr (P<ID>::shake)
     thshake_t<P<ID>::NW, L>(mid256, A, get, out);
   else
-    thT_sha2<ID, L>(mid256, mid512, A, get, out);
+    thT_sha2<ID, L, V>(mid256, mid512, A, get, out);
 }
 
 // ---------------------------------------------------------------- byte streams

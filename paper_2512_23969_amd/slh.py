@@ -42,8 +42,26 @@ class SlhError(RuntimeError):
 
 
 class slh_tuning(ctypes.Structure):
-    _fields_ = [("fors_trees_per_group", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
-                ("keep_chains", ctypes.c_uint32), ("split_max_blocks", ctypes.c_uint32)]
+    _fields_ = [(f, ctypes.c_uint32) for f in
+                ("fors_trees_per_group", "wgs_per_cu", "keep_chains", "split_max_blocks", "fors_leaves_per_lane",
+                 "fors_threads", "tree_waves", "layer_order", "variant_tree", "variant_fors", "variant_verify",
+                 "reserved")]
+
+
+TUNING_FIELDS = tuple(f for f, _ in slh_tuning._fields_ if f != "reserved")
+LAYERS_PARALLEL, LAYERS_IN_ORDER = 0, 1
+VARIANT_DEFAULT, VARIANT_NO_BITOP3, VARIANT_SPLIT_ADDS = 0, 1, 2
+VARIANTS = {VARIANT_DEFAULT: "default", VARIANT_NO_BITOP3: "no-bitop3", VARIANT_SPLIT_ADDS: "split-adds"}
+
+
+def make_tuning(fors_trees_per_group=0, wgs_per_cu=0, keep_chains=1, split_max_blocks=0, **knobs):
+    """An slh_tuning from keyword knobs (the fields of slh.h; 0 = default)."""
+    t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks)
+    for k, v in knobs.items():
+        if k not in TUNING_FIELDS and k != "reserved":  # reserved: passed on for the library to refuse
+            raise TypeError("unknown tuning knob %r" % k)
+        setattr(t, k, int(v))
+    return t
 
 
 class slh_serve_config(ctypes.Structure):
@@ -221,14 +239,17 @@ class Context:
         _check(lib.slh_ctx_cache_keys(self.h, int(first_slot), int(count), int(layers)), self.h)
 
     def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0,
-                   keep_chains: int = 1, split_max_blocks: int = 0):
-        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks)
+                   keep_chains: int = 1, split_max_blocks: int = 0, **knobs):
+        """Set the kernel knobs of a parameter set (slh_tuning fields as keywords:
+        fors_leaves_per_lane, fors_threads, tree_waves, layer_order,
+        variant_tree, variant_fors, variant_verify; 0 = default)."""
+        t = make_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks, **knobs)
         _check(lib.slh_ctx_set_tuning(self.h, int(param), ctypes.byref(t)), self.h)
 
     def get_tuning(self, param: int) -> dict:
         t = slh_tuning()
         _check(lib.slh_ctx_get_tuning(self.h, int(param), ctypes.byref(t)), self.h)
-        return {f: getattr(t, f) for f, _ in t._fields_}
+        return {f: getattr(t, f) for f in TUNING_FIELDS}
 
     def profile(self, enable: bool = True):
         """Record HIP events around every kernel of later sign_batch calls."""
@@ -421,8 +442,8 @@ class Server:
         return first.value
 
     def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0, keep_chains: int = 1,
-                   split_max_blocks: int = 0):
-        t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks)
+                   split_max_blocks: int = 0, **knobs):
+        t = make_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks, **knobs)
         self._check(lib.slh_serve_set_tuning(self.h, int(param), ctypes.byref(t)))
 
     def replay(self, reqs: np.ndarray, msgs: bytes, skip: int = 0):

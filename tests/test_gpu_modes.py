@@ -1,8 +1,10 @@
 """GPU parity of the batched execution modes and of every tuning knob: the
 fused persistent kernel, the captured hipGraph (replayed several times with
 new message contents, eager work in between), mixed parameter sets in one
-launch, every compiled FORS group size and the recompute-WOTS variant all
-give the oracle's signature, byte for byte."""
+launch, every compiled FORS group size, the recompute-WOTS variant, every
+compiled kernel shape (FORS leaves per lane and workgroup lanes, TREE block
+waves), both layer orders and every instruction variant of the TREE, FORS
+and verification kernels all give the oracle's signature, byte for byte."""
 import numpy as np
 import pytest
 
@@ -94,8 +96,10 @@ def test_every_tuning_variant(slh, keys, param):
             for keep in (1, 0):
                 for wpc, split in ((0, slh.SPLIT_NEVER), (1, slh.SPLIT_NEVER), (0, 0), (0, 1)):
                     ctx.set_tuning(param, fg, wpc, keep, split)
-                    assert ctx.get_tuning(param) == {"fors_trees_per_group": fg, "wgs_per_cu": wpc,
-                                                     "keep_chains": keep, "split_max_blocks": split}
+                    t = ctx.get_tuning(param)
+                    assert {k: t[k] for k in ("fors_trees_per_group", "wgs_per_cu", "keep_chains",
+                                              "split_max_blocks")} == {
+                        "fors_trees_per_group": fg, "wgs_per_cu": wpc, "keep_chains": keep, "split_max_blocks": split}
                     for mode in ("plain", "fused"):
                         print(NAMES[param], fg, keep, wpc, split, mode, flush=True)
                         got = slh.sign_messages(ctx, [param] * 7, [slot] * 7, msgs, slh.MODES[mode])
@@ -104,12 +108,17 @@ def test_every_tuning_variant(slh, keys, param):
 
 def test_tuning_rejects_uncompiled_variants(slh):
     with slh.Context(0) as ctx:
-        with pytest.raises(slh.SlhError):
-            ctx.set_tuning(1, 3, 0, 1)
-        with pytest.raises(slh.SlhError):
-            ctx.set_tuning(3, 16, 0, 1)
-        with pytest.raises(slh.SlhError):
-            ctx.set_tuning(2, 8, 0, 2)
+        for args, knobs in (((1, 3, 0, 1), {}), ((3, 16, 0, 1), {}), ((2, 8, 0, 2), {}),
+                            ((1,), {"fors_leaves_per_lane": 8}), ((1,), {"fors_threads": 64}),
+                            ((1,), {"tree_waves": 3}), ((1,), {"layer_order": 2}), ((1,), {"variant_tree": 3}),
+                            ((1,), {"variant_tree": 1, "tree_waves": 8}),
+                            ((2,), {"variant_fors": 2, "fors_leaves_per_lane": 4}),
+                            ((3,), {"variant_fors": 1, "fors_threads": 512}),
+                            ((7,), {"variant_tree": 1}), ((9,), {"variant_verify": 2}),
+                            ((4,), {"tree_waves": 2}), ((5,), {"layer_order": 1}), ((1,), {"reserved": 1})):
+            with pytest.raises(slh.SlhError) as e:
+                ctx.set_tuning(*args, **knobs)
+            assert e.value.code == slh.EINVAL, (args, knobs)
 
 
 def test_reserve_then_sign(slh, keys):
@@ -164,3 +173,104 @@ def test_graph_after_key_table_grows(slh, keys):
                     assert host[o:o + sb] == want[i], "growth %d replay %d item %d" % (grow, rep, i)
                 d_s.zero_()
                 torch.cuda.synchronize()
+
+
+# every compiled shape of the per-phase kernels and of the fused kernel
+SHAPES = [dict(fors_leaves_per_lane=lpl, fors_threads=ft) for lpl in (2, 4) for ft in (128, 256, 512)]
+
+
+@pytest.mark.parametrize("param", [1, 2, 3, 7])
+def test_every_kernel_shape(slh, keys, param):
+    """FORS leaves per lane x workgroup lanes for every group size, TREE blocks
+    of 2/4/8 waves, in plain and fused mode (the fused kernel takes the leaves
+    per lane; its workgroups keep 256 lanes)."""
+    sk = keys[param][1] if param in keys else oracle_keys(param, [workloads.key_seed(param, 20)])[0][1]
+    msgs = workloads.messages(170 + param, 6, 40)
+    want = oracle_sign_many([(param, sk, m) for m in msgs])
+    with slh.Context(0) as ctx:
+        slot = ctx.add_keys(param, sk)
+        for fg in slh.FORS_GROUPS[param]:
+            for sh in SHAPES:
+                for waves in (2, 4, 8):
+                    ctx.set_tuning(param, fg, 0, 1, slh.SPLIT_NEVER, tree_waves=waves, **sh)
+                    for mode in ("plain", "fused") if sh["fors_threads"] == 256 and waves == 4 else ("plain",):
+                        what = "%s fg%d %s waves%d %s" % (NAMES[param], fg, sh, waves, mode)
+                        print(what, flush=True)
+                        got = slh.sign_messages(ctx, [param] * 6, [slot] * 6, msgs, slh.MODES[mode])
+                        _check(param, got, want, what)
+
+
+@pytest.mark.parametrize("param", [1, 2, 3, 7, 9])
+def test_layers_in_order(slh, keys, param):
+    """Layers signed in order (one TREE launch per layer, the WOTS+ signature
+    captured as the chains pass the digits) in every mode and block size,
+    with kept or recomputed chains requested (in-order keeps nothing), with
+    several keys and ragged messages, and a batch larger than one block per
+    layer; the dedup modes keep the parallel order."""
+    rng = np.random.default_rng([180, param])
+    ks = oracle_keys(param, [workloads.key_seed(param, 30 + i) for i in range(3)])
+    with slh.Context(0) as ctx:
+        first = ctx.add_keys(param, [sk for _, sk in ks])
+        for count in (5, 70):
+            kidx = [int(rng.integers(0, 3)) for _ in range(count)]
+            msgs = [rng.bytes(int(rng.integers(0, 200))) for _ in range(count)]
+            want = oracle_sign_many([(param, ks[k][1], m) for k, m in zip(kidx, msgs)])
+            for waves in (2, 4, 8):
+                for keep in (1, 0):
+                    ctx.set_tuning(param, 0, 0, keep, 0, tree_waves=waves, layer_order=slh.LAYERS_IN_ORDER)
+                    for mode in ("plain", "fused", "graph", "dedup", "fused-dedup"):
+                        if (waves != 4 or keep == 0) and mode not in ("plain", "fused"):
+                            continue
+                        what = "%s in-order n%d waves%d keep%d %s" % (NAMES[param], count, waves, keep, mode)
+                        print(what, flush=True)
+                        got = slh.sign_messages(ctx, [param] * count, [first + k for k in kidx], msgs,
+                                                slh.MODES[mode])
+                        _check(param, got, want, what)
+
+
+@pytest.mark.parametrize("param", [1, 2, 3])
+def test_every_instruction_variant(slh, keys, param):
+    """The TREE and FORS kernels in each instruction variant (alone and
+    together, plain and in-order, recomputed WOTS), then GPU verification in
+    each variant accepting the oracle's signatures and rejecting a corrupted
+    one."""
+    import torch
+    pk, sk = keys[param]
+    msgs = workloads.messages(190 + param, 6, 48)
+    want = oracle_sign_many([(param, sk, m) for m in msgs])
+    with slh.Context(0) as ctx:
+        slot = ctx.add_keys(param, sk)
+        for vt in (0, 1, 2):
+            for vf in (0, 1, 2):
+                for order in (slh.LAYERS_PARALLEL, slh.LAYERS_IN_ORDER):
+                    for keep in (1, 0):
+                        if order == slh.LAYERS_IN_ORDER and keep == 0:
+                            continue
+                        ctx.set_tuning(param, 0, 0, keep, slh.SPLIT_NEVER, variant_tree=vt, variant_fors=vf,
+                                       layer_order=order)
+                        what = "%s tree %s fors %s order %d keep %d" % (
+                            NAMES[param], slh.VARIANTS[vt], slh.VARIANTS[vf], order, keep)
+                        print(what, flush=True)
+                        got = slh.sign_messages(ctx, [param] * 6, [slot] * 6, msgs)
+                        _check(param, got, want, what)
+        sigs = list(want)
+        bad = bytearray(sigs[2])
+        bad[len(bad) // 2] ^= 0x10
+        sigs[2] = bytes(bad)
+        sb = slh.sizes(param)["sig_bytes"]
+        items = np.zeros(6, dtype=slh.VERIFY_DTYPE)
+        mblob = b"".join(msgs)
+        off = 0
+        for i, m in enumerate(msgs):
+            items[i] = (param, 0, off, len(m), i * sb, 0)
+            off += len(m)
+        d_m = torch.frombuffer(bytearray(mblob), dtype=torch.uint8).cuda()
+        d_s = torch.frombuffer(bytearray(b"".join(sigs)), dtype=torch.uint8).cuda()
+        d_pk = torch.frombuffer(bytearray(pk), dtype=torch.uint8).cuda()
+        for vv in (0, 1, 2):
+            ctx.set_tuning(param, variant_verify=vv)
+            res = torch.full((6,), -7, dtype=torch.int32, device="cuda")
+            print("%s verify %s" % (NAMES[param], slh.VARIANTS[vv]), flush=True)
+            ctx.verify_batch(items, d_m, d_s, d_pk, res)
+            torch.cuda.synchronize()
+            assert res.cpu().tolist() == [1, 1, 0, 1, 1, 1], "verify variant %d" % vv
