@@ -26,9 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "c2_128f_4096": "SPHINCS+-SHA2-128f, 1 key, 4096 x 32-byte messages",
-    "c3_192f_4096": "SPHINCS+-SHA2-192f, 1 key, 4096 x 32-byte messages",
-    "c4_256f_4096x64": "SPHINCS+-SHA2-256f, 64 keys, 4096 x 32-byte messages",
+    "c2_128f_4096": "SPHINCS+-SHA2-128f, 1 key, 4096 x 32-byte messages, one fused persistent launch",
+    "c3_192f_4096": "SPHINCS+-SHA2-192f, 1 key, 4096 x 32-byte messages, hipGraph-captured pipeline",
+    "c4_256f_4096x64": "SPHINCS+-SHA2-256f, 64 keys, 4096 x 32-byte messages, one fused multi-key launch",
     "s1_128s_1024": "SPHINCS+-SHA2-128s, 1 key, 1024 x 32-byte messages",
     "s2_192s_1024": "SPHINCS+-SHA2-192s, 1 key, 1024 x 32-byte messages",
     "s3_256s_1024": "SPHINCS+-SHA2-256s, 1 key, 1024 x 32-byte messages",
@@ -42,8 +42,30 @@ WORKLOADS = {
 # the metric as the benchmark specification names it; the value is the 128f
 # workload's, and "extra" holds the 192f and 256f ones
 METRIC = "signatures/s (128f/192f/256f, batch 4096) + p50/p99 latency; % VALU peak"
-# the batch-4096 workloads of the default line, each tuned and plain
+# the batch-4096 workloads of the default line, each in the execution mode
+# its configuration names and in the plain per-phase path
 DEFAULT_WORKLOADS = ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64")
+# "graph-any": the hipGraph-captured pipeline over the per-phase kernels or
+# over the fused kernel, whichever the autotuner found faster
+CONFIG_MODE = {"c2_128f_4096": "fused", "c3_192f_4096": "graph-any", "c4_256f_4096x64": "fused"}
+
+
+def resolve_mode(autotune, param, batch, mode, path=None):
+    """(mode, tuned knobs) for a requested mode: "auto" = the autotuner's
+    fastest, "graph-any" = its faster hipGraph pipeline, else the mode itself
+    with the knobs tuned for that mode (or the fastest mode's knobs)."""
+    path = path or autotune.DEFAULT_CACHE
+    if mode == "auto":
+        b = autotune.best_for(param, batch, None, path)
+        return (b or {}).get("mode", "plain"), b
+    if mode == "graph-any":
+        g = [autotune.best_for(param, batch, m, path) for m in ("graph-plain", "graph")]
+        g = [x for x in g if x]
+        if not g:
+            return "graph", autotune.best_for(param, batch, None, path)
+        b = min(g, key=lambda x: x["ms"])
+        return b["mode"], b
+    return mode, autotune.best_for(param, batch, mode, path) or autotune.best_for(param, batch, None, path)
 # HBM bytes per launch measured with rocprofv3 counters, valid while the
 # device sources hash to the value recorded with them
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_b4096.json")
@@ -236,7 +258,7 @@ def energy_summary(e0, e1, t0, t1, signatures, what):
 
 
 def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=None, verify=False,
-        telemetry_s=2.0):
+        telemetry_s=2.0, knobs=None):
     import torch
     from paper_2512_23969_amd import autotune
     ctx, items, d_m, d_s, cfg, msgs, kidx = setup(slh, workloads, name)
@@ -247,13 +269,13 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         torch.cuda.synchronize()
         best, _ = autotune.tune_and_store(slh, ctx, cfg["param"], items, d_m, d_s, cfg["batch"], path, log=log,
                                           verify=verify_inputs(slh, ctx, items, d_m, d_s, cfg, kidx))
-    else:
-        best = (autotune.lookup(cfg["param"], cfg["batch"], path) or {}).get("best")
-    tuned = None
+    mode, best = resolve_mode(autotune, cfg["param"], cfg["batch"], mode, path)
+    if knobs:
+        # explicit knobs over the tuned ones (profiling one kernel variant)
+        best = dict(best or autotune.KNOB_DEFAULTS, **knobs)
     if best:
-        tuned = autotune.apply(ctx, cfg["param"], best)
-    if mode == "auto":
-        mode = tuned or "plain"
+        autotune.apply(ctx, cfg["param"], best)
+        best = {k: v for k, v in best.items() if k != "by_mode"}
     m = slh.MODES[mode]
     ctx.dedup_stats(reset=True)
     stream = torch.cuda.current_stream()
@@ -610,10 +632,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2_128f_4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="auto",
-                    choices=["auto", "plain", "fused", "graph", "dedup", "fused-dedup", "graph-dedup"],
-                    help="execution mode; auto = the autotuned mode for the workload (dedup modes: "
-                         "within-batch tree dedup)")
+    ap.add_argument("--mode", default="config",
+                    choices=["config", "auto", "plain", "fused", "graph", "graph-plain", "graph-any", "dedup",
+                             "fused-dedup", "graph-dedup"],
+                    help="execution mode; config = the mode the workload's configuration names (fused launch, "
+                         "hipGraph pipeline), else the autotuned one; auto = the autotuner's fastest mode; "
+                         "graph-any = the faster hipGraph pipeline (dedup modes: within-batch tree dedup)")
     ap.add_argument("--tune", action="store_true", help="run the autotuner first and store its result")
     ap.add_argument("--tune-out", default=None, help="tuning cache file (default: the package's tuning.json)")
     ap.add_argument("--only", action="store_true",
@@ -636,6 +660,9 @@ def main():
                          "keeps 4 lanes x 4 streams busy; with 16 hardware queues none of them share one")
     ap.add_argument("--no-serve-dedup", action="store_true",
                     help="skip the second serving run (fused-dedup with 4 cached layers per key)")
+    ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
+                    help="set one slh_tuning knob of the --workload over its tuned value (repeatable); "
+                         "for profiling a kernel shape or instruction variant")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates HBM counters)")
     args = ap.parse_args()
@@ -659,9 +686,16 @@ def main():
     from paper_2512_23969_amd import slh, workloads
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log("bench: workload", args.workload, args.mode)
-    res = run(slh, workloads, args.workload, args.steps, args.warmup, args.mode, args.tune, args.tune_out,
-              verify=True, telemetry_s=args.telemetry_s)
+    mode0 = CONFIG_MODE.get(args.workload, "auto") if args.mode == "config" else args.mode
+    log("bench: workload", args.workload, mode0)
+    knobs = {}
+    for kv in args.knob:
+        k, _, v = kv.partition("=")
+        if k not in slh.TUNING_FIELDS:
+            ap.error("unknown knob %r (one of %s)" % (k, ", ".join(slh.TUNING_FIELDS)))
+        knobs[k] = int(v)
+    res = run(slh, workloads, args.workload, args.steps, args.warmup, mode0, args.tune, args.tune_out,
+              verify=True, telemetry_s=args.telemetry_s, knobs=knobs)
     param = res["cfg"]["param"]
     line = {
         "metric": METRIC,
@@ -697,15 +731,16 @@ def main():
     extra = {}
     steps_c = max(3, args.steps // 2)
     if not args.only:
-        # every batch-4096 SHA2 fast-set workload in its autotuned mode and in
-        # the plain per-phase path, the reference the batched modes are
-        # measured against
+        # every batch-4096 SHA2 fast-set workload in the execution mode its
+        # configuration names (with that mode's tuned knobs) and in the plain
+        # per-phase path, the reference the batched modes are measured against
         from paper_2512_23969_amd import autotune
         for name in DEFAULT_WORKLOADS:
             cfg = workloads.CONFIGS[name]
-            tuned_mode = ((autotune.lookup(cfg["param"], cfg["batch"]) or {}).get("best") or {}).get("mode", "plain")
+            cmode, _ = resolve_mode(autotune, cfg["param"], cfg["batch"], CONFIG_MODE[name])
             got = {}
-            for mode in dict.fromkeys((tuned_mode, "plain")):
+            # a fused graph's kernels are timed in an eager fused run beside it
+            for mode in dict.fromkeys((cmode, "plain") + (("fused",) if cmode == "graph" else ())):
                 if name == args.workload and mode == res["mode"]:
                     got[mode] = summary(acc, res, mode)
                     continue
@@ -714,10 +749,14 @@ def main():
                 got[mode] = summary(acc, r, mode)
             for mode, v in got.items():
                 extra["%s/%s" % (name, mode)] = v
-            tuned = [m for m in got if m != "plain"]
-            if tuned and "plain" in got:
-                extra["%s/tuned_vs_plain" % name] = {
-                    "tuned_mode": tuned[0], "ratio": round(got[tuned[0]]["value"] / got["plain"]["value"], 4)}
+            if cmode != "plain":
+                extra["%s/config_vs_plain" % name] = {
+                    "config_mode": cmode, "ratio": round(got[cmode]["value"] / got["plain"]["value"], 4)}
+                if "graph" in cmode:
+                    # a graph replays the same kernels; their per-kernel figures
+                    # are those of the eager run of the same knobs
+                    base = "plain" if cmode == "graph-plain" else "fused"
+                    extra["%s/%s" % (name, cmode)]["roofline_of_kernels"] = "%s/%s" % (name, base)
     if args.all:
         log("bench: small-batch latency")
         line["latency"] = latency_bench(slh, workloads)

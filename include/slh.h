@@ -403,7 +403,26 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *                         exists for the default shape of its kernel
  *                         (tree_waves 4; fors_leaves_per_lane 2 and
  *                         fors_threads 256); the fused kernel has the
- *                         default only */
+ *                         default only
+ *   fused_wave0_chunks    fused mode: chains chunks (one chain of each of a
+ *                         block's 64 leaves) that wave 0 of a workgroup runs
+ *                         per TREE block while it also finishes the previous
+ *                         block (T_len and the XMSS levels); the other waves
+ *                         share the rest.  0 = the share that balances the
+ *                         instruction counts (four waves: 8 / 11 / 14 for len 35 /
+ *                         51 / 67, per block of an item); else 2 ..
+ *                         fused_blocks_per_item x len - 6
+ *   fused_waves           fused mode: waves per persistent workgroup, 4 or 2
+ *                         (0 = 4; fast sets).  A TREE block's chains go to
+ *                         the waves in whole chunks and each block ends at a
+ *                         workgroup barrier; with two waves the chunk split
+ *                         (fused_wave0_chunks default 17 / 24 / 31) leaves
+ *                         less of a block's time unbalanced
+ *   fused_blocks_per_item fused mode: TREE blocks per work item, 1 or 2
+ *                         (0 = 1; fast sets).  With 2 the chunks of both
+ *                         blocks are dealt out together (wave 0's default
+ *                         share doubles), which balances the waves more
+ *                         finely; staging per workgroup doubles */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;
@@ -416,7 +435,9 @@ typedef struct {
     uint32_t variant_tree;
     uint32_t variant_fors;
     uint32_t variant_verify;
-    uint32_t reserved; /* 0 */
+    uint32_t fused_wave0_chunks;
+    uint32_t fused_waves;
+    uint32_t fused_blocks_per_item;
 } slh_tuning;
 #define SLH_SPLIT_NEVER 0xFFFFFFFFu
 #define SLH_LAYERS_PARALLEL 0u

@@ -134,6 +134,18 @@ def lookup(param: int, batch: int, path: str = DEFAULT_CACHE):
     return c.get(cache_key(_arch(), param, batch))
 
 
+def best_for(param: int, batch: int, mode: str | None = None, path: str = DEFAULT_CACHE):
+    """The tuned knobs of the fastest mode (mode None) or of `mode` (plain,
+    fused, graph-plain, graph) for (this GPU, param, batch), or None."""
+    e = lookup(param, batch, path)
+    if not e:
+        return None
+    b = e.get("best")
+    if mode is None or (b and b.get("mode") == mode):
+        return b
+    return (b or {}).get("by_mode", {}).get(mode)
+
+
 # Knobs the empirical stage searches, per parameter-set family (slh.h
 # slh_tuning): fast sets have every FORS and TREE shape and both layer
 # orders; the SHA2 fast sets also the instruction variants; the small sets
@@ -145,7 +157,12 @@ VARIANTS = (1, 2)  # SLH_VARIANT_NO_BITOP3, SLH_VARIANT_SPLIT_ADDS (0 is the def
 WGS_PER_CU = (0, 1, 2, 3)
 KNOB_DEFAULTS = {"fors_trees_per_group": 0, "wgs_per_cu": 0, "keep_chains": 1, "split_max_blocks": 0,
                  "fors_leaves_per_lane": 2, "fors_threads": 256, "tree_waves": 4, "layer_order": 0,
-                 "variant_tree": 0, "variant_fors": 0, "variant_verify": 0}
+                 "variant_tree": 0, "variant_fors": 0, "variant_verify": 0, "fused_wave0_chunks": 0,
+                 "fused_waves": 4, "fused_blocks_per_item": 1}
+# default chains chunks of wave 0 in a fused TREE block, by waves per
+# workgroup and len (35 / 51 / 67)
+FUSED_W0 = {4: {35: 8, 51: 11, 67: 14}, 2: {35: 17, 51: 24, 67: 31}}
+FUSED_WAVES = (4, 2)
 
 
 def _fast(param):
@@ -204,8 +221,11 @@ def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 7, log=None, v
          (parallel with kept or recomputed chains, or in order), and the
          instruction variants;
       3. mode: the per-phase path with the winners of 1-2 against the fused
-         persistent kernel (trees per group x leaves per lane x persistent
-         workgroups per CU x keep_chains);
+         persistent kernel (trees per group x leaves per lane at 4 and 2
+         waves per workgroup, then 1 or 2 TREE blocks per work item, then
+         persistent workgroups per CU x
+         keep_chains, then wave 0's share of a TREE block around the
+         default), and each mode's winner captured in a hipGraph;
       4. verification (if `verify` = (items, msgs, sigs, pks, results) is
          given): the instruction variants of the verify kernel.
     Every point is the median of `reps` timed runs after a warm-up."""
@@ -259,20 +279,55 @@ def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 7, log=None, v
                 tree.append(row)
     best = min(tree, key=lambda r: r["ms"])
     say("mode", dict(best))
-    # 3. the fused persistent kernel (parallel layers; workgroups of 256 lanes)
+    # 3. the fused persistent kernel (parallel layers): its FORS shape at each
+    # workgroup size, then persistent workgroups per CU and kept chains, then
+    # wave 0's share of a TREE block around the default
     if _fast(param):
-        for fg in slh.FORS_GROUPS[param]:
-            for lpl in LPLS:
-                for wpc in WGS_PER_CU:
-                    for keep in (1, 0):
-                        k = knobs(fors_trees_per_group=fg, fors_leaves_per_lane=lpl, wgs_per_cu=wpc,
-                                  keep_chains=keep)
-                        setk(k)
-                        med, mn = _events_ms(torch, stream, sign("fused"), reps)
-                        row = dict(k, mode="fused", ms=round(med, 4), min_ms=round(mn, 4))
-                        say("mode", row)
-                        if row["ms"] < best["ms"]:
-                            best = row
+        fused = []
+
+        def time_fused(k):
+            setk(k)
+            med, mn = _events_ms(torch, stream, sign("fused"), reps)
+            row = dict(k, mode="fused", ms=round(med, 4), min_ms=round(mn, 4))
+            say("mode", row)
+            fused.append(row)
+            return row
+
+        for nw in FUSED_WAVES:
+            for fg in slh.FORS_GROUPS[param]:
+                for lpl in LPLS:
+                    time_fused(knobs(fors_trees_per_group=fg, fors_leaves_per_lane=lpl, fused_waves=nw))
+        fb = min(fused, key=lambda r: r["ms"])
+        time_fused(dict(fb, fused_blocks_per_item=2))
+        fb = min(fused, key=lambda r: r["ms"])
+        per = 4 // fb["fused_waves"]  # workgroups of this size per four-wave workgroup
+        for wpc in WGS_PER_CU:
+            for keep in (1, 0):
+                if (wpc, keep) != (0, 1):
+                    time_fused(dict(fb, wgs_per_cu=wpc * per, keep_chains=keep))
+        fb = min(fused, key=lambda r: r["ms"])
+        w0d = FUSED_W0[fb["fused_waves"]][slh.sizes(param)["len"]] * fb["fused_blocks_per_item"]
+        for w0 in (w0d - 2, w0d - 1, w0d + 1, w0d + 2):
+            time_fused(dict(fb, fused_wave0_chunks=w0))
+        fb = min(fused, key=lambda r: r["ms"])
+        if fb["ms"] < best["ms"]:
+            best = fb
+    # the hipGraph-captured pipeline of each mode's best knobs
+    by_mode = {}
+    for r in stages["mode"]:
+        if r["mode"] not in by_mode or r["ms"] < by_mode[r["mode"]]["ms"]:
+            by_mode[r["mode"]] = dict(r)
+    for base_mode, graph_mode in (("plain", "graph-plain"), ("fused", "graph")):
+        if base_mode not in by_mode:
+            continue
+        k = dict(by_mode[base_mode])
+        setk(k)
+        med, mn = _events_ms(torch, stream, sign(graph_mode), reps)
+        row = dict(k, mode=graph_mode, ms=round(med, 4), min_ms=round(mn, 4))
+        say("mode", row)
+        by_mode[graph_mode] = row
+        if row["ms"] < best["ms"]:
+            best = row
     # 4. verification
     best = dict(best)
     if verify is not None:
@@ -287,7 +342,10 @@ def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 7, log=None, v
             if vbest is None or row["ms"] < vbest["ms"]:
                 vbest = row
         best["variant_verify"] = vbest["variant_verify"]
+        for r in by_mode.values():
+            r["variant_verify"] = vbest["variant_verify"]
     apply(ctx, param, best)
+    best["by_mode"] = by_mode
     return best, stages
 
 
@@ -305,6 +363,7 @@ def tune_and_store(slh, ctx, param, items, d_msgs, d_sigs, batch, path: str = DE
 
 
 def apply(ctx, param: int, setting: dict):
-    """Set the tuned knobs on a context; returns the tuned mode name."""
+    """Set the tuned knobs (a row of the tuner's tables) on a context;
+    returns its mode name."""
     ctx.set_tuning(param, **{f: setting.get(f, v) for f, v in KNOB_DEFAULTS.items()})
     return setting.get("mode", "plain")

@@ -850,6 +850,11 @@ int slh_verify_batch_ext(slh_ctx* c, const slh_verify_item_ext* items, uint32_t 
 
 namespace {
 
+uint32_t len_of(uint32_t param) {
+  Sizes sz;
+  return sizes_of(param, &sz) ? sz.len : 0u;
+}
+
 // Knobs of set `param` from a caller's slh_tuning (0 = default), checked
 // against the compiled kernels; on error *msg says why.
 bool resolve_tuning(uint32_t param, const slh_tuning& t, Tuning* out, std::string* msg) {
@@ -875,8 +880,16 @@ bool resolve_tuning(uint32_t param, const slh_tuning& t, Tuning* out, std::strin
   if (r.inorder > SLH_LAYERS_IN_ORDER) return *msg = "unknown layer_order", false;
   if (r.vtree > SLH_VARIANT_SPLIT_ADDS || r.vfors > SLH_VARIANT_SPLIT_ADDS || r.vverify > SLH_VARIANT_SPLIT_ADDS)
     return *msg = "unknown instruction variant", false;
-  if (t.reserved) return *msg = "reserved field must be 0", false;
-  if (!fast_set(param) && (r.lpl != 2 || r.fors_threads != uint32_t(kForsThreads) || r.tree_waves != 4 || r.inorder))
+  r.fused_waves = t.fused_waves ? t.fused_waves : 4u;
+  if (r.fused_waves != 2 && r.fused_waves != 4) return *msg = "fused_waves must be 2 or 4", false;
+  r.fused_bpi = t.fused_blocks_per_item ? t.fused_blocks_per_item : 1u;
+  if (r.fused_bpi != 1 && r.fused_bpi != 2) return *msg = "fused_blocks_per_item must be 1 or 2", false;
+  r.fused_w0 = t.fused_wave0_chunks;
+  if (r.fused_w0 && (r.fused_w0 < 2 || r.fused_w0 > r.fused_bpi * len_of(param) - 6))
+    return *msg = "fused_wave0_chunks must be 0 or 2 .. blocks per item x len - 6", false;
+  if (!fast_set(param) &&
+      (r.lpl != 2 || r.fors_threads != uint32_t(kForsThreads) || r.tree_waves != 4 || r.inorder || r.fused_waves != 4 ||
+       r.fused_bpi != 1))
     return *msg = "the small parameter sets have the default kernel shapes and layer order only", false;
   if (!sha2_fast_set(param) && (r.vtree || r.vfors || r.vverify))
     return *msg = "instruction variants exist for the SHA2 fast sets only", false;
@@ -920,6 +933,9 @@ int slh_ctx_get_tuning(const slh_ctx* c, uint32_t param, slh_tuning* t) {
   t->variant_tree = r.vtree;
   t->variant_fors = r.vfors;
   t->variant_verify = r.vverify;
+  t->fused_wave0_chunks = r.fused_w0;
+  t->fused_waves = r.fused_waves;
+  t->fused_blocks_per_item = r.fused_bpi;
   return SLH_OK;
 }
 

@@ -35,6 +35,9 @@ struct Tuning {
   uint32_t tree_waves = 4;  // waves of a per-phase TREE block
   uint32_t inorder = 0;     // layers signed in order
   uint32_t vtree = 0, vfors = 0, vverify = 0;  // SHA-2 instruction variants
+  uint32_t fused_w0 = 0;  // fused kernel: wave 0's chunks per TREE block (0 = default)
+  uint32_t fused_waves = 4;  // fused kernel: waves per workgroup
+  uint32_t fused_bpi = 1;    // fused kernel: TREE blocks per work item
 };
 
 struct GraphKey {

@@ -671,15 +671,19 @@ struct TreeList {
 // NWAV: waves of the block (chunk split of TreeSplit); V: instruction
 // variant; CAP: layers signed in order, the signing leaf's chains write the
 // WOTS+ signature of the layer as they pass its digits.
+// w0 > 0 overrides wave 0's share of the chunks (the fused kernel's tuning);
+// cstep > 0 overrides the whole split: this wave runs chunks cbeg, cbeg +
+// cstep, ... below cend (the fused kernel's items of several blocks).
 template <int ID, int KIND, bool SPLIT = false, int NWAV = 4, int V = 0, bool CAP = false>
 __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, WorkRec* __restrict__ recs,
                                             uint32_t ntrees, uint8_t* sigs, uint32_t* __restrict__ st,
                                             uint32_t* __restrict__ spill, uint32_t key_slot, uint32_t* root_out,
-                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr, nullptr, 0u}) {
+                                            uint32_t block, TreeList tl = TreeList{nullptr, nullptr, nullptr, 0u},
+                                            int w0 = 0, int cbeg = 0, int cend_ = 0, int cstep_ = 0) {
   using Q = P<ID>;
   constexpr int NW = Q::NW, LEN = Q::len, LV = 1 << Q::unit_hp, UT = Q::tree_units;
   constexpr int TPB = kLeavesPerBlock / LV;
-  constexpr int W0 = TreeSplit<ID, NWAV>::wave0;
+  const int W0 = w0 > 0 ? w0 : TreeSplit<ID, NWAV>::wave0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t tree0 = block * TPB;
   const uint32_t lt = lane / LV;
@@ -700,9 +704,9 @@ __device__ __forceinline__ void tree_chains(const DevKey* __restrict__ keys, Wor
   // a block of NWAV waves: wave 0 chunks 0 .. W0-1, waves 1..NWAV-1 chunks
   // W0 + (wave - 1) + (NWAV - 1) i; a split block (one wave per workgroup,
   // part blockIdx.y of gridDim.y): chunks part, part + parts, ...
-  const int c0 = SPLIT ? int(blockIdx.y) : (wave == 0 ? 0 : W0 + wave - 1);
-  const int cend = SPLIT ? LEN : (wave == 0 ? W0 : LEN);
-  const int cstep = SPLIT ? int(gridDim.y) : (wave == 0 ? 1 : NWAV - 1);
+  const int c0 = cstep_ > 0 ? cbeg : SPLIT ? int(blockIdx.y) : (wave == 0 ? 0 : W0 + wave - 1);
+  const int cend = cstep_ > 0 ? cend_ : SPLIT ? LEN : (wave == 0 ? W0 : LEN);
+  const int cstep = cstep_ > 0 ? cstep_ : SPLIT ? int(gridDim.y) : (wave == 0 ? 1 : NWAV - 1);
   const bool cap = CAP && int32_t(kp) == J.sign_leaf;
   for (int c = c0; c < cend; c += cstep) {
     uint32_t x[NW];
@@ -881,6 +885,12 @@ __global__ void k_tree_top(const DevKey* __restrict__ keys, WorkRec* __restrict_
 // with the grid, not the batch.  The counter is zeroed by k_prelude of the
 // same batch; every workgroup leaves once the counter passes the end.
 //
+// wave0_chunks: chunks of an item's chains that wave 0 runs (it also
+// finishes the previous item); 0 = TreeSplit's share per block, which
+// balances instruction counts.  bpi: TREE blocks per work item (1 or 2):
+// the chunks of both blocks of an item are dealt out together, so the
+// waves' shares can be balanced more finely.
+//
 // Waves per SIMD the fused kernel is compiled for (bounds its VGPRs to 168).
 // Three for every set: a four-wave build (128 VGPRs, a few spills) ran no
 // faster, and the persistent grid gains nothing beyond three workgroups per
@@ -890,26 +900,45 @@ struct FusedOcc {
   static constexpr int waves = 3;
 };
 
-template <int ID, int FG, int LPL = 2>
-__global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
+// NWAV: waves per workgroup, 4 or 2.  A TREE block's chains are dealt to
+// the waves in whole chunks (one chain of all 64 leaves), and every item
+// ends at a workgroup barrier, so the slowest wave sets an item's time:
+// with four waves the three chunk waves share len - w0 chunks evenly only
+// when that divides by three (192f: 14 + 13 + 13 against wave 0's 11 +
+// finish); with two waves, wave 0's chunks plus the finish and wave 1's
+// chunks can be balanced to within half a chunk.  FORS groups of the same
+// workgroup use 64 NWAV lanes.
+template <int ID, int FG, int LPL = 2, int NWAV = 4>
+__global__ __launch_bounds__(64 * NWAV, FusedOcc<ID>::waves) void k_fused(
     const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg, uint8_t* sigs,
     uint32_t* __restrict__ stage, uint32_t* __restrict__ spill, uint32_t* __restrict__ roots, uint32_t* queue,
     uint32_t ntb, uint32_t nfg, const uint32_t* ulist, const uint32_t* ucount, const uint32_t* lown,
-    uint32_t* nodes) {
-  static_assert(kTreeThreads == kForsThreads, "one workgroup shape for both item kinds");
+    uint32_t* nodes, uint32_t wave0_chunks, uint32_t bpi) {
+  static_assert(NWAV == 2 || NWAV == 4, "fused workgroups of 2 or 4 waves");
   using Q = P<ID>;
-  constexpr size_t SW = size_t(Q::len) * kLeavesPerBlock * Q::NW;  // words of one staging buffer
+  constexpr int LEN = Q::len;
+  constexpr size_t SW = size_t(LEN) * kLeavesPerBlock * Q::NW;  // words of one block's staging
   __shared__ uint32_t node[FG * ForsLeaves<ID, LPL>::BASE * Q::NW];
   __shared__ uint32_t item;
-  uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * SW;
+  uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * bpi * SW;
   const TreeList tl{ulist, ucount, lown, 0u};
   const uint32_t ntrees = nmsg * Q::d;
   constexpr uint32_t TPB = kLeavesPerBlock / Q::leaves;
   if (ucount) ntb = (*ucount + TPB - 1) / TPB;  // TREE blocks over the distinct trees only
-  const uint32_t total = ntb + nfg;
-  const bool w0 = (threadIdx.x >> 6) == 0;
-  uint32_t pend = 0xffffffffu;  // TREE block waiting for its finish (uniform)
-  uint32_t cur = 0;             // staging buffer of the next TREE block (uniform)
+  const uint32_t nti = (ntb + bpi - 1) / bpi;   // TREE items of bpi blocks
+  const uint32_t total = nti + nfg;
+  const int wave = int(threadIdx.x >> 6);
+  const bool w0 = wave == 0;
+  // this wave's chunks of an item: wave 0 takes 0 .. W0-1, wave k >= 1 takes
+  // W0 + (k - 1) + (NWAV - 1) i, over the bpi * len chunks of the item
+  const int W0 = wave0_chunks ? int(wave0_chunks) : int(bpi) * TreeSplit<ID, NWAV>::wave0;
+  const int cc0 = w0 ? 0 : W0 + wave - 1, ccend = w0 ? W0 : int(bpi) * LEN, ccstep = w0 ? 1 : NWAV - 1;
+  uint32_t pend = 0xffffffffu;  // TREE item waiting for its finish (uniform)
+  uint32_t cur = 0;             // staging half of the next TREE item (uniform)
+  auto finish = [&](uint32_t ti, uint32_t* st) {
+    for (uint32_t b = 0; b < bpi && ti * bpi + b < ntb; b++)
+      tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st + b * SW, spill, 0u, nullptr, ti * bpi + b, tl, nodes);
+  };
   for (;;) {
     if (threadIdx.x == 0) item = atomicAdd(queue, 1u);
     __syncthreads();
@@ -917,21 +946,29 @@ __global__ __launch_bounds__(kTreeThreads, FusedOcc<ID>::waves) void k_fused(
     __syncthreads();  // everyone holds `it` before thread 0 may overwrite `item`
     if (it >= total) break;
     if (pend != 0xffffffffu) {
-      // finish the previous TREE block while the other waves start this item
-      if (w0) tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u, nullptr, pend, tl,
-                                     nodes);
+      // finish the previous TREE item while the other waves start this item
+      if (w0) finish(pend, st0 + (cur ^ 1) * bpi * SW);
       pend = 0xffffffffu;
     }
-    if (it < ntb) {
-      tree_chains<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + cur * SW, spill, 0u, nullptr, it, tl);
+    if (it < nti) {
+      uint32_t* st = st0 + cur * bpi * SW;
+      for (uint32_t b = 0; b < bpi && it * bpi + b < ntb; b++) {
+        // this wave's chunks inside block b: the part of its sequence in
+        // [b len, (b + 1) len), shifted to the block's own chunk numbers
+        const int lo = int(b) * LEN, hi = lo + LEN;
+        const int first = cc0 >= lo ? cc0 : cc0 + ((lo - cc0 + ccstep - 1) / ccstep) * ccstep;
+        const int end = ccend < hi ? ccend : hi;
+        if (first < end)
+          tree_chains<ID, kSignTrees, false, NWAV>(keys, recs, ntrees, sigs, st + b * SW, spill, 0u, nullptr,
+                                                   it * bpi + b, tl, 0, first - lo, end - lo, ccstep);
+      }
       pend = it;
       cur ^= 1;
     } else {
-      fors_group<ID, FG, LPL>(keys, recs, nmsg * Q::k, sigs, roots, it - ntb, node);
+      fors_group<ID, FG, LPL, 64 * NWAV>(keys, recs, nmsg * Q::k, sigs, roots, it - nti, node);
     }
   }
-  if (pend != 0xffffffffu && w0) tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + (cur ^ 1) * SW, spill, 0u,
-                                                        nullptr, pend, tl, nodes);
+  if (pend != 0xffffffffu && w0) finish(pend, st0 + (cur ^ 1) * bpi * SW);
 }
 
 // ------------------------------------------------------------------ WOTS
@@ -1162,7 +1199,7 @@ __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restric
 // Batched verification (FIPS 205 Algorithm 20).  A group of G lanes (16: a
 // quarter of a wave; 32 for batches too small to give every SIMD a wave at
 // 16) verifies one signature; a workgroup of 256 lanes holds 256 / G
-// signatures that go through the same phases together:
+// signatures:
 //   setup   : the group's first lane derives the per-key chaining values,
 //             recomputes the digest (H_msg) and splits it;
 //   FORS    : one lane per FORS tree (trees g, g + G, ...) climbs from the
@@ -1172,7 +1209,14 @@ __global__ void k_wots_dedup(const DevKey* __restrict__ keys, WorkRec* __restric
 //             r mod G, reversed on odd rounds), so that every lane has about
 //             the same number of F steps; each lane works through its chains
 //             step by step; the first lane then runs T_len and climbs the
-//             h' authentication levels to the layer's root.
+//             h' authentication levels to the layer's root.  The next
+//             lanes load that layer's h' authentication nodes into LDS while
+//             the chains start, so the climb does not wait for memory.
+// A group never spans two waves, and its lanes share only LDS slots of
+// their own group, so the phases are separated by wave-local ordering
+// (wave_sync) rather than workgroup barriers: each wave moves on as soon as
+// its own four (or two) signatures are done with a phase, instead of
+// waiting for the slowest signature of the workgroup.
 // The result (1 valid, 0 invalid) is written to results[res_idx].  V: the
 // instruction variant of the chain, tree and T_l hashes (sha2_dev.hpp).
 struct VerifyItem {
@@ -1191,6 +1235,28 @@ __device__ __forceinline__ void load_be(const uint8_t* p, uint32_t* v) {
 #pragma unroll
   for (int i = 0; i < NW; i++) v[i] = load_be32(p + 4 * i);
 }
+// The same from a 4-byte aligned address as dword loads (`aligned`), else
+// byte by byte.
+template <int NW>
+__device__ __forceinline__ void load_be_any(const uint8_t* p, bool aligned, uint32_t* v) {
+  if (aligned) {
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+    for (int i = 0; i < NW; i++) v[i] = __builtin_bswap32(q[i]);
+  } else {
+    load_be<NW>(p, v);
+  }
+}
+
+// Orders the LDS accesses of one wave: the lanes of a wave execute in
+// lockstep and a wave's LDS operations complete in issue order, so a
+// compiler fence around the wave barrier is all that separates a phase's
+// LDS writes from the next phase's reads by other lanes of the same wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Base-16 digit of WOTS+ chain c for message words M (len1 message digits,
 // then the three checksum digits of csum << 4), FIPS 205 Algorithm 7.
@@ -1206,10 +1272,13 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
                                                           const uint8_t* sigs, const uint8_t* pks,
                                                           int* results) {
   using Q = P<ID>;
-  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a, kVerifySigs = kVerifyThreads / G;
+  constexpr int NW = Q::NW, LEN = Q::len, KT = Q::k, A = Q::a, HP = Q::hp, kVerifySigs = kVerifyThreads / G;
   constexpr int SLOTS = (LEN + G - 1) / G;
   static_assert(KT <= 64, "FORS indices per signature");
+  static_assert(64 % G == 0, "a verify group lies inside one wave");
+  static_assert(HP < G, "one loading lane per authentication node");
   __shared__ uint32_t s_vals[kVerifySigs][(LEN > KT ? LEN : KT) * NW];
+  __shared__ uint32_t s_auth[kVerifySigs][HP * NW];
   __shared__ uint16_t s_order[kVerifySigs][SLOTS * G];
   __shared__ uint16_t s_idx[kVerifySigs][64];
   __shared__ uint32_t s_mid256[kVerifySigs][8], s_mid512[kVerifySigs][16], s_root[kVerifySigs][8];
@@ -1221,6 +1290,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
   const bool valid = sidx < count;
   const VerifyItem it = valid ? items[sidx] : VerifyItem{0, 0, 0, 0, 0};
   const uint8_t* sig = sigs + it.sig_off;
+  const bool al = (reinterpret_cast<uintptr_t>(sig) & 3) == 0;  // every signature part is then aligned
   uint32_t* vals = s_vals[grp];
   // ---- setup
   if (valid && g == 0) {
@@ -1252,7 +1322,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
 #pragma unroll
     for (int j = 0; j < 8; j++) s_root[grp][j] = pk_root[j];
     uint32_t R[NW], digest[16];
-    load_be<NW>(sig, R);
+    load_be_any<NW>(sig, al, R);
     const KeyView kv{nullptr, pk_seed, pk_root, nullptr};
     h_msg<ID>(kv, R, msgs + it.msg_off, it.msg_len, digest);
     uint64_t tree;
@@ -1261,7 +1331,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     s_tree[grp] = tree;
     s_leaf[grp] = leaf;
   }
-  __syncthreads();
+  wave_sync();
   uint32_t mid256[8], mid512[16];
 #pragma unroll
   for (int j = 0; j < 8; j++) mid256[j] = s_mid256[grp][j];
@@ -1275,12 +1345,12 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
       const uint8_t* ts = sig + Q::n + t * (A + 1) * Q::n;
       const uint32_t idx = s_idx[grp][t];
       uint32_t x[NW], y[NW], lr[2 * NW];
-      load_be<NW>(ts, x);
+      load_be_any<NW>(ts, al, x);
       uint32_t gi = (uint32_t(t) << A) + idx;
       thF<ID, V>(mid256, make_adrs(0, tree, A_FORS_TREE, leaf, 0, gi), x, y);
       for (int j = 0; j < A; j++) {
         uint32_t au[NW];
-        load_be<NW>(ts + (1 + j) * Q::n, au);
+        load_be_any<NW>(ts + (1 + j) * Q::n, al, au);
         const bool even = ((idx >> j) & 1u) == 0;
 #pragma unroll
         for (int u = 0; u < NW; u++) {
@@ -1293,14 +1363,14 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
       store_words<NW>(&vals[t * NW], y);
     }
   }
-  __syncthreads();
+  wave_sync();
   if (valid && g == 0) {
     auto get = [&](int wi) -> uint32_t { return vals[wi]; };
     uint32_t pk[NW];
     thT<ID, KT, V>(mid256, mid512, make_adrs(0, tree, A_FORS_ROOTS, leaf, 0, 0), get, pk);
     store_words<NW>(s_cur[grp], pk);
   }
-  __syncthreads();
+  wave_sync();
   const uint8_t* ht = sig + Q::ht_off;
   for (int layer = 0; layer < Q::d; layer++) {
     const uint8_t* xs = ht + layer * Q::xmss_bytes;
@@ -1312,11 +1382,17 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
     for (int i = 0; i < Q::len1; i++) csum += 15u - ((M[i >> 3] >> (28 - 4 * (i & 7))) & 15u);
     csum <<= 4;  // (8 - (len2 * lg_w) mod 8) mod 8 = 4 for len2 = 3
     if (valid) {
+      // lanes 1..h' fetch the layer's authentication nodes for the climb
+      if (g >= 1 && g <= HP) {
+        uint32_t au[NW];
+        load_be_any<NW>(xs + (LEN + g - 1) * Q::n, al, au);
+        store_words<NW>(&s_auth[grp][(g - 1) * NW], au);
+      }
       // chain start values (the signature's WOTS+ part) into LDS, and the
       // rank of each of this lane's home chains by descending step count
       for (int c = g; c < LEN; c += G) {
         uint32_t x[NW];
-        load_be<NW>(xs + c * Q::n, x);
+        load_be_any<NW>(xs + c * Q::n, al, x);
         store_words<NW>(&vals[c * NW], x);
         const uint32_t sc = 15u - verify_digit<ID>(s_cur[grp], csum, c);
         uint32_t rank = 0;
@@ -1328,7 +1404,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
         s_order[grp][rank] = uint16_t(c);
       }
     }
-    __syncthreads();
+    wave_sync();
     if (valid) {
       // this lane's chains: ranks g, 2G - 1 - g, 2G + g, ... (snake order)
       int slot = 0;
@@ -1357,15 +1433,15 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
         st++;
       }
     }
-    __syncthreads();
+    wave_sync();
     if (valid && g == 0) {
       auto get = [&](int wi) -> uint32_t { return vals[wi]; };
       uint32_t node[NW], lr[2 * NW];
       thT<ID, LEN, V>(mid256, mid512, make_adrs(layer, tree, A_WOTS_PK, leaf, 0, 0), get, node);
       uint32_t ti = leaf;
-      for (int j = 0; j < Q::hp; j++) {
+      for (int j = 0; j < HP; j++) {
         uint32_t au[NW];
-        load_be<NW>(xs + (LEN + j) * Q::n, au);
+        load_words<NW>(&s_auth[grp][j * NW], au);
         const bool even = (ti & 1u) == 0;
 #pragma unroll
         for (int u = 0; u < NW; u++) {
@@ -1377,7 +1453,7 @@ __global__ __launch_bounds__(kVerifyThreads) void k_verify(const VerifyItem* __r
       }
       store_words<NW>(s_cur[grp], node);
     }
-    __syncthreads();
+    wave_sync();
     leaf = uint32_t(tree & ((1u << Q::hp) - 1));
     tree = Q::hp >= 64 ? 0 : (tree >> Q::hp);
   }

@@ -1,5 +1,6 @@
 // set_02.hip -- kernels and host launch code of parameter set 2 (SHA2-192f);
-// its FORS and TREE selectors compile in set_02_fors.hip and set_02_tree.hip.
+// its FORS, TREE and fused selectors compile in set_02_fors.hip,
+// set_02_tree.hip and set_02_fused.hip.
 #include "set_impl.hpp"
 
 SLH_EXTERN_SELECTORS(2)

@@ -1,5 +1,6 @@
 // set_07.hip -- kernels and host launch code of parameter set 7 (SHAKE-128f);
-// its FORS and TREE selectors compile in set_07_fors.hip and set_07_tree.hip.
+// its FORS, TREE and fused selectors compile in set_07_fors.hip,
+// set_07_tree.hip and set_07_fused.hip.
 #include "set_impl.hpp"
 
 SLH_EXTERN_SELECTORS(7)

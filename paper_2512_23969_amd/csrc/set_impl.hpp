@@ -49,26 +49,36 @@ void with_nwav(uint32_t nwav, F&& f) {
   if (nwav == 2) f(FgC<2>{}); else if (nwav == 8) f(FgC<8>{}); else f(FgC<4>{});
 }
 
-template <int ID, int FG, int LPL>
+template <typename F>
+void with_fused_waves(uint32_t nwav, F&& f) {
+  if (nwav == 2) f(FgC<2>{}); else f(FgC<4>{});
+}
+
+// Workgroups of the fused kernel variant that fit one CU (its persistent grid).
+template <int ID, int FG, int LPL, int NWAV>
 int occupancy_of() {
   static int occ = -1;
   if (occ < 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused<ID, FG, LPL>),
-                                                     kTreeThreads, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused<ID, FG, LPL, NWAV>),
+                                                     64 * NWAV, 0) != hipSuccess || nb < 1)
       nb = 1;
     occ = nb;
   }
   return occ;
 }
 template <int ID>
-int occupancy(uint32_t fg, uint32_t lpl) {
+int occupancy(uint32_t fg, uint32_t lpl, uint32_t nwav) {
   if constexpr (!whole_trees<ID>()) {
     return 1;
   } else {
     int occ = 1;
     with_fg<ID>(fg, [&](auto fgc) {
-      with_lpl(lpl, [&](auto l) { occ = occupancy_of<ID, decltype(fgc)::value, decltype(l)::value>(); });
+      with_lpl(lpl, [&](auto l) {
+        with_fused_waves(nwav, [&](auto nw) {
+          occ = occupancy_of<ID, decltype(fgc)::value, decltype(l)::value, decltype(nw)::value>();
+        });
+      });
     });
     return occ;
   }
@@ -89,6 +99,9 @@ struct Plan {
   uint32_t parts = 0;  // > 0: TREE blocks' chains split over this many workgroups (small batches)
   uint32_t fg = 8, grid = 0, ntb = 0, nfg = 0, table = 0;
   uint32_t lpl = 2, ft = kForsThreads, nwav = 4, vtree = 0, vfors = 0;  // kernel shapes and variants
+  uint32_t w0 = 0;  // fused kernel: wave 0's chunks per TREE block (0 = default)
+  uint32_t fwav = 4;  // fused kernel: waves per workgroup
+  uint32_t bpi = 1;   // fused kernel: TREE blocks per work item
   size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
   size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, o_troots = 0, o_uroots = 0, total = 0;
   static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
@@ -104,6 +117,9 @@ struct Plan {
       nwav = t.tree_waves;
       vtree = t.vtree;
       vfors = t.vfors;
+      w0 = t.fused_w0;
+      fwav = t.fused_waves;
+      bpi = t.fused_bpi;
       inorder = t.inorder != 0 && !dedup;
     }
     const size_t trees = n * Q::d;
@@ -127,16 +143,16 @@ struct Plan {
       fused = false;
     }
     if (fused) {
-      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg, lpl));
-      grid = std::min<uint32_t>(per_cu * uint32_t(cus), ntb + nfg);
+      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg, lpl, fwav));
+      grid = std::min<uint32_t>(per_cu * uint32_t(cus), (ntb + bpi - 1) / bpi + nfg);
     } else {
       grid = std::min(ntb, kMaxTreeBlocks);
     }
     o_recs = 0;
     o_items = o_recs + up(n * sizeof(WorkRec));
     o_stage = o_items + up(n * sizeof(DevItem));
-    // the fused kernel double-buffers its staging per workgroup
-    o_spill = o_stage + up(size_t(grid) * stage_per_block * (fused ? 2 : 1));
+    // the fused kernel double-buffers its staging per workgroup, bpi blocks each
+    o_spill = o_stage + up(size_t(grid) * stage_per_block * (fused ? 2 * bpi : 1));
     o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
     o_troots = o_roots + up(n * Q::k * Q::fors_units * Q::NW * 4);  // unit roots
     o_uroots = o_troots + (Q::fors_units > 1 ? up(n * Q::k * Q::NW * 4) : 0);  // tree roots
@@ -231,11 +247,24 @@ void launch_tree_sel(slh_ctx* c, const Plan<ID>& pl, bool cap, const TreeLaunch&
   }
 }
 
-template <int ID, int FG, int LPL>
-void launch_fused(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
-                  uint32_t* roots, uint32_t* queue, const DedupBufs& db, hipStream_t s) {
-  hipLaunchKernelGGL((k_fused<ID, FG, LPL>), dim3(pl.grid), dim3(kTreeThreads), 0, s, c->keys, recs, uint32_t(pl.n),
-                     sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist, db.ucount, db.lown, db.nodes);
+// The fused kernel of the plan's shape (trees per group, leaves per lane,
+// waves per workgroup); the fast sets' instantiations compile in
+// set_<id>_fused.hip.
+template <int ID>
+void launch_fused_sel(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
+                      uint32_t* roots, uint32_t* queue, const DedupBufs& db, hipStream_t s) {
+  if constexpr (whole_trees<ID>()) {
+    with_fg<ID>(pl.fg, [&](auto fgc) {
+      with_lpl(pl.lpl, [&](auto l) {
+        with_fused_waves(pl.fwav, [&](auto nw) {
+          constexpr int FG = decltype(fgc)::value, LPL = decltype(l)::value, NWAV = decltype(nw)::value;
+          hipLaunchKernelGGL((k_fused<ID, FG, LPL, NWAV>), dim3(pl.grid), dim3(64 * NWAV), 0, s, c->keys, recs,
+                             uint32_t(pl.n), sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist, db.ucount,
+                             db.lown, db.nodes, pl.w0, pl.bpi);
+        });
+      });
+    });
+  }
 }
 
 // Enqueue one chunk on stream s with working memory at `base`.  `src` is
@@ -290,12 +319,7 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, uint8_t* base, const DevItem* s
   if constexpr (whole_trees<ID>()) {
     if (pl.fused) {
       PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
-      with_fg<ID>(pl.fg, [&](auto fgc) {
-        with_lpl(pl.lpl, [&](auto l) {
-          launch_fused<ID, decltype(fgc)::value, decltype(l)::value>(c, pl, sigs, recs, stage, spill, roots, queue,
-                                                                     db, s);
-        });
-      });
+      launch_fused_sel<ID>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
     }
   }
   if (!pl.fused) {
@@ -532,19 +556,29 @@ void verify_launch(const VerifyItem* items, uint32_t count, bool wide, uint32_t 
                         &verify_launch<ID>};                                                                \
   }
 
-// The fast sets compile the FORS and TREE selectors (every kernel shape and
-// variant they launch) in translation units of their own: the set's main
-// unit declares them (SLH_EXTERN_SELECTORS, before SLH_DEFINE_SET_OPS) and
-// set_<id>_fors.hip / set_<id>_tree.hip instantiate them.
+// The fast sets compile the FORS, TREE and fused selectors (every kernel
+// shape and variant they launch) in translation units of their own: the
+// set's main unit declares them (SLH_EXTERN_SELECTORS, before
+// SLH_DEFINE_SET_OPS) and set_<id>_fors.hip / set_<id>_tree.hip /
+// set_<id>_fused.hip instantiate them.
 #define SLH_EXTERN_SELECTORS(ID)                                                                              \
   namespace slh {                                                                                           \
   extern template void launch_fors_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*,         \
                                            hipStream_t);                                                     \
   extern template void launch_tree_sel<ID>(slh_ctx*, const Plan<ID>&, bool, const TreeLaunch&, hipStream_t); \
+  extern template void launch_fused_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*,        \
+                                            uint32_t*, uint32_t*, uint32_t*, const DedupBufs&, hipStream_t); \
+  extern template int occupancy<ID>(uint32_t, uint32_t, uint32_t);                                           \
   }
 #define SLH_DEFINE_FORS_SELECTOR(ID)                                                                         \
   namespace slh {                                                                                           \
   template void launch_fors_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*, hipStream_t);  \
+  }
+#define SLH_DEFINE_FUSED_SELECTOR(ID)                                                                        \
+  namespace slh {                                                                                           \
+  template void launch_fused_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*, uint32_t*,    \
+                                     uint32_t*, uint32_t*, const DedupBufs&, hipStream_t);                   \
+  template int occupancy<ID>(uint32_t, uint32_t, uint32_t);                                                  \
   }
 #define SLH_DEFINE_TREE_SELECTOR(ID)                                                                         \
   namespace slh {                                                                                           \

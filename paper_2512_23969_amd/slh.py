@@ -45,10 +45,10 @@ class slh_tuning(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in
                 ("fors_trees_per_group", "wgs_per_cu", "keep_chains", "split_max_blocks", "fors_leaves_per_lane",
                  "fors_threads", "tree_waves", "layer_order", "variant_tree", "variant_fors", "variant_verify",
-                 "reserved")]
+                 "fused_wave0_chunks", "fused_waves", "fused_blocks_per_item")]
 
 
-TUNING_FIELDS = tuple(f for f, _ in slh_tuning._fields_ if f != "reserved")
+TUNING_FIELDS = tuple(f for f, _ in slh_tuning._fields_)
 LAYERS_PARALLEL, LAYERS_IN_ORDER = 0, 1
 VARIANT_DEFAULT, VARIANT_NO_BITOP3, VARIANT_SPLIT_ADDS = 0, 1, 2
 VARIANTS = {VARIANT_DEFAULT: "default", VARIANT_NO_BITOP3: "no-bitop3", VARIANT_SPLIT_ADDS: "split-adds"}
@@ -58,7 +58,7 @@ def make_tuning(fors_trees_per_group=0, wgs_per_cu=0, keep_chains=1, split_max_b
     """An slh_tuning from keyword knobs (the fields of slh.h; 0 = default)."""
     t = slh_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks)
     for k, v in knobs.items():
-        if k not in TUNING_FIELDS and k != "reserved":  # reserved: passed on for the library to refuse
+        if k not in TUNING_FIELDS:
             raise TypeError("unknown tuning knob %r" % k)
         setattr(t, k, int(v))
     return t

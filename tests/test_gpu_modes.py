@@ -115,7 +115,11 @@ def test_tuning_rejects_uncompiled_variants(slh):
                             ((2,), {"variant_fors": 2, "fors_leaves_per_lane": 4}),
                             ((3,), {"variant_fors": 1, "fors_threads": 512}),
                             ((7,), {"variant_tree": 1}), ((9,), {"variant_verify": 2}),
-                            ((4,), {"tree_waves": 2}), ((5,), {"layer_order": 1}), ((1,), {"reserved": 1})):
+                            ((4,), {"tree_waves": 2}), ((5,), {"layer_order": 1}), ((1,), {"fused_wave0_chunks": 1}),
+                            ((1,), {"fused_wave0_chunks": 30}), ((3,), {"fused_wave0_chunks": 62}),
+                            ((1,), {"fused_waves": 8}), ((4,), {"fused_waves": 2}),
+                            ((1,), {"fused_blocks_per_item": 3}), ((5,), {"fused_blocks_per_item": 2}),
+                            ((2,), {"fused_blocks_per_item": 2, "fused_wave0_chunks": 97})):
             with pytest.raises(slh.SlhError) as e:
                 ctx.set_tuning(*args, **knobs)
             assert e.value.code == slh.EINVAL, (args, knobs)
@@ -192,11 +196,38 @@ def test_every_kernel_shape(slh, keys, param):
         for fg in slh.FORS_GROUPS[param]:
             for sh in SHAPES:
                 for waves in (2, 4, 8):
-                    ctx.set_tuning(param, fg, 0, 1, slh.SPLIT_NEVER, tree_waves=waves, **sh)
-                    for mode in ("plain", "fused") if sh["fors_threads"] == 256 and waves == 4 else ("plain",):
+                    # the fused kernel takes tree_waves 2/4 as its workgroup size
+                    fw = {"fused_waves": waves} if waves != 8 else {}
+                    ctx.set_tuning(param, fg, 0, 1, slh.SPLIT_NEVER, tree_waves=waves, **sh, **fw)
+                    for mode in ("plain", "fused") if sh["fors_threads"] == 256 and waves != 8 else ("plain",):
                         what = "%s fg%d %s waves%d %s" % (NAMES[param], fg, sh, waves, mode)
                         print(what, flush=True)
                         got = slh.sign_messages(ctx, [param] * 6, [slot] * 6, msgs, slh.MODES[mode])
+                        _check(param, got, want, what)
+
+
+@pytest.mark.parametrize("param", [1, 2, 3, 7])
+def test_fused_wave0_share(slh, keys, param):
+    """The fused kernel with wave 0 taking fewer or more chains chunks per
+    TREE block than the default, across several persistent grids."""
+    sk = keys[param][1] if param in keys else oracle_keys(param, [workloads.key_seed(param, 20)])[0][1]
+    msgs = workloads.messages(200 + param, 40, 32)
+    want = oracle_sign_many([(param, sk, m) for m in msgs])
+    L = slh.sizes(param)["len"]
+    with slh.Context(0) as ctx:
+        slot = ctx.add_keys(param, sk)
+        for waves in (4, 2):
+            for bpi in (1, 2):
+                for w0 in (0, 2, 5, 8, 13, L // 2, L - 6, L + 3, 2 * L - 6):
+                    if w0 > bpi * L - 6:
+                        continue
+                    for wpc in (0, 1):
+                        ctx.set_tuning(param, 0, wpc, 1, slh.SPLIT_NEVER, fused_wave0_chunks=w0, fused_waves=waves,
+                                       fused_blocks_per_item=bpi)
+                        what = "%s fused waves %d bpi %d w0 %d wpc %d" % (NAMES[param], waves, bpi, w0, wpc)
+                        print(what, flush=True)
+                        got = slh.sign_messages(ctx, [param] * len(msgs), [slot] * len(msgs), msgs,
+                                                slh.MODES["fused"])
                         _check(param, got, want, what)
 
 
