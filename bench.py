@@ -25,6 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2512_23969_amd import workloads as _workloads  # noqa: E402  (numpy only)
+
 WORKLOADS = {
     "c2_128f_4096": "SPHINCS+-SHA2-128f, 1 key, 4096 x 32-byte messages, one fused persistent launch",
     "c3_192f_4096": "SPHINCS+-SHA2-192f, 1 key, 4096 x 32-byte messages, hipGraph-captured pipeline",
@@ -45,27 +47,12 @@ METRIC = "signatures/s (128f/192f/256f, batch 4096) + p50/p99 latency; % VALU pe
 # the batch-4096 workloads of the default line, each in the execution mode
 # its configuration names and in the plain per-phase path
 DEFAULT_WORKLOADS = ("c2_128f_4096", "c3_192f_4096", "c4_256f_4096x64")
-# "graph-any": the hipGraph-captured pipeline over the per-phase kernels or
-# over the fused kernel, whichever the autotuner found faster
-CONFIG_MODE = {"c2_128f_4096": "fused", "c3_192f_4096": "graph-any", "c4_256f_4096x64": "fused"}
+# the mode each batch-4096 configuration is timed in ("graph-any": the
+# hipGraph-captured pipeline over the per-phase kernels or over the fused
+# kernel, whichever the autotuner found faster)
+CONFIG_MODE = {name: c["mode"] for name, c in _workloads.CONFIGS.items() if "mode" in c}
 
 
-def resolve_mode(autotune, param, batch, mode, path=None):
-    """(mode, tuned knobs) for a requested mode: "auto" = the autotuner's
-    fastest, "graph-any" = its faster hipGraph pipeline, else the mode itself
-    with the knobs tuned for that mode (or the fastest mode's knobs)."""
-    path = path or autotune.DEFAULT_CACHE
-    if mode == "auto":
-        b = autotune.best_for(param, batch, None, path)
-        return (b or {}).get("mode", "plain"), b
-    if mode == "graph-any":
-        g = [autotune.best_for(param, batch, m, path) for m in ("graph-plain", "graph")]
-        g = [x for x in g if x]
-        if not g:
-            return "graph", autotune.best_for(param, batch, None, path)
-        b = min(g, key=lambda x: x["ms"])
-        return b["mode"], b
-    return mode, autotune.best_for(param, batch, mode, path) or autotune.best_for(param, batch, None, path)
 # HBM bytes per launch measured with rocprofv3 counters, valid while the
 # device sources hash to the value recorded with them
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_b4096.json")
@@ -269,7 +256,7 @@ def run(slh, workloads, name, steps, warmup, mode="plain", tune=False, tune_out=
         torch.cuda.synchronize()
         best, _ = autotune.tune_and_store(slh, ctx, cfg["param"], items, d_m, d_s, cfg["batch"], path, log=log,
                                           verify=verify_inputs(slh, ctx, items, d_m, d_s, cfg, kidx))
-    mode, best = resolve_mode(autotune, cfg["param"], cfg["batch"], mode, path)
+    mode, best = autotune.resolve_mode(cfg["param"], cfg["batch"], mode, path or autotune.DEFAULT_CACHE)
     if knobs:
         # explicit knobs over the tuned ones (profiling one kernel variant)
         best = dict(best or autotune.KNOB_DEFAULTS, **knobs)
@@ -737,7 +724,7 @@ def main():
         from paper_2512_23969_amd import autotune
         for name in DEFAULT_WORKLOADS:
             cfg = workloads.CONFIGS[name]
-            cmode, _ = resolve_mode(autotune, cfg["param"], cfg["batch"], CONFIG_MODE[name])
+            cmode, _ = autotune.resolve_mode(cfg["param"], cfg["batch"], CONFIG_MODE[name])
             got = {}
             # a fused graph's kernels are timed in an eager fused run beside it
             for mode in dict.fromkeys((cmode, "plain") + (("fused",) if cmode == "graph" else ())):

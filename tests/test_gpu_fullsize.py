@@ -1,9 +1,10 @@
 """Full-size parity in the launch configurations the benchmark times: each
 batch-4096 workload (128f 1 key, 192f 1 key, 256f 64 keys, and the SHAKE
-fast sets alike) and each batch-1024 small-set workload, signed in its
-autotuned mode and in the other modes (within-batch tree dedup included),
-gives identical bytes.  Every key is the oracle's, derived from its seed, and
-the GPU's key generation must give the same key for every seed used.  For
+fast sets alike) and each batch-1024 small-set workload, signed in the mode
+the benchmark times it in (with that mode's tuned knobs) and in every other
+mode (within-batch tree dedup included), gives identical bytes.  Every key
+is the oracle's, derived from its seed, and the GPU's key generation must
+give the same key for every seed used.  For
 the SHA2 fast sets (128f, 192f, 256f over 64 keys) all 4096 signatures equal
 the oracle's; for the others a sample (16 plus the first and last) does.
 Every signature of the batch verifies on the GPU (a property that holds at
@@ -48,19 +49,21 @@ def test_full_batch(slh, name):
         items, blob, total = slh.pack_batch([param] * batch, slots, msgs)
         d_m = torch.frombuffer(bytearray(blob), dtype=torch.uint8).cuda()
         outs = {}
-        tuned = autotune.lookup(param, batch)
-        if tuned:
-            autotune.apply(ctx, param, tuned["best"])
-        tuned_mode = tuned["best"]["mode"] if tuned else "plain"
-        for mode in ("plain", "fused", "graph", "dedup", "graph-dedup"):
+        # the mode and knobs the benchmark times this workload with
+        tuned_mode, knobs = autotune.resolve_mode(param, batch, cfg.get("mode", "auto"))
+        if knobs:
+            autotune.apply(ctx, param, knobs)
+        modes = ("plain", "fused", "graph-plain", "graph", "dedup", "fused-dedup", "graph-dedup")
+        assert tuned_mode in modes, tuned_mode
+        for mode in modes:
             d_s = torch.zeros(total, dtype=torch.uint8, device="cuda")
             print(name, mode, flush=True)
             ctx.sign_batch(items, d_m, d_s, mode=slh.MODES[mode])
             torch.cuda.synchronize()
             outs[mode] = d_s
-        for mode in ("fused", "graph", "dedup", "graph-dedup"):
+        for mode in modes[1:]:
             assert torch.equal(outs[mode], outs["plain"]), mode
-        # the oracle against the autotuned mode's output (the mode the benchmark times)
+        # the oracle against the output of the mode the benchmark times
         host = outs[tuned_mode].cpu().numpy().tobytes()
         sb = slh.sizes(param)["sig_bytes"]
         sig = lambda i: host[int(items[i]["sig_off"]):int(items[i]["sig_off"]) + sb]  # noqa: E731
