@@ -422,7 +422,17 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *                         (0 = 1; fast sets).  With 2 the chunks of both
  *                         blocks are dealt out together (wave 0's default
  *                         share doubles), which balances the waves more
- *                         finely; staging per workgroup doubles */
+ *                         finely; staging per workgroup doubles
+ *   fused_schedule        fused mode: SLH_FUSED_ITEMS (0 = this default):
+ *                         workgroups take items of whole TREE blocks, each
+ *                         ending at a workgroup barrier; SLH_FUSED_CHUNKS:
+ *                         workgroup g owns TREE blocks g, g + grid, ...,
+ *                         its waves take single chains chunks of them, and
+ *                         the wave that completes a block's chunks finishes
+ *                         it (no barrier per block; staging for every
+ *                         block, as in the per-phase path).  SLH_FUSED_CHUNKS
+ *                         requires fused_waves 4 and fused_blocks_per_item
+ *                         and fused_wave0_chunks 0 (fast sets) */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;
@@ -438,8 +448,11 @@ typedef struct {
     uint32_t fused_wave0_chunks;
     uint32_t fused_waves;
     uint32_t fused_blocks_per_item;
+    uint32_t fused_schedule;
 } slh_tuning;
 #define SLH_SPLIT_NEVER 0xFFFFFFFFu
+#define SLH_FUSED_ITEMS 1u
+#define SLH_FUSED_CHUNKS 2u
 #define SLH_LAYERS_PARALLEL 0u
 #define SLH_LAYERS_IN_ORDER 1u
 #define SLH_VARIANT_DEFAULT 0u

@@ -146,6 +146,23 @@ def best_for(param: int, batch: int, mode: str | None = None, path: str = DEFAUL
     return (b or {}).get("by_mode", {}).get(mode)
 
 
+def resolve_mode(param: int, batch: int, mode: str, path: str = DEFAULT_CACHE):
+    """(mode, tuned knobs) for a requested mode: "auto" = the fastest tuned
+    mode, "graph-any" = the faster of the two hipGraph pipelines, else the
+    mode itself with the knobs tuned for it (or the fastest mode's knobs)."""
+    if mode == "auto":
+        b = best_for(param, batch, None, path)
+        return (b or {}).get("mode", "plain"), b
+    if mode == "graph-any":
+        g = [best_for(param, batch, m, path) for m in ("graph-plain", "graph")]
+        g = [x for x in g if x]
+        if not g:
+            return "graph", best_for(param, batch, None, path)
+        b = min(g, key=lambda x: x["ms"])
+        return b["mode"], b
+    return mode, best_for(param, batch, mode, path) or best_for(param, batch, None, path)
+
+
 # Knobs the empirical stage searches, per parameter-set family (slh.h
 # slh_tuning): fast sets have every FORS and TREE shape and both layer
 # orders; the SHA2 fast sets also the instruction variants; the small sets
@@ -158,11 +175,12 @@ WGS_PER_CU = (0, 1, 2, 3)
 KNOB_DEFAULTS = {"fors_trees_per_group": 0, "wgs_per_cu": 0, "keep_chains": 1, "split_max_blocks": 0,
                  "fors_leaves_per_lane": 2, "fors_threads": 256, "tree_waves": 4, "layer_order": 0,
                  "variant_tree": 0, "variant_fors": 0, "variant_verify": 0, "fused_wave0_chunks": 0,
-                 "fused_waves": 4, "fused_blocks_per_item": 1}
+                 "fused_waves": 4, "fused_blocks_per_item": 1, "fused_schedule": 1}
 # default chains chunks of wave 0 in a fused TREE block, by waves per
 # workgroup and len (35 / 51 / 67)
 FUSED_W0 = {4: {35: 8, 51: 11, 67: 14}, 2: {35: 17, 51: 24, 67: 31}}
 FUSED_WAVES = (4, 2)
+FUSED_CHUNKS = 2  # fused_schedule: SLH_FUSED_CHUNKS
 
 
 def _fast(param):
@@ -309,6 +327,15 @@ def tune(slh, ctx, param: int, items, d_msgs, d_sigs, reps: int = 7, log=None, v
         w0d = FUSED_W0[fb["fused_waves"]][slh.sizes(param)["len"]] * fb["fused_blocks_per_item"]
         for w0 in (w0d - 2, w0d - 1, w0d + 1, w0d + 2):
             time_fused(dict(fb, fused_wave0_chunks=w0))
+        # the kernel scheduled per chains chunk (no barrier per item): its
+        # FORS shape, then persistent workgroups per CU and kept chains
+        chunks = [time_fused(knobs(fors_trees_per_group=fg, fors_leaves_per_lane=lpl, fused_schedule=FUSED_CHUNKS))
+                  for fg in slh.FORS_GROUPS[param] for lpl in LPLS]
+        cb = min(chunks, key=lambda r: r["ms"])
+        for wpc in WGS_PER_CU:
+            for keep in (1, 0):
+                if (wpc, keep) != (0, 1):
+                    time_fused(dict(cb, wgs_per_cu=wpc, keep_chains=keep))
         fb = min(fused, key=lambda r: r["ms"])
         if fb["ms"] < best["ms"]:
             best = fb

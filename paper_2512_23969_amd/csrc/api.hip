@@ -885,11 +885,17 @@ bool resolve_tuning(uint32_t param, const slh_tuning& t, Tuning* out, std::strin
   r.fused_bpi = t.fused_blocks_per_item ? t.fused_blocks_per_item : 1u;
   if (r.fused_bpi != 1 && r.fused_bpi != 2) return *msg = "fused_blocks_per_item must be 1 or 2", false;
   r.fused_w0 = t.fused_wave0_chunks;
+  r.fused_sched = t.fused_schedule ? t.fused_schedule : uint32_t(SLH_FUSED_ITEMS);
+  if (r.fused_sched != SLH_FUSED_ITEMS && r.fused_sched != SLH_FUSED_CHUNKS)
+    return *msg = "fused_schedule must be SLH_FUSED_ITEMS or SLH_FUSED_CHUNKS", false;
+  if (r.fused_sched == SLH_FUSED_CHUNKS && (r.fused_waves != 4 || r.fused_bpi != 1 || t.fused_wave0_chunks))
+    return *msg = "the chunk-scheduled fused kernel has four waves and no work items (fused_waves 4, "
+                  "fused_blocks_per_item and fused_wave0_chunks 0)", false;
   if (r.fused_w0 && (r.fused_w0 < 2 || r.fused_w0 > r.fused_bpi * len_of(param) - 6))
     return *msg = "fused_wave0_chunks must be 0 or 2 .. blocks per item x len - 6", false;
   if (!fast_set(param) &&
       (r.lpl != 2 || r.fors_threads != uint32_t(kForsThreads) || r.tree_waves != 4 || r.inorder || r.fused_waves != 4 ||
-       r.fused_bpi != 1))
+       r.fused_bpi != 1 || r.fused_sched != SLH_FUSED_ITEMS))
     return *msg = "the small parameter sets have the default kernel shapes and layer order only", false;
   if (!sha2_fast_set(param) && (r.vtree || r.vfors || r.vverify))
     return *msg = "instruction variants exist for the SHA2 fast sets only", false;
@@ -936,6 +942,7 @@ int slh_ctx_get_tuning(const slh_ctx* c, uint32_t param, slh_tuning* t) {
   t->fused_wave0_chunks = r.fused_w0;
   t->fused_waves = r.fused_waves;
   t->fused_blocks_per_item = r.fused_bpi;
+  t->fused_schedule = r.fused_sched;
   return SLH_OK;
 }
 

@@ -38,6 +38,7 @@ struct Tuning {
   uint32_t fused_w0 = 0;  // fused kernel: wave 0's chunks per TREE block (0 = default)
   uint32_t fused_waves = 4;  // fused kernel: waves per workgroup
   uint32_t fused_bpi = 1;    // fused kernel: TREE blocks per work item
+  uint32_t fused_sched = SLH_FUSED_ITEMS;  // fused kernel: items with barriers, or chunks per wave
 };
 
 struct GraphKey {

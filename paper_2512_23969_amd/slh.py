@@ -45,11 +45,12 @@ class slh_tuning(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint32) for f in
                 ("fors_trees_per_group", "wgs_per_cu", "keep_chains", "split_max_blocks", "fors_leaves_per_lane",
                  "fors_threads", "tree_waves", "layer_order", "variant_tree", "variant_fors", "variant_verify",
-                 "fused_wave0_chunks", "fused_waves", "fused_blocks_per_item")]
+                 "fused_wave0_chunks", "fused_waves", "fused_blocks_per_item", "fused_schedule")]
 
 
 TUNING_FIELDS = tuple(f for f, _ in slh_tuning._fields_)
 LAYERS_PARALLEL, LAYERS_IN_ORDER = 0, 1
+FUSED_ITEMS, FUSED_CHUNKS = 1, 2
 VARIANT_DEFAULT, VARIANT_NO_BITOP3, VARIANT_SPLIT_ADDS = 0, 1, 2
 VARIANTS = {VARIANT_DEFAULT: "default", VARIANT_NO_BITOP3: "no-bitop3", VARIANT_SPLIT_ADDS: "split-adds"}
 
@@ -240,9 +241,8 @@ class Context:
 
     def set_tuning(self, param: int, fors_trees_per_group: int = 0, wgs_per_cu: int = 0,
                    keep_chains: int = 1, split_max_blocks: int = 0, **knobs):
-        """Set the kernel knobs of a parameter set (slh_tuning fields as keywords:
-        fors_leaves_per_lane, fors_threads, tree_waves, layer_order,
-        variant_tree, variant_fors, variant_verify; 0 = default)."""
+        """Set the kernel knobs of a parameter set (the other slh_tuning
+        fields, TUNING_FIELDS, as keywords; 0 = default)."""
         t = make_tuning(fors_trees_per_group, wgs_per_cu, keep_chains, split_max_blocks, **knobs)
         _check(lib.slh_ctx_set_tuning(self.h, int(param), ctypes.byref(t)), self.h)
 

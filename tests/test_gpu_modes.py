@@ -119,7 +119,10 @@ def test_tuning_rejects_uncompiled_variants(slh):
                             ((1,), {"fused_wave0_chunks": 30}), ((3,), {"fused_wave0_chunks": 62}),
                             ((1,), {"fused_waves": 8}), ((4,), {"fused_waves": 2}),
                             ((1,), {"fused_blocks_per_item": 3}), ((5,), {"fused_blocks_per_item": 2}),
-                            ((2,), {"fused_blocks_per_item": 2, "fused_wave0_chunks": 97})):
+                            ((2,), {"fused_blocks_per_item": 2, "fused_wave0_chunks": 97}),
+                            ((1,), {"fused_schedule": 3}), ((1,), {"fused_schedule": 2, "fused_waves": 2}),
+                            ((2,), {"fused_schedule": 2, "fused_blocks_per_item": 2}),
+                            ((3,), {"fused_schedule": 2, "fused_wave0_chunks": 14}), ((4,), {"fused_schedule": 2})):
             with pytest.raises(slh.SlhError) as e:
                 ctx.set_tuning(*args, **knobs)
             assert e.value.code == slh.EINVAL, (args, knobs)
@@ -229,6 +232,41 @@ def test_fused_wave0_share(slh, keys, param):
                         got = slh.sign_messages(ctx, [param] * len(msgs), [slot] * len(msgs), msgs,
                                                 slh.MODES["fused"])
                         _check(param, got, want, what)
+
+
+@pytest.mark.parametrize("param", [1, 2, 3, 7, 9])
+def test_fused_chunk_schedule(slh, param):
+    """The fused kernel scheduled per chains chunk (each workgroup owns every
+    grid-th TREE block, its waves take single chunks, the wave completing a
+    block finishes it): several keys and ragged messages, batches with fewer
+    TREE blocks than workgroups and with several blocks per workgroup, kept
+    and recomputed chains, every FORS shape it is compiled for, with and
+    without dedup and graph capture."""
+    rng = np.random.default_rng([190, param])
+    ks = oracle_keys(param, [workloads.key_seed(param, 40 + i) for i in range(3)])
+    big = {1: 300, 2: 160, 3: 100, 7: 160, 9: 60}[param]
+    with slh.Context(0) as ctx:
+        first = ctx.add_keys(param, [sk for _, sk in ks])
+        for count in (9, big):
+            kidx = [int(rng.integers(0, 3)) for _ in range(count)]
+            msgs = [rng.bytes(int(rng.integers(0, 300))) for _ in range(count)]
+            want = oracle_sign_many([(param, ks[k][1], m) for k, m in zip(kidx, msgs)])
+            for fg in slh.FORS_GROUPS[param]:
+                for lpl in (2, 4):
+                    for keep in (1, 0):
+                        for wpc in (0, 1):
+                            if (fg != slh.FORS_GROUPS[param][-1] or lpl != 4) and (keep == 0 or wpc == 1):
+                                continue
+                            ctx.set_tuning(param, fg, wpc, keep, slh.SPLIT_NEVER, fors_leaves_per_lane=lpl,
+                                           fused_schedule=slh.FUSED_CHUNKS)
+                            modes = ("fused", "graph", "fused-dedup", "graph-dedup") if keep and not wpc else ("fused",)
+                            for mode in modes:
+                                what = "%s chunks n%d fg%d lpl%d keep%d wpc%d %s" % (NAMES[param], count, fg, lpl,
+                                                                                     keep, wpc, mode)
+                                print(what, flush=True)
+                                got = slh.sign_messages(ctx, [param] * count, [first + k for k in kidx], msgs,
+                                                        slh.MODES[mode])
+                                _check(param, got, want, what)
 
 
 @pytest.mark.parametrize("param", [1, 2, 3, 7, 9])

@@ -90,6 +90,24 @@ def test_two_calls_equal_sign_batch(env, mode):
         check(slh, keys, params, kidx, msgs, items, got, want, first_last(params))
 
 
+def test_chunk_scheduled_fused(env):
+    """The fused kernel scheduled per chains chunk keeps a chunk counter and
+    staging for every TREE block of a chunk of the batch; both fit the array."""
+    slh, ctx, keys, slots = env
+    try:
+        for p in SETS:
+            ctx.set_tuning(p, fused_schedule=slh.FUSED_CHUNKS)
+        for mode in ("fused", "fused-dedup"):
+            for call, spec in enumerate(([(1, 300), (2, 100), (3, 60)], [(1, 40), (3, 5)])):
+                print("no-alloc chunk-scheduled %s call %d: %s" % (mode, call, spec), flush=True)
+                params, ks, kidx, msgs = make_batch(slots, spec, 30 + 10 * call + len(mode))
+                items, got, want = sign_both(slh, ctx, params, ks, msgs, slh.MODES[mode])
+                check(slh, keys, params, kidx, msgs, items, got, want, first_last(params))
+    finally:
+        for p in SETS:
+            ctx.set_tuning(p)
+
+
 def test_several_chunks(env):
     """400 requests of 256f need about 470 MB of working memory in plain mode
     with kept chains: more than the array holds, so they run in chunks."""
