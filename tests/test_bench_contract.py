@@ -55,6 +55,21 @@ def test_roofline_of_the_plain_path_and_dedup_scaling():
     assert r["achieved"] == pytest.approx(full["achieved"] * 0.8, rel=1e-3)
 
 
+def test_roofline_of_a_graph_replay():
+    # the whole step against its FORS + TREE work
+    msgs, step = 4096, 25.0
+    res = {"cfg": {"batch": msgs}, "ms_per_step": step, "dedup": None}
+    r = bench.graph_roofline(2, res)
+    ops = (acc.ops_per_signature(2, "fors", textbook=True) + acc.ops_per_signature(2, "tree", textbook=True)) * msgs
+    assert r["achieved"] == pytest.approx(ops / (step / 1e3) / 1e12, rel=1e-3)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], abs=1e-4)
+    assert r["traffic"] is None and r["avg_launch_ms"] == pytest.approx(step)
+    # with tree dedup only the distinct trees count
+    d = bench.graph_roofline(2, dict(res, dedup=(1000, 800)))
+    dops = (acc.ops_per_signature(2, "fors", textbook=True) + 0.8 * acc.ops_per_signature(2, "tree", textbook=True)) * msgs
+    assert d["achieved"] == pytest.approx(dops / (step / 1e3) / 1e12, rel=1e-3)
+
+
 def test_phase_rooflines():
     msgs = 4096
     pr = bench.phase_rooflines(1, _res(1, {"prelude": 0.05, "fors": 1.0, "tree": 12.0, "wots": 0.13}, msgs))
@@ -107,12 +122,14 @@ def test_energy_summary_and_per_set_percentiles():
 def test_traffic_only_from_counters_on_the_current_kernels(tmp_path, monkeypatch):
     f = tmp_path / "traffic.json"
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
-    assert bench.profiled_traffic("c2_128f_4096", "k_fused") == (None, "no counter summary")
+    assert bench.profiled_traffic("c2_128f_4096", "fused", "k_fused") == (None, "no counter summary")
     import json
     f.write_text(json.dumps({"device_source_sha256": bench.device_source_hash(),
-                             "entries": {"c2_128f_4096/k_fused": {"bytes_per_launch": 123, "summary": "x.md"}}}))
-    assert bench.profiled_traffic("c2_128f_4096", "k_fused") == (123, "x.md")
-    assert bench.profiled_traffic("c3_192f_4096", "k_tree")[0] is None
+                             "entries": {"c2_128f_4096/fused/k_fused": {"bytes_per_launch": 123, "summary": "x.md"}}}))
+    assert bench.profiled_traffic("c2_128f_4096", "fused", "k_fused") == (123, "x.md")
+    # another mode runs other kernels (or the same kernel over other trees)
+    assert bench.profiled_traffic("c2_128f_4096", "fused-dedup", "k_fused")[0] is None
+    assert bench.profiled_traffic("c3_192f_4096", "plain", "k_tree")[0] is None
     f.write_text(json.dumps({"device_source_sha256": "0" * 64,
-                             "entries": {"c2_128f_4096/k_fused": {"bytes_per_launch": 123}}}))
-    assert bench.profiled_traffic("c2_128f_4096", "k_fused")[0] is None
+                             "entries": {"c2_128f_4096/fused/k_fused": {"bytes_per_launch": 123}}}))
+    assert bench.profiled_traffic("c2_128f_4096", "fused", "k_fused")[0] is None
