@@ -432,7 +432,10 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *                         it (no barrier per block; staging for every
  *                         block, as in the per-phase path).  SLH_FUSED_CHUNKS
  *                         requires fused_waves 4 and fused_blocks_per_item
- *                         and fused_wave0_chunks 0 (fast sets) */
+ *                         and fused_wave0_chunks 0 (fast sets).  Its default
+ *                         grid is what fits the CUs at once; a wgs_per_cu
+ *                         above that leaves workgroups waiting to start with
+ *                         their owned blocks (slower, same bytes) */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;

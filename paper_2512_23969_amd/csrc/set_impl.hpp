@@ -54,30 +54,35 @@ void with_fused_waves(uint32_t nwav, F&& f) {
   if (nwav == 2) f(FgC<2>{}); else f(FgC<4>{});
 }
 
-// Workgroups of the fused kernel variant that fit one CU (its persistent grid).
-template <int ID, int FG, int LPL, int NWAV>
+// Workgroups of the fused kernel variant that fit one CU (its persistent
+// grid): the item kernel of NWAV waves, or with CHUNKS the chunk-scheduled
+// kernel (four waves), whose owned blocks must all be resident at once.
+template <int ID, int FG, int LPL, int NWAV, bool CHUNKS>
 int occupancy_of() {
   static int occ = -1;
   if (occ < 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_fused<ID, FG, LPL, NWAV>),
-                                                     64 * NWAV, 0) != hipSuccess || nb < 1)
-      nb = 1;
+    const void* k = CHUNKS ? reinterpret_cast<const void*>(&k_fused_chunks<ID, FG, LPL>)
+                           : reinterpret_cast<const void*>(&k_fused<ID, FG, LPL, NWAV>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * NWAV, 0) != hipSuccess || nb < 1) nb = 1;
     occ = nb;
   }
   return occ;
 }
 template <int ID>
-int occupancy(uint32_t fg, uint32_t lpl, uint32_t nwav) {
+int occupancy(uint32_t fg, uint32_t lpl, uint32_t nwav, bool chunks) {
   if constexpr (!whole_trees<ID>()) {
     return 1;
   } else {
     int occ = 1;
     with_fg<ID>(fg, [&](auto fgc) {
       with_lpl(lpl, [&](auto l) {
-        with_fused_waves(nwav, [&](auto nw) {
-          occ = occupancy_of<ID, decltype(fgc)::value, decltype(l)::value, decltype(nw)::value>();
-        });
+        constexpr int FG = decltype(fgc)::value, LPL = decltype(l)::value;
+        if (chunks) {
+          occ = occupancy_of<ID, FG, LPL, 4, true>();
+          return;
+        }
+        with_fused_waves(nwav, [&](auto nw) { occ = occupancy_of<ID, FG, LPL, decltype(nw)::value, false>(); });
       });
     });
     return occ;
@@ -146,9 +151,7 @@ struct Plan {
     }
     fchunks = fchunks && fused;
     if (fused) {
-      // the per-chunk kernel has the launch bounds and LDS of the four-wave
-      // item kernel
-      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg, lpl, fchunks ? 4u : fwav));
+      const uint32_t per_cu = t.wgs_per_cu ? t.wgs_per_cu : uint32_t(occupancy<ID>(fg, lpl, fwav, fchunks));
       grid = std::min<uint32_t>(per_cu * uint32_t(cus), fchunks ? ntb + nfg : (ntb + bpi - 1) / bpi + nfg);
     } else {
       grid = std::min(ntb, kMaxTreeBlocks);
@@ -585,7 +588,7 @@ void verify_launch(const VerifyItem* items, uint32_t count, bool wide, uint32_t 
   extern template void launch_fused_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*,        \
                                             uint32_t*, uint32_t*, uint32_t*, uint32_t*, const DedupBufs&,    \
                                             hipStream_t);                                                     \
-  extern template int occupancy<ID>(uint32_t, uint32_t, uint32_t);                                           \
+  extern template int occupancy<ID>(uint32_t, uint32_t, uint32_t, bool);                                     \
   }
 #define SLH_DEFINE_FORS_SELECTOR(ID)                                                                         \
   namespace slh {                                                                                           \
@@ -595,7 +598,7 @@ void verify_launch(const VerifyItem* items, uint32_t count, bool wide, uint32_t 
   namespace slh {                                                                                           \
   template void launch_fused_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*, uint32_t*,    \
                                      uint32_t*, uint32_t*, uint32_t*, const DedupBufs&, hipStream_t);        \
-  template int occupancy<ID>(uint32_t, uint32_t, uint32_t);                                                  \
+  template int occupancy<ID>(uint32_t, uint32_t, uint32_t, bool);                                            \
   }
 #define SLH_DEFINE_TREE_SELECTOR(ID)                                                                         \
   namespace slh {                                                                                           \
