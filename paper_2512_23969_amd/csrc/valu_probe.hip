@@ -16,6 +16,12 @@
 //     v_bitop3, SHA-256 with v_add_u32 pairs instead of v_add3_u32, SHA-512
 //     with carry pairs instead of v_lshl_add_u64, Keccak-f with theta's
 //     one-bit rotate built from dual-rate operations instead of v_alignbit.
+//   - occupancy probes: the SHA-256 compression with one or two independent
+//     states per lane at 1, 2 and 3 waves per SIMD (256, 512 and 768
+//     workgroups of 256 lanes), and SHA-512 and Keccak-f at one wave per
+//     SIMD, to see what issue rate a wave sustains with few or no other
+//     waves beside it (the verification kernel's situation at batch 4096:
+//     one wave per SIMD).
 // Prints one JSON line per probe.
 #include <hip/hip_runtime.h>
 
@@ -86,6 +92,30 @@ __global__ __launch_bounds__(kThreads) void k_sha256(uint32_t* out, int iters, u
     }
   }
   out[blockIdx.x * kThreads + threadIdx.x] = st[0][0] ^ st[1][3];
+}
+
+// Occupancy probes: S independent SHA-256 states per lane.
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_sha256_states(uint32_t* out, int iters, uint32_t seed) {
+  uint32_t st[S][8], w[16];
+#pragma unroll
+  for (int s = 0; s < S; s++) {
+    slh::sha256_iv(st[s]);
+#pragma unroll
+    for (int j = 0; j < 8; j++) st[s][j] ^= (seed + threadIdx.x + 977u * blockIdx.x) * (2u * j + 1u + 16u * s);
+  }
+  for (int i = 0; i < iters; i++) {
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+#pragma unroll
+      for (int j = 0; j < 16; j++) w[j] = st[s][j & 7] + uint32_t(j) + blockIdx.x;
+      slh::sha256_compress(st[s], w);
+    }
+  }
+  uint32_t r = 0;
+#pragma unroll
+  for (int s = 0; s < S; s++) r ^= st[s][s & 7];
+  out[blockIdx.x * kThreads + threadIdx.x] = r;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sha512(uint32_t* out, int iters, uint32_t seed) {
@@ -299,16 +329,19 @@ __global__ __launch_bounds__(kThreads) void k_keccak_fast_theta(uint32_t* out, i
   out[blockIdx.x * kThreads + threadIdx.x] = s[0].lo ^ s[7].hi;
 }
 
+// `blocks` workgroups of kThreads lanes (at most kBlocks: `d` holds one word
+// per lane of kBlocks workgroups).
 template <typename K>
-int time_kernel(K kernel, uint32_t* d, int iters, float* ms) {
+int time_kernel(K kernel, uint32_t* d, int iters, float* ms, int blocks = kBlocks) {
+  if (blocks < 1 || blocks > kBlocks) return 1;
   hipEvent_t e0, e1;
   PCHK(hipEventCreate(&e0));
   PCHK(hipEventCreate(&e1));
-  hipLaunchKernelGGL(kernel, dim3(kBlocks), dim3(kThreads), 0, 0, d, 4, 1u);  // warm-up
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), 0, 0, d, 4, 1u);  // warm-up
   PCHK(hipGetLastError());
   PCHK(hipDeviceSynchronize());
   PCHK(hipEventRecord(e0));
-  hipLaunchKernelGGL(kernel, dim3(kBlocks), dim3(kThreads), 0, 0, d, iters, 2u);
+  hipLaunchKernelGGL(kernel, dim3(blocks), dim3(kThreads), 0, 0, d, iters, 2u);
   PCHK(hipEventRecord(e1));
   PCHK(hipEventSynchronize(e1));
   PCHK(hipEventElapsedTime(ms, e0, e1));
@@ -340,6 +373,18 @@ int run_unit(const char* name, K kernel, int per_iter, int iters, uint32_t* d) {
   return 0;
 }
 
+template <typename K>
+int run_occupancy(const char* name, K kernel, int states, int blocks, int iters, uint32_t* d) {
+  float ms = 0;
+  if (time_kernel(kernel, d, iters, &ms, blocks)) return 1;
+  const double units = double(blocks) * kThreads * iters * states;
+  std::printf("{\"probe\": \"occupancy\", \"name\": \"%s\", \"waves_per_simd\": %d, \"states_per_lane\": %d, "
+              "\"ms\": %.4f, \"units\": %.6e, \"units_per_s\": %.6e}\n",
+              name, blocks / 256, states, ms, units, units / (ms * 1e-3));
+  std::fflush(stdout);
+  return 0;
+}
+
 }  // namespace
 
 int main() {
@@ -355,7 +400,15 @@ int main() {
       run_unit("variant sha256 bfi/xor", k_sha256_variant<0, 1>, 2, 400, d) ||
       run_unit("variant sha256 reference", k_sha256_variant<0, 0>, 2, 400, d) ||
       run_unit("variant sha512 carry pairs", k_sha512_carry, 1, 150, d) ||
-      run_unit("variant keccak theta dual-rate", k_keccak_fast_theta, 1, 150, d))
+      run_unit("variant keccak theta dual-rate", k_keccak_fast_theta, 1, 150, d) ||
+      run_occupancy("sha256 1 state", k_sha256_states<1>, 1, 256, 2000, d) ||
+      run_occupancy("sha256 1 state", k_sha256_states<1>, 1, 512, 2000, d) ||
+      run_occupancy("sha256 1 state", k_sha256_states<1>, 1, 768, 2000, d) ||
+      run_occupancy("sha256 2 states", k_sha256_states<2>, 2, 256, 1000, d) ||
+      run_occupancy("sha256 2 states", k_sha256_states<2>, 2, 512, 1000, d) ||
+      run_occupancy("sha256 1 state", k_sha256_states<1>, 1, 2048, 400, d) ||
+      run_occupancy("sha512 1 state", k_sha512, 1, 256, 1000, d) ||
+      run_occupancy("keccak 1 state", k_keccak, 1, 256, 1000, d))
     return 1;
   PCHK(hipFree(d));
   return 0;
