@@ -38,7 +38,10 @@ def _mix(n, seed=9):
     return [p for p, _, _ in reqs], [k for _, k, _ in reqs], [m for _, _, m in reqs]
 
 
-def test_replay_equals_alone_and_oracle(slh, keyset):
+@pytest.mark.parametrize("schedule", ["default", "chunks"])
+def test_replay_equals_alone_and_oracle(slh, keyset, schedule):
+    """`chunks`: the server's fused batches run the chunk-scheduled kernel
+    (never the split small-batch path), with several lanes in flight."""
     n = 600
     params, kidx, msgs = _mix(n)
     with slh.Server(0, lanes=3, max_batch=128, max_wait_us=500) as srv, slh.Context(0) as ctx:
@@ -46,6 +49,8 @@ def test_replay_equals_alone_and_oracle(slh, keyset):
         for p in (1, 2, 3):
             slots[p] = srv.add_keys(p, [sk for _, sk in keyset[p]])
             assert ctx.add_keys(p, [sk for _, sk in keyset[p]]) == slots[p]
+            if schedule == "chunks":
+                srv.set_tuning(p, split_max_blocks=slh.SPLIT_NEVER, fused_schedule=slh.FUSED_CHUNKS)
         ks = [slots[p] + k for p, k in zip(params, kidx)]
         # arrivals at ~ 4x a 128-batch every few ms: batches overlap
         arr = np.cumsum(np.random.default_rng(3).exponential(2e-5, size=n))
