@@ -52,3 +52,46 @@ def test_cache_key_buckets():
     assert at.cache_key("gfx950", 1, 4096) == "gfx950/1/4096"
     assert at.cache_key("gfx950", 2, 3000) == "gfx950/2/4096"
     assert at.cache_key("gfx950", 3, 1) == "gfx950/3/1"
+
+
+def _table(tmp_path, monkeypatch):
+    monkeypatch.setattr(at, "_arch", lambda: "gfx950")
+    best = {"mode": "graph-plain", "ms": 13.9, "fors_trees_per_group": 16,
+            "by_mode": {"plain": {"mode": "plain", "ms": 14.0, "fors_trees_per_group": 16},
+                        "fused": {"mode": "fused", "ms": 14.1, "fors_trees_per_group": 8, "fused_schedule": 2},
+                        "graph": {"mode": "graph", "ms": 14.05, "fors_trees_per_group": 8},
+                        "graph-plain": {"mode": "graph-plain", "ms": 13.9, "fors_trees_per_group": 16}}}
+    f = tmp_path / "tuning.json"
+    f.write_text(json.dumps({"gfx950/1/4096": {"best": best}}))
+    return str(f)
+
+
+def test_resolve_mode(tmp_path, monkeypatch):
+    """The benchmark's modes: a named mode takes that mode's tuned knobs,
+    "auto" the fastest mode, "graph-any" the faster hipGraph pipeline; an
+    untuned (set, batch) falls back to the defaults."""
+    path = _table(tmp_path, monkeypatch)
+    mode, k = at.resolve_mode(1, 4096, "fused", path)
+    assert mode == "fused" and k["fors_trees_per_group"] == 8 and k["fused_schedule"] == 2
+    assert at.resolve_mode(1, 4096, "auto", path)[0] == "graph-plain"
+    mode, k = at.resolve_mode(1, 3000, "graph-any", path)  # the 4096 bucket
+    assert mode == "graph-plain" and k["ms"] == 13.9
+    assert at.resolve_mode(2, 4096, "auto", path) == ("plain", None)
+    assert at.resolve_mode(2, 4096, "graph-any", path) == ("graph", None)
+
+
+def test_apply_sets_every_knob(tmp_path, monkeypatch):
+    """apply() passes every slh_tuning knob, tuned or default, to the context."""
+    path = _table(tmp_path, monkeypatch)
+    got = {}
+
+    class Ctx:
+        def set_tuning(self, param, **knobs):
+            got.update(knobs, param=param)
+
+    _, k = at.resolve_mode(1, 4096, "fused", path)
+    assert at.apply(Ctx(), 1, k) == "fused"
+    assert set(got) == set(at.KNOB_DEFAULTS) | {"param"}
+    assert got["fors_trees_per_group"] == 8 and got["fused_schedule"] == 2 and got["keep_chains"] == 1
+    from paper_2512_23969_amd import slh
+    assert set(at.KNOB_DEFAULTS) == set(slh.TUNING_FIELDS)
