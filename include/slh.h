@@ -424,18 +424,16 @@ int slh_verify_batch_ext(slh_ctx *ctx, const slh_verify_item_ext *items, uint32_
  *                         share doubles), which balances the waves more
  *                         finely; staging per workgroup doubles
  *   fused_schedule        fused mode: SLH_FUSED_ITEMS (0 = this default):
- *                         workgroups take items of whole TREE blocks, each
- *                         ending at a workgroup barrier; SLH_FUSED_CHUNKS:
- *                         workgroup g owns TREE blocks g, g + grid, ...,
- *                         its waves take single chains chunks of them, and
- *                         the wave that completes a block's chunks finishes
- *                         it (no barrier per block; staging for every
- *                         block, as in the per-phase path).  SLH_FUSED_CHUNKS
+ *                         workgroups take items of whole TREE blocks, whose
+ *                         chains chunks are dealt to the waves by a fixed
+ *                         share; SLH_FUSED_CHUNKS: workgroups take one TREE
+ *                         block at a time and its waves take its chains
+ *                         chunks one at a time, so slower waves and slower
+ *                         workgroups (the SIMD serves older waves first)
+ *                         take less; a rotating wave finishes each block
+ *                         while the others start the next.  SLH_FUSED_CHUNKS
  *                         requires fused_waves 4 and fused_blocks_per_item
- *                         and fused_wave0_chunks 0 (fast sets).  Its default
- *                         grid is what fits the CUs at once; a wgs_per_cu
- *                         above that leaves workgroups waiting to start with
- *                         their owned blocks (slower, same bytes) */
+ *                         and fused_wave0_chunks 0 (fast sets) */
 typedef struct {
     uint32_t fors_trees_per_group;
     uint32_t wgs_per_cu;

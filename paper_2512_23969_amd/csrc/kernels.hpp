@@ -274,15 +274,13 @@ __device__ void split_digest(const uint32_t digest[16], uint16_t* indices, uint6
 template <int ID>
 __global__ __launch_bounds__(64) void k_prelude(const DevKey* __restrict__ keys, const DevItem* __restrict__ items,
                           uint32_t count, const uint8_t* __restrict__ msgs, uint8_t* sigs,
-                          WorkRec* __restrict__ recs, uint32_t* queue, uint32_t* bdone, uint32_t nbdone) {
+                          WorkRec* __restrict__ recs, uint32_t* queue) {
   constexpr int NW = P<ID>::NW;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0 && queue) {
     queue[0] = 0u;  // work counter of the fused kernel of this batch
-    queue[2] = 0u;  // its TREE block counter (scheduled per chunk)
+    queue[2] = 0u;  // its TREE block counter (chunk-scheduled kernel)
   }
-  // chunk counters of the TREE blocks (fused kernel scheduled per chunk)
-  for (uint32_t j = i; j < nbdone; j += gridDim.x * blockDim.x) bdone[j] = 0u;
   if (i >= count) return;
   const DevItem it = items[i];
   const DevKey& K = keys[it.key_slot];
@@ -976,53 +974,57 @@ __global__ __launch_bounds__(64 * NWAV, FusedOcc<ID>::waves) void k_fused(
   if (pend != 0xffffffffu && w0) finish(pend, st0 + (cur ^ 1) * bpi * SW);
 }
 
-// The fused kernel without a barrier per work item: TREE chunks are
-// scheduled per wave.  Workgroup g owns TREE blocks g, g + G, g + 2G, ...
-// (G = gridDim.x; all but about one round of the blocks), each with staging
-// of its own, and its four waves take the chains chunks of those blocks one
-// at a time from a counter in LDS (chunk i is chunk i mod len of the
-// workgroup's block i / len).  A wave that has written a chunk's chain ends
-// counts the chunk in its block's counter (bdone, zeroed by k_prelude of the
-// same batch); the wave that counts the last chunk finishes the block (T_len
-// and the XMSS levels) and then takes chunks again.  Every wave is therefore
-// busy until its workgroup runs out of chunks, whichever wave is slow, and a
-// finish costs one wave its time instead of the whole item.  Writer and
-// finisher are waves of the same workgroup, so workgroup-scope ordering
-// makes the chain ends visible.  The remaining blocks are then taken one per
-// workgroup from a device counter (queue[2]), with a barrier between them,
-// and the FORS groups after them (queue[0]).
+// The fused kernel scheduled per chains chunk.  Workgroups take TREE blocks
+// one at a time from a device counter (queue[2]); inside a block the four
+// waves take its chains chunks one at a time from a counter in LDS, so a
+// wave that is slower (it finished the previous block, or shares its SIMD
+// with older waves, which the SIMD's arbiter serves first) simply takes
+// fewer, and workgroups that run slower take fewer blocks.  A barrier ends
+// each block; after it, one wave (rotating with the block) finishes that
+// block (T_len and the XMSS levels) from its half of the workgroup's
+// double-buffered staging while the other waves start the next block's
+// chunks.  The FORS groups follow from the device counter queue[0].
 template <int ID, int FG, int LPL = 2>
 __global__ __launch_bounds__(256, FusedOcc<ID>::waves) void k_fused_chunks(
     const DevKey* __restrict__ keys, WorkRec* __restrict__ recs, uint32_t nmsg, uint8_t* sigs,
     uint32_t* __restrict__ stage, uint32_t* __restrict__ spill, uint32_t* __restrict__ roots, uint32_t* queue,
     uint32_t ntb, uint32_t nfg, const uint32_t* ulist, const uint32_t* ucount, const uint32_t* lown,
-    uint32_t* nodes, uint32_t* bdone) {
+    uint32_t* nodes) {
   using Q = P<ID>;
   constexpr uint32_t LEN = Q::len;
-  constexpr size_t SW = size_t(LEN) * kLeavesPerBlock * Q::NW;  // words of one block's staging
-  __shared__ uint32_t node[FG * ForsLeaves<ID, LPL>::BASE * Q::NW];
+  constexpr int NW = Q::NW, LV = Q::leaves;
+  constexpr size_t SW = size_t(LEN) * kLeavesPerBlock * NW;  // words of one block's staging
+  __shared__ uint32_t node[FG * ForsLeaves<ID, LPL>::BASE * NW];
   __shared__ uint32_t next, item;
   const TreeList tl{ulist, ucount, lown, 0u};
   const uint32_t ntrees = nmsg * Q::d;
   constexpr uint32_t TPB = kLeavesPerBlock / Q::leaves;
   if (ucount) ntb = (*ucount + TPB - 1) / TPB;  // TREE blocks over the distinct trees only
-  uint32_t* bq = queue + 2;                      // counter of the blocks taken one at a time
-  constexpr int NW = Q::NW, LV = Q::leaves;
-  const uint32_t g = blockIdx.x, G = gridDim.x;
-  const int lane = int(threadIdx.x & 63);
+  const int lane = int(threadIdx.x & 63), wave = int(threadIdx.x >> 6);
+  uint32_t* st0 = stage + size_t(blockIdx.x) * 2 * SW;
   auto take = [&]() -> uint32_t {
     uint32_t v = 0;
     if (lane == 0) v = atomicAdd(&next, 1u);
     return __shfl(v, 0, 64);
   };
-  // The chunks [0, total) of the workgroup's current block list (position
-  // p = chunk / len is TREE block blk(p)), taken one at a time by the waves.
-  auto run = [&](uint32_t total, auto blk) {
+  uint32_t prev = 0xffffffffu;  // the block finished after the next barrier
+  uint32_t cur = 0;             // staging half of the next block
+  for (;;) {
+    if (threadIdx.x == 0) {
+      item = atomicAdd(queue + 2, 1u);
+      next = 0u;
+    }
+    __syncthreads();  // the new block is known, and every chunk of the previous one is written
+    const uint32_t b = item;
+    if (prev != 0xffffffffu && wave == int(prev & 3u))
+      tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st0 + (cur ^ 1u) * SW, spill, 0u, nullptr, prev, tl,
+                                  nodes);
+    if (b >= ntb) break;
+    uint32_t* st = st0 + cur * SW;
     uint32_t i = take();
-    while (i < total) {
-      // the lane's leaf of block b and its chain inputs, kept while the
-      // wave takes consecutive chunks of the same block
-      const uint32_t b = blk(i / LEN);
+    if (i < LEN) {
+      // the lane's leaf of block b and its chain inputs, kept over this
+      // wave's chunks of the block
       const uint32_t lt = uint32_t(lane) / LV, kp = uint32_t(lane) % LV;
       const bool valid = b * TPB + lt < tl.count(ntrees);
       const uint32_t ft = valid ? tl.at(b * TPB + lt) : 0u;
@@ -1037,51 +1039,18 @@ __global__ __launch_bounds__(256, FusedOcc<ID>::waves) void k_fused_chunks(
       } else if (J.spill && int32_t(kp) == J.sign_leaf) {
         keep = J.spill;
       }
-      uint32_t* st = stage + size_t(b) * SW;
-      bool fin = false;
-      for (;;) {
-        const uint32_t c = i % LEN;
+      do {
         if (valid) {
           uint32_t x[NW];
-          wots_chain<ID>(mid, sks, J.layer, J.tree, kp, c, keep ? keep + c * 16 * NW : nullptr, x);
-          store_words<NW>(st + (c * kLeavesPerBlock + lane) * NW, x);
+          wots_chain<ID>(mid, sks, J.layer, J.tree, kp, i, keep ? keep + i * 16 * NW : nullptr, x);
+          store_words<NW>(st + (i * kLeavesPerBlock + lane) * NW, x);
         }
-        // this wave's chain-end stores are complete before the chunk is counted
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        uint32_t done = 0;
-        if (lane == 0) done = __hip_atomic_fetch_add(&bdone[b], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        done = __shfl(done, 0, 64);
         i = take();
-        if (done == LEN - 1) {  // every chunk of block b is counted
-          fin = true;
-          break;
-        }
-        if (i >= total || blk(i / LEN) != b) break;
-      }
-      if (fin) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        tree_finish<ID, kSignTrees>(keys, recs, ntrees, sigs, st, spill, 0u, nullptr, b, tl, nodes);
-      }
+      } while (i < LEN);
     }
-  };
-  // Owned blocks: all but about one round of the TREE blocks, the same
-  // number for every workgroup (blocks g, g + G, ...).
-  const uint32_t owned = ntb / G > 1 ? ntb / G - 1 : 0u;
-  if (threadIdx.x == 0) next = 0u;
-  __syncthreads();
-  run(owned * LEN, [&](uint32_t p) { return g + p * G; });
-  // The rest, one block at a time from the device counter bq, so that
-  // workgroups that were slower with their owned blocks take fewer.
-  for (;;) {
-    __syncthreads();  // the waves are done with the previous block list
-    if (threadIdx.x == 0) {
-      item = owned * G + atomicAdd(bq, 1u);
-      next = 0u;
-    }
-    __syncthreads();
-    const uint32_t b = item;
-    if (b >= ntb) break;
-    run(LEN, [&](uint32_t) { return b; });
+    prev = b;
+    cur ^= 1u;
+    __syncthreads();  // every chunk of b is written; everyone holds b before item changes
   }
   __syncthreads();
   for (;;) {

@@ -56,7 +56,7 @@ void with_fused_waves(uint32_t nwav, F&& f) {
 
 // Workgroups of the fused kernel variant that fit one CU (its persistent
 // grid): the item kernel of NWAV waves, or with CHUNKS the chunk-scheduled
-// kernel (four waves), whose owned blocks must all be resident at once.
+// kernel (four waves).
 template <int ID, int FG, int LPL, int NWAV, bool CHUNKS>
 int occupancy_of() {
   static int occ = -1;
@@ -108,7 +108,7 @@ struct Plan {
   uint32_t fwav = 4;  // fused kernel: waves per workgroup
   uint32_t bpi = 1;   // fused kernel: TREE blocks per work item
   bool fchunks = false;  // fused kernel scheduled per chains chunk (k_fused_chunks)
-  size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0, o_bdone = 0;
+  size_t o_recs = 0, o_items = 0, o_stage = 0, o_spill = 0, o_roots = 0, o_queue = 0;
   size_t o_table = 0, o_rep = 0, o_ulist = 0, o_lown = 0, o_nodes = 0, o_troots = 0, o_uroots = 0, total = 0;
   static constexpr size_t stage_per_block = size_t(Q::len) * kLeavesPerBlock * Q::NW * 4;
   Plan(size_t n_, uint32_t mode, const Tuning& t, int cus)
@@ -159,10 +159,9 @@ struct Plan {
     o_recs = 0;
     o_items = o_recs + up(n * sizeof(WorkRec));
     o_stage = o_items + up(n * sizeof(DevItem));
-    // the item-scheduled fused kernel double-buffers its staging per
-    // workgroup, bpi blocks each; the chunk-scheduled one stages every block
-    o_spill = o_stage + up(fchunks ? size_t(ntb) * stage_per_block
-                                   : size_t(grid) * stage_per_block * (fused ? 2 * bpi : 1));
+    // the fused kernels double-buffer their staging per workgroup, bpi
+    // blocks each (the chunk-scheduled one works on one block at a time)
+    o_spill = o_stage + up(size_t(grid) * stage_per_block * (fused ? 2 * (fchunks ? 1 : bpi) : 1));
     o_roots = o_spill + (keep ? up(n * Q::d * Q::len * 16 * Q::NW * 4) : 0);
     o_troots = o_roots + up(n * Q::k * Q::fors_units * Q::NW * 4);  // unit roots
     o_uroots = o_troots + (Q::fors_units > 1 ? up(n * Q::k * Q::NW * 4) : 0);  // tree roots
@@ -170,8 +169,7 @@ struct Plan {
     // dedup: hash table (>= 2 slots per tree), representative per tree, list
     // of representatives (its count is the word after the work counter), the
     // owner of every leaf of every tree, and every node of every tree
-    o_bdone = o_queue + kAlign;
-    o_table = o_bdone + (fchunks ? up(size_t(ntb) * 4) : 0);  // chunk counter of every TREE block
+    o_table = o_queue + kAlign;
     if (dedup) {
       table = 2;
       while (table < 2 * trees) table <<= 1;
@@ -263,7 +261,7 @@ void launch_tree_sel(slh_ctx* c, const Plan<ID>& pl, bool cap, const TreeLaunch&
 // set_<id>_fused.hip.
 template <int ID>
 void launch_fused_sel(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* recs, uint32_t* stage, uint32_t* spill,
-                      uint32_t* roots, uint32_t* queue, uint32_t* bdone, const DedupBufs& db, hipStream_t s) {
+                      uint32_t* roots, uint32_t* queue, const DedupBufs& db, hipStream_t s) {
   if constexpr (whole_trees<ID>()) {
     with_fg<ID>(pl.fg, [&](auto fgc) {
       with_lpl(pl.lpl, [&](auto l) {
@@ -273,7 +271,7 @@ void launch_fused_sel(slh_ctx* c, const Plan<ID>& pl, uint8_t* sigs, WorkRec* re
             if constexpr (NWAV == 4)
               hipLaunchKernelGGL((k_fused_chunks<ID, FG, LPL>), dim3(pl.grid), dim3(256), 0, s, c->keys, recs,
                                  uint32_t(pl.n), sigs, stage, spill, roots, queue, pl.ntb, pl.nfg, db.ulist,
-                                 db.ucount, db.lown, db.nodes, bdone);
+                                 db.ucount, db.lown, db.nodes);
             return;
           }
           hipLaunchKernelGGL((k_fused<ID, FG, LPL, NWAV>), dim3(pl.grid), dim3(64 * NWAV), 0, s, c->keys, recs,
@@ -302,7 +300,6 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, uint8_t* base, const DevItem* s
   uint32_t* spill = pl.keep ? reinterpret_cast<uint32_t*>(base + pl.o_spill) : nullptr;
   uint32_t* roots = reinterpret_cast<uint32_t*>(base + pl.o_roots);
   uint32_t* queue = reinterpret_cast<uint32_t*>(base + pl.o_queue);
-  uint32_t* bdone = pl.fchunks ? reinterpret_cast<uint32_t*>(base + pl.o_bdone) : nullptr;
   DedupBufs db;
   if (pl.dedup) {
     db.table = reinterpret_cast<DedupSlot*>(base + pl.o_table);
@@ -319,7 +316,7 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, uint8_t* base, const DevItem* s
   {
     PhaseTimer t(c, s, SLH_PHASE_PRELUDE, n, timing);
     hipLaunchKernelGGL((k_prelude<ID>), dim3((n + 63) / 64), dim3(64), 0, s, c->keys, items, n, msgs, sigs, recs,
-                       pl.fused ? queue : nullptr, bdone, pl.fchunks ? pl.ntb : 0u);
+                       pl.fused ? queue : nullptr);
     if constexpr (whole_trees<ID>()) {
       if (pl.dedup) {
       const uint32_t nlown = trees * Q::leaves;
@@ -338,7 +335,7 @@ int launch_chunk(slh_ctx* c, const Plan<ID>& pl, uint8_t* base, const DevItem* s
   if constexpr (whole_trees<ID>()) {
     if (pl.fused) {
       PhaseTimer t(c, s, SLH_PHASE_FUSED, n, timing);
-      launch_fused_sel<ID>(c, pl, sigs, recs, stage, spill, roots, queue, bdone, db, s);
+      launch_fused_sel<ID>(c, pl, sigs, recs, stage, spill, roots, queue, db, s);
     }
   }
   if (!pl.fused) {
@@ -586,8 +583,7 @@ void verify_launch(const VerifyItem* items, uint32_t count, bool wide, uint32_t 
                                            hipStream_t);                                                     \
   extern template void launch_tree_sel<ID>(slh_ctx*, const Plan<ID>&, bool, const TreeLaunch&, hipStream_t); \
   extern template void launch_fused_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*,        \
-                                            uint32_t*, uint32_t*, uint32_t*, uint32_t*, const DedupBufs&,    \
-                                            hipStream_t);                                                     \
+                                            uint32_t*, uint32_t*, uint32_t*, const DedupBufs&, hipStream_t); \
   extern template int occupancy<ID>(uint32_t, uint32_t, uint32_t, bool);                                     \
   }
 #define SLH_DEFINE_FORS_SELECTOR(ID)                                                                         \
@@ -597,7 +593,7 @@ void verify_launch(const VerifyItem* items, uint32_t count, bool wide, uint32_t 
 #define SLH_DEFINE_FUSED_SELECTOR(ID)                                                                        \
   namespace slh {                                                                                           \
   template void launch_fused_sel<ID>(slh_ctx*, const Plan<ID>&, uint8_t*, WorkRec*, uint32_t*, uint32_t*,    \
-                                     uint32_t*, uint32_t*, uint32_t*, const DedupBufs&, hipStream_t);        \
+                                     uint32_t*, uint32_t*, const DedupBufs&, hipStream_t);                   \
   template int occupancy<ID>(uint32_t, uint32_t, uint32_t, bool);                                            \
   }
 #define SLH_DEFINE_TREE_SELECTOR(ID)                                                                         \

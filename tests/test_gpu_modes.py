@@ -236,12 +236,12 @@ def test_fused_wave0_share(slh, keys, param):
 
 @pytest.mark.parametrize("param", [1, 2, 3, 7, 9])
 def test_fused_chunk_schedule(slh, param):
-    """The fused kernel scheduled per chains chunk (each workgroup owns every
-    grid-th TREE block, its waves take single chunks, the wave completing a
-    block finishes it): several keys and ragged messages, batches with fewer
-    TREE blocks than workgroups and with several blocks per workgroup, kept
-    and recomputed chains, every FORS shape it is compiled for, with and
-    without dedup and graph capture."""
+    """The fused kernel scheduled per chains chunk (workgroups take one TREE
+    block at a time, its waves take single chunks, a rotating wave finishes
+    each block while the others start the next): several keys and ragged
+    messages, batches with fewer TREE blocks than workgroups and with several
+    blocks per workgroup, kept and recomputed chains, every FORS shape it is
+    compiled for, with and without dedup and graph capture."""
     rng = np.random.default_rng([190, param])
     ks = oracle_keys(param, [workloads.key_seed(param, 40 + i) for i in range(3)])
     big = {1: 300, 2: 160, 3: 100, 7: 160, 9: 60}[param]

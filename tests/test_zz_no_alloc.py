@@ -91,8 +91,8 @@ def test_two_calls_equal_sign_batch(env, mode):
 
 
 def test_chunk_scheduled_fused(env):
-    """The fused kernel scheduled per chains chunk keeps a chunk counter and
-    staging for every TREE block of a chunk of the batch; both fit the array."""
+    """The fused kernel scheduled per chains chunk, in both fused modes, on
+    two calls in a row."""
     slh, ctx, keys, slots = env
     try:
         for p in SETS:
