@@ -438,7 +438,7 @@ def per_set_latency(slh, params, lat, skip):
     return out
 
 
-def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lanes=4):
+def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lanes=4, schedule="items"):
     """Serving workload: n requests, parameter set 50/30/20 % 128f/192f/256f,
     256 device-resident keys (128/77/51), log-normal message lengths (median
     256 B, 32 B - 16 KiB), random bytes.  First all requests at time 0 (the
@@ -461,10 +461,12 @@ def serve_bench(slh, workloads, n, rates, log, mode="fused", cache_layers=0, lan
     for p, cnt in zip((1, 2, 3), keys_per_set):
         sks[p] = [slh.keygen(p, workloads.key_seed(p, 1000 + i))[1] for i in range(cnt)]
         slots[p] = srv.add_keys(p, sks[p])
+        if schedule == "chunks":
+            srv.set_tuning(p, fused_schedule=slh.FUSED_CHUNKS)
     ks = [slots[p] + k for p, k in zip(params, kidx)]
     out = {"requests": n, "mix": "50/30/20 % 128f/192f/256f", "keys": 256,
            "msg_len": "log-normal, median 256 B, clipped to [32, 16384]", "lanes": lanes, "max_batch": 4096,
-           "max_wait_us": 2000, "mode": mode, "cache_layers": cache_layers,
+           "max_wait_us": 2000, "mode": mode, "cache_layers": cache_layers, "fused_schedule": schedule,
            "latency": "arrival to completion, host buffers (PCIe included)",
            "points": []}
     reqs0, blob = slh.trace(params, ks, msgs, [0.0] * n)
@@ -666,6 +668,8 @@ def main():
     ap.add_argument("--serve-cache-layers", type=int, default=0,
                     help="upper hypertree layers cached per key on the server's lanes (dedup modes)")
     ap.add_argument("--serve-lanes", type=int, default=4, help="in-flight batches of the signing server")
+    ap.add_argument("--serve-schedule", default="items", choices=["items", "chunks"],
+                    help="fused kernel schedule of the server's batches (fused_schedule of the SHA2 fast sets)")
     ap.add_argument("--telemetry-s", type=float, default=2.0,
                     help="seconds of further untimed steps (after a 1 s settle) over which amdsmi reads the "
                          "clock, power and energy counter; 0 = none (profiler runs)")
@@ -800,13 +804,13 @@ def main():
         log("bench: serving")
         rates = [float(x) for x in args.serve_rates.split(",")]
         line["serving"] = serve_bench(slh, workloads, args.serve_n, rates, log, args.serve_mode,
-                                      args.serve_cache_layers, args.serve_lanes)
+                                      args.serve_cache_layers, args.serve_lanes, args.serve_schedule)
         if not args.no_serve_dedup:
             # tree sharing across the requests of a key (within-batch dedup and
             # a per-key cache of the top layers): same bytes, less work
             log("bench: serving with dedup and key cache")
             line["serving_dedup_cache"] = serve_bench(slh, workloads, args.serve_n, rates, log, "fused-dedup", 4,
-                                                      args.serve_lanes)
+                                                      args.serve_lanes, args.serve_schedule)
     if not args.no_cpu:
         log("bench: cpu baseline")
         line["cpu_baseline"] = cpu_baseline(args.workload, workloads, args.cpu_seconds)
