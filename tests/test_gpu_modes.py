@@ -54,13 +54,18 @@ def test_modes_single_set(slh, keys, mode, split):
             _check(p, got, oracle_sign_many([(p, sk, m) for m in msgs]), mode)
 
 
-def test_graph_mixed_batch_replays(slh, keys):
+@pytest.mark.parametrize("schedule", ["default", "chunks"])
+def test_graph_mixed_batch_replays(slh, keys, schedule):
     """One captured graph with three parameter-set branches, replayed with new
-    message bytes of the same layout; every replay matches the oracle."""
+    message bytes of the same layout; every replay matches the oracle.
+    `chunks`: each branch runs the chunk-scheduled fused kernel."""
     import torch
     rng = np.random.default_rng([61, 0])
     with slh.Context(0) as ctx:
         slots = {p: ctx.add_keys(p, keys[p][1]) for p in (1, 2, 3)}
+        if schedule == "chunks":
+            for p in (1, 2, 3):
+                ctx.set_tuning(p, split_max_blocks=slh.SPLIT_NEVER, fused_schedule=slh.FUSED_CHUNKS)
         params = [1, 2, 3, 1, 3, 2, 1]
         lens = [32, 200, 5, 64, 1000, 0, 33]
         msgs = [rng.bytes(L) for L in lens]
