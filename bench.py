@@ -698,7 +698,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: signing shards by message with no exchange, "
-              "and this build measures the single-GPU kernel (--gpus 1).", file=sys.stderr)
+              "and the benchmark measures the single-GPU kernel (--gpus 1).", file=sys.stderr)
         sys.exit(2)
     from paper_2512_23969_amd import accounting as acc
     from paper_2512_23969_amd import slh, workloads
