@@ -18,7 +18,9 @@ are timed on the GPU and the fastest is kept.
   kernel (the FORS shape and instruction variant from the FORS kernel's own
   HIP events; TREE block size, layer order, kept or recomputed chains and
   the TREE instruction variant from whole steps; then the per-phase path
-  against the fused persistent kernel; then the verification kernel's
+  against the fused persistent kernel in both of its schedules (fixed chunk
+  shares per work item, or chunks taken one at a time); then the
+  verification kernel's
   variant) and keeps the fastest; results are cached in a JSON file keyed
   by GPU architecture, parameter set and batch size.
 """
