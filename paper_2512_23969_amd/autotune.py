@@ -20,9 +20,8 @@ are timed on the GPU and the fastest is kept.
   the TREE instruction variant from whole steps; then the per-phase path
   against the fused persistent kernel in both of its schedules (fixed chunk
   shares per work item, or chunks taken one at a time); then the
-  verification kernel's
-  variant) and keeps the fastest; results are cached in a JSON file keyed
-  by GPU architecture, parameter set and batch size.
+  verification kernel's variant) and keeps the fastest; results are cached
+  in a JSON file keyed by GPU architecture, parameter set and batch size.
 """
 from __future__ import annotations
 
